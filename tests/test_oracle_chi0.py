@@ -1,0 +1,138 @@
+"""Pins of the oracle's chi0: three independent routes agree, the closed-form
+free-electron (Lindhard-type) response, and the structural properties the
+paper states (symmetry, negative semi-definiteness, charge conservation)."""
+import numpy as np
+import pytest
+
+import oracle.response as resp
+from oracle.groundstate import ground_state
+from oracle.response import (HxcKernel, SumOverStates, apply_dielectric,
+                             chi0_fd, chi0_sternheimer, orbital_row_norm)
+from oracle.system import System
+from workloads import config, random_field
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small_metal", "small_rect", "tiny_k"])
+def test_sos_equals_sternheimer(name, oracle_case):
+    sys, gs = oracle_case(name)
+    dv = random_field(sys.spec, 1)
+    sos = SumOverStates(sys, gs).apply(dv)
+    st = chi0_sternheimer(sys, gs, dv, 1e-12)
+    assert np.linalg.norm(sos - st) < 1e-9 * np.linalg.norm(sos)
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small_metal"])
+def test_sos_equals_finite_difference(name, oracle_case):
+    sys, gs = oracle_case(name)
+    dv = random_field(sys.spec, 1)
+    sos = SumOverStates(sys, gs).apply(dv)
+    fd = chi0_fd(sys, dv, h=1e-4)
+    # central difference error O(h^2)
+    assert np.linalg.norm(sos - fd) < 5e-8 * np.linalg.norm(sos)
+
+
+def test_printed_occupied_weight_fails_for_fractional_occupations(oracle_case, monkeypatch):
+    """Planting the printed weight f_n^2/(f_n^2+f_m^2) breaks chi0 = SOS on a
+    smeared cell, which is what pins the f_n/(f_n^2+f_m^2) reading."""
+    sys, gs = oracle_case("small_metal")
+    dv = random_field(sys.spec, 1)
+    sos = SumOverStates(sys, gs).apply(dv)
+    good = chi0_sternheimer(sys, gs, dv, 1e-12)
+    orig = resp.divided_difference
+
+    def printed(sys_, gs_, ik, n, m):
+        f = gs_.occ[ik]
+        d = orig(sys_, gs_, ik, n, m)
+        # oracle uses alpha = f_n d / (f_n^2 + f_m^2); the printed formula is
+        # alpha = f_n^2 d / (f_n^2 + f_m^2), i.e. an extra factor f_n
+        return d * f[n]
+    monkeypatch.setattr(resp, "divided_difference", printed)
+    bad = chi0_sternheimer(sys, gs, dv, 1e-12)
+    assert np.linalg.norm(good - sos) < 1e-9 * np.linalg.norm(sos)
+    assert np.linalg.norm(bad - sos) > 1e-3 * np.linalg.norm(sos)
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_metal"])
+def test_dense_chi0_symmetric_nsd_charge_conserving(name, oracle_case):
+    sys, gs = oracle_case(name)
+    sos = SumOverStates(sys, gs)
+    chi = sos.dense_matrix()
+    scale = np.max(np.abs(chi))
+    assert np.max(np.abs(chi - chi.T)) < 1e-12 * scale
+    ev = np.linalg.eigvalsh(chi)
+    assert ev.max() < 1e-12 * scale
+    ones = np.ones(sys.ng)
+    assert np.max(np.abs(chi @ ones)) < 1e-12 * scale * sys.ng
+    assert np.max(np.abs(ones @ chi)) < 1e-12 * scale * sys.ng
+    # dense matrix and the apply loop agree
+    dv = random_field(sys.spec, 1)
+    assert np.allclose(chi @ dv.ravel(), sos.apply(dv).ravel(), rtol=0,
+                       atol=1e-12 * np.linalg.norm(chi @ dv.ravel()))
+
+
+def _lindhard(sys, nocc_shell, q_miller):
+    """X(q) = (2/|Omega|) sum_k w_k sum_{G occ} sum_{t=+-1}
+    1[G + t q in sphere minus occ] / (e_G - e_{G+tq}), e_G = |G+k|^2/2
+    (free electrons, closed shells), derived from the sum over states."""
+    X = 0.0
+    for kb in sys.bases:
+        order = np.argsort(kb.kin, kind="stable")
+        occ = {tuple(m) for m in kb.miller[order[:nocc_shell]]}
+        allg = {tuple(m): e for m, e in zip(kb.miller, kb.kin)}
+        for g in occ:
+            eg = allg[g]
+            for t in (1, -1):
+                g2 = tuple(np.array(g) + t * np.array(q_miller))
+                if g2 in allg and g2 not in occ:
+                    X += kb.weight * 1.0 / (eg - allg[g2])
+    return 2.0 * X / sys.volume
+
+
+def test_free_electron_closed_form_response():
+    spec = config("cfg1").with_(amp=np.zeros(2), d_proj=0.0, nocc=7, nextra=2)
+    sys = System(spec)
+    gs = ground_state(sys, dense=True)
+    q = (1, 0, 0)
+    x1 = np.arange(sys.n[0]) / sys.n[0]
+    cosq = np.cos(2 * np.pi * x1)[:, None, None] * np.ones(sys.n)
+    X = _lindhard(sys, 7, q)
+    st = chi0_sternheimer(sys, gs, cosq, 1e-13)
+    assert np.max(np.abs(st - X * cosq)) < 1e-11 * abs(X)
+    # the dielectric adjoint on the same mode: E cos = (1 - X K(q)) cos with
+    # K(q) = 4 pi/|q|^2 + f_x(rho0), rho0 = 2 nocc/|Omega| uniform
+    kern = HxcKernel(sys, gs.rho, xc=1)
+    rho0 = 2 * 7 / sys.volume
+    fx0 = -(1 / 3) * (3 / np.pi) ** (1 / 3) * rho0 ** (-2 / 3)
+    kq = 4 * np.pi / sys.b[0] ** 2 + fx0
+    ev, _ = apply_dielectric(sys, gs, kern, cosq, lambda nu: 1e-13)
+    assert np.max(np.abs(ev - (1 - X * kq) * cosq)) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small_rect"])
+def test_orbital_row_norm_bounds(name, oracle_case):
+    """sqrt(N_occ/|Omega|) <= ||F^-1 Phi||_{2,inf} <= sqrt(N_g/|Omega|)
+    (Proposition FinvPhi_bound)."""
+    sys, gs = oracle_case(name)
+    for ik in range(len(sys.bases)):
+        val = orbital_row_norm(sys, gs, ik, real_part=False)
+        assert np.sqrt(gs.nocc_k[ik] / sys.volume) <= val * (1 + 1e-12)
+        assert val <= np.sqrt(sys.ng / sys.volume) * (1 + 1e-12)
+        assert orbital_row_norm(sys, gs, ik, real_part=True) <= val * (1 + 1e-12)
+
+
+def test_lemma_cgtol_bound_holds(oracle_case):
+    """||(E - E~) v|| <= 2 ||Kv|| ||F^-1 Phi||_{2,inf} sqrt(N_g N_occ)/sqrt|Omega|
+    * max_n f_n tau_n / (e_{N+1} - e_n)   (Lemma cgtol_E, Gamma only)."""
+    sys, gs = oracle_case("cfg1")
+    kern = HxcKernel(sys, gs.rho, xc=1)
+    v = random_field(sys.spec, 2)
+    exact, knorm = apply_dielectric(sys, gs, kern, v, lambda nu: 1e-14)
+    nocc = gs.nocc_k[0]
+    orb = orbital_row_norm(sys, gs, 0, real_part=False)
+    gap = gs.eps[0][nocc] - gs.eps[0][:nocc]
+    for tau in (1e-3, 1e-5, 1e-7):
+        approx, _ = apply_dielectric(sys, gs, kern, v, lambda nu: tau)
+        err = np.linalg.norm(exact - approx)
+        bound = 2 * knorm * orb * np.sqrt(sys.ng * nocc) / np.sqrt(sys.volume) \
+            * np.max(gs.occ[0][:nocc] * tau / gap)
+        assert err <= bound
