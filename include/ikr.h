@@ -1,0 +1,199 @@
+/*
+ * ikr.h -- C ABI of the MI355X (gfx950) inexact-Krylov linear-response library.
+ *
+ * The library solves the discretised Dyson equation  E drho = b  with
+ * E = 1 - chi0 K  (the dielectric adjoint; paper Sec. 2.2, eq. dyson_discretised)
+ * by inexact GMRES(m) (paper Alg. 1) whose operator applications solve the
+ * Sternheimer equations of every occupied band and k-point by preconditioned
+ * CG under the adaptive per-band tolerances of paper Table 1 / Table
+ * strategies_k, then accumulate the density response (eq. kchi0).
+ *
+ * Conventions shared by every entry point
+ *   - Grid vectors (potentials, densities, b, drho) are real FP64 arrays of
+ *     length N_g = fft[0]*fft[1]*fft[2] in C order [N0][N1][N2] (index 2
+ *     fastest), values on the real-space grid of paper Sec. 2.3.1.  Norms of
+ *     grid vectors are plain Euclidean norms of these values.
+ *   - Orbital-coefficient vectors are complex128 (interleaved re, im) with a
+ *     row stride of nb_max complex numbers, in the basis order returned by
+ *     ikr_get_basis (per k-point).
+ *   - Pointers named *_dev are device pointers (hipMalloc'd memory of the
+ *     device that was current at setup); *_host are host pointers.  The
+ *     caller owns every buffer it passes; the library never frees them.
+ *   - Every call enqueues its work on the HIP stream given at setup and
+ *     returns after that work has completed (host-side scalars are needed
+ *     by the GMRES loop).  A handle is not thread-safe; separate handles are
+ *     independent.
+ *   - Errors are returned as ikr_status codes; no C++ exception crosses the
+ *     ABI.  ikr_last_error() returns a message for the last failing call on
+ *     the calling thread.
+ */
+#ifndef IKR_H
+#define IKR_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ikr_system* ikr_handle;
+
+typedef enum {
+  IKR_OK = 0,
+  IKR_E_ARG = 1,       /* invalid argument (null pointer, size, unsupported grid) */
+  IKR_E_STATE = 2,     /* handle not ready for this call */
+  IKR_E_NOGAP = 3,     /* no gap above the occupied bands of some k-point */
+  IKR_E_NOCONV = 4,    /* a CG or GMRES iteration cap was hit (best result written) */
+  IKR_E_NAN = 5,       /* non-finite input or intermediate */
+  IKR_E_OOM = 6,       /* device allocation failed */
+  IKR_E_HIP = 7,       /* HIP runtime error */
+  IKR_E_INTERNAL = 8
+} ikr_status;
+
+/* CG-tolerance strategies: paper Table 1 (agr, bal, grt and the baselines
+ * D10, D100, D10n) in the k-point form of Table strategies_k.  IKR_FIXED
+ * applies the common factor unchanged to every band. */
+typedef enum {
+  IKR_AGR = 0, IKR_BAL = 1, IKR_GRT = 2, IKR_D10 = 3, IKR_D100 = 4,
+  IKR_D10N = 5, IKR_FIXED = 6
+} ikr_strategy;
+
+/* Model system (host memory, read during ikr_setup_system only).
+ * Orthorhombic cell; per atom a Gaussian local potential with Fourier
+ * coefficients -amp * exp(-sigma_loc^2 |G|^2 / 2) e^{-iG.R} / |Omega| and an
+ * L2-normalised Gaussian separable projector of width sigma_proj and
+ * strength d_proj (Ha).  Gamma-centred k-grid kgrid (no symmetry reduction).
+ * temperature = 0: nocc doubly occupied bands per k; > 0: Fermi-Dirac
+ * smearing of 2*nocc electrons over nocc + nextra bands. */
+typedef struct {
+  double lattice[3];        /* cell lengths a_i (bohr) */
+  int natoms;
+  const double* frac_pos;   /* [natoms][3] fractional positions */
+  const double* amp;        /* [natoms] local-potential amplitudes */
+  double sigma_loc;         /* bohr */
+  double sigma_proj;        /* bohr */
+  double d_proj;            /* Ha */
+  double ecut;              /* Ha; sphere |G + k|^2 <= 2 ecut (eq. fourier_bases) */
+  int fft[3];               /* real-space grid; each a product of 2, 3, 5 in the
+                               supported set (see ikr_supported_fft_size) */
+  int kgrid[3];
+  int nocc;
+  int nextra;
+  double temperature;       /* Ha */
+  int xc;                   /* 0: Hartree kernel only, 1: + Slater exchange */
+} ikr_system_desc;
+
+/* Optional imported ground state (host memory).  eps [nk][nbands] ascending
+ * per k; coeffs complex128 [nk][nbands][nb_max] orthonormal per k, in the
+ * ikr_get_basis order of each k (entries beyond nb_k ignored).  The basis
+ * order is known only after setup, so an import is made by
+ * ikr_import_ground_state on a handle set up with compute_ground_state = 0. */
+typedef struct {
+  const double* eps;
+  const double* coeffs;
+} ikr_ground_state;
+
+typedef struct {
+  int strategy;             /* ikr_strategy */
+  double tol;               /* GMRES tolerance tau */
+  int tol_is_relative;      /* 1: tau = tol * ||b|| */
+  int restart_m;            /* GMRES restart size m (default 20) */
+  double s0;                /* initial estimate s of sigma_m(H_m) (default 1) */
+  int max_restarts;         /* default 50 */
+  int precision;            /* 0: FP64 Sternheimer CG, 1: FP32 CG where loose */
+  int cg_min_iter;          /* default 1 (paper Sec. 4.1.2) */
+  int cg_max_iter;          /* default 1000 */
+  double fp32_theta;        /* FP32 used when tau_nk >= theta * ||b_nk|| */
+  double b_norm;            /* ||b|| for D10n inside ikr_apply_dielectric */
+  int want_true_residual;   /* 1: report ||b - E x|| with tight CG at exit */
+  double true_res_cg_tol;   /* CG tolerance of the true-residual apply (1e-14) */
+} ikr_solver_opts;
+
+typedef struct {
+  long long n_ham;          /* Hamiltonian band-applications (one per CG iter) */
+  long long n_ham_fp32;
+  long long n_ham_fp64;
+  int gmres_iters;
+  int restarts;
+  int cg_unconverged;       /* Sternheimer solves that hit the iteration cap */
+  double est_res;           /* final estimated GMRES residual */
+  double true_res;          /* ||b - E x|| if requested, else -1 */
+  double s_final;
+  double sigma_min;
+  double knorm_last;        /* ||K v|| of the last dielectric application */
+  double seconds;
+} ikr_stats;
+
+/* Fill opts with the defaults above (strategy bal, tol 1e-8 relative). */
+void ikr_default_opts(ikr_solver_opts* opts);
+
+/* 1 if n is a supported FFT length (products of 2, 3, 5 in the library's
+ * compiled set), else 0. */
+int ikr_supported_fft_size(int n);
+
+/* Build the discretisation (paper Sec. 2.3.1), the local potential on the
+ * grid, the projectors, and -- if gs is NULL -- the ground state by the
+ * library's own block eigensolver on the GPU; occupations, Fermi level,
+ * density, per-k gaps.  stream: hipStream_t (may be NULL for the default
+ * stream).  Returns IKR_E_NOGAP if some k has e_{Nocc+1} - e_{Nocc} < 1e-6 Ha
+ * (Lemma cgtol_E needs a gap); the handle is still created in that case. */
+ikr_status ikr_setup_system(const ikr_system_desc* desc, void* stream,
+                            int compute_ground_state, ikr_handle* out);
+
+/* Import eigenpairs (host) for a handle created with compute_ground_state=0;
+ * completes setup (occupations, density, caches). */
+ikr_status ikr_import_ground_state(ikr_handle h, const ikr_ground_state* gs);
+
+/* Sizes: nk, nbands, nb_max, N_g, and per-k occupied counts (host [nk]). */
+ikr_status ikr_get_info(ikr_handle h, int* nk, int* nbands, int* nb_max,
+                        int* ng, int* nocc_k_host);
+
+/* Basis of k-point k: nb_k and the Miller indices [nb_k][3] in the order the
+ * library uses (G = sum_i m_i b_i, |G + k|^2 <= 2 ecut).  miller_host may be
+ * NULL to query nb_k only. */
+ikr_status ikr_get_basis(ikr_handle h, int k, int* nb_k, int* miller_host);
+
+/* Ground state (host): eps [nk][nbands], occupations [nk][nbands],
+ * coefficients complex128 [nk][nbands][nb_max] (may be NULL), Fermi level. */
+ikr_status ikr_get_ground_state(ikr_handle h, double* eps_host,
+                                double* occ_host, double* coeffs_host,
+                                double* fermi_host);
+
+/* Ground-state density on the grid (device, C order). */
+ikr_status ikr_get_density(ikr_handle h, double* rho_dev);
+
+/* y = H_k x for nvec vectors (device, complex128 [nvec][nb_max]); the
+ * kinetic, local (FFT) and nonlocal terms of eq. Hamiltonian, Bloch form. */
+ikr_status ikr_apply_hamiltonian(ikr_handle h, int k, int nvec,
+                                 const double* x_dev, double* y_dev);
+
+/* kv = K v, K = K_H + K_xc at the ground-state density (device grid
+ * vectors).  Hartree 4 pi/|G|^2 with G = 0 -> 0 (paper Sec. 3.4.3). */
+ikr_status ikr_apply_hxc_kernel(ikr_handle h, const double* v_dev,
+                                double* kv_dev);
+
+/* drho = chi0 dv through the Sternheimer route (eq. kchi0, eq.
+ * delta_phi_P, eq. sternheimer_equation, eq. delta_f).  CG tolerances are
+ * absolute on the Sternheimer right-hand sides of dv: cg_tol for every band,
+ * or per band from cg_tol_host [nk][nbands] (entries of unoccupied bands
+ * ignored) when non-NULL. */
+ikr_status ikr_apply_chi0(ikr_handle h, const double* dv_dev, double* drho_dev,
+                          double cg_tol, const double* cg_tol_host,
+                          ikr_stats* stats);
+
+/* ev = E~ v = v - ||K v|| chi0~(K v / ||K v||)  (eq. op_discretised), the
+ * per-band CG tolerances being prefactor(strategy) * common  (Table 1). */
+ikr_status ikr_apply_dielectric(ikr_handle h, const double* v_dev,
+                                double* ev_dev, double common,
+                                const ikr_solver_opts* opts, ikr_stats* stats);
+
+/* drho solving E drho = b by inexact GMRES(m), Alg. 1. */
+ikr_status ikr_solve_response(ikr_handle h, const double* b_dev,
+                              double* drho_dev, const ikr_solver_opts* opts,
+                              ikr_stats* stats);
+
+const char* ikr_last_error(void);
+void ikr_destroy(ikr_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IKR_H */

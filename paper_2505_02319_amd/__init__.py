@@ -1,0 +1,12 @@
+"""MI355X-native inexact-Krylov linear-response solver (HIP, gfx950).
+
+The compute path lives in ``libikr.so`` (C ABI in ``include/ikr.h``); this
+package holds the build script and a thin ctypes binding.
+"""
+from .binding import (IKR_AGR, IKR_BAL, IKR_D10, IKR_D10N, IKR_D100, IKR_FIXED,
+                      IKR_GRT, STRATEGY, IkrError, ResponseSystem, SIGNATURES,
+                      default_opts, lib, LIB_PATH)
+
+__all__ = ["ResponseSystem", "IkrError", "default_opts", "lib", "LIB_PATH", "STRATEGY",
+           "SIGNATURES", "IKR_AGR", "IKR_BAL", "IKR_GRT", "IKR_D10", "IKR_D100",
+           "IKR_D10N", "IKR_FIXED"]

@@ -1,0 +1,295 @@
+"""ctypes binding of libikr.so (the C ABI of include/ikr.h).
+
+Argument marshalling only: every step of the response path runs in the HIP
+library.  PyTorch provides device memory (tensors passed by data_ptr) and
+the HIP stream.  There is no fallback: if the library is missing or fails
+to load, import raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libikr.so")
+
+IKR_AGR, IKR_BAL, IKR_GRT, IKR_D10, IKR_D100, IKR_D10N, IKR_FIXED = range(7)
+STRATEGY = {"agr": IKR_AGR, "bal": IKR_BAL, "grt": IKR_GRT, "D10": IKR_D10,
+            "D100": IKR_D100, "D10n": IKR_D10N, "fixed": IKR_FIXED}
+STATUS = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NOGAP", 4: "E_NOCONV",
+          5: "E_NAN", 6: "E_OOM", 7: "E_HIP", 8: "E_INTERNAL"}
+
+
+class IkrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ikr {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class SystemDesc(C.Structure):
+    _fields_ = [("lattice", C.c_double * 3), ("natoms", C.c_int),
+                ("frac_pos", C.POINTER(C.c_double)), ("amp", C.POINTER(C.c_double)),
+                ("sigma_loc", C.c_double), ("sigma_proj", C.c_double),
+                ("d_proj", C.c_double), ("ecut", C.c_double), ("fft", C.c_int * 3),
+                ("kgrid", C.c_int * 3), ("nocc", C.c_int), ("nextra", C.c_int),
+                ("temperature", C.c_double), ("xc", C.c_int)]
+
+
+class GroundStateC(C.Structure):
+    _fields_ = [("eps", C.POINTER(C.c_double)), ("coeffs", C.POINTER(C.c_double))]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("strategy", C.c_int), ("tol", C.c_double), ("tol_is_relative", C.c_int),
+                ("restart_m", C.c_int), ("s0", C.c_double), ("max_restarts", C.c_int),
+                ("precision", C.c_int), ("cg_min_iter", C.c_int), ("cg_max_iter", C.c_int),
+                ("fp32_theta", C.c_double), ("b_norm", C.c_double),
+                ("want_true_residual", C.c_int), ("true_res_cg_tol", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_ham", C.c_longlong), ("n_ham_fp32", C.c_longlong),
+                ("n_ham_fp64", C.c_longlong), ("gmres_iters", C.c_int),
+                ("restarts", C.c_int), ("cg_unconverged", C.c_int),
+                ("est_res", C.c_double), ("true_res", C.c_double),
+                ("s_final", C.c_double), ("sigma_min", C.c_double),
+                ("knorm_last", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+# Exported symbols and their signatures (must match include/ikr.h).
+_VP = C.c_void_p
+SIGNATURES = {
+    "ikr_default_opts": (None, [C.POINTER(SolverOpts)]),
+    "ikr_supported_fft_size": (C.c_int, [C.c_int]),
+    "ikr_setup_system": (C.c_int, [C.POINTER(SystemDesc), _VP, C.c_int, C.POINTER(_VP)]),
+    "ikr_import_ground_state": (C.c_int, [_VP, C.POINTER(GroundStateC)]),
+    "ikr_get_info": (C.c_int, [_VP, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                               C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "ikr_get_basis": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "ikr_get_ground_state": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "ikr_get_density": (C.c_int, [_VP, _VP]),
+    "ikr_apply_hamiltonian": (C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP]),
+    "ikr_apply_hxc_kernel": (C.c_int, [_VP, _VP, _VP]),
+    "ikr_apply_chi0": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(C.c_double),
+                                 C.POINTER(Stats)]),
+    "ikr_apply_dielectric": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(SolverOpts),
+                                       C.POINTER(Stats)]),
+    "ikr_solve_response": (C.c_int, [_VP, _VP, _VP, C.POINTER(SolverOpts), C.POINTER(Stats)]),
+    "ikr_last_error": (C.c_char_p, []),
+    "ikr_destroy": (None, [_VP]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libikr.so (raises if it is missing: there is no other path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built; run paper_2505_02319_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != 0:
+        raise IkrError(code, lib().ikr_last_error().decode())
+
+
+def default_opts(**kw) -> SolverOpts:
+    o = SolverOpts()
+    lib().ikr_default_opts(C.byref(o))
+    for key, val in kw.items():
+        if key == "strategy" and isinstance(val, str):
+            val = STRATEGY[val]
+        setattr(o, key, val)
+    return o
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Info:
+    nk: int
+    nbands: int
+    nb_max: int
+    ng: int
+
+
+class ResponseSystem:
+    """One response system (opaque handle) on the current CUDA/HIP device.
+
+    ``spec`` is any object with the fields of ikr_system_desc (lattice,
+    frac_pos, amp, sigma_loc, sigma_proj, d_proj, ecut, fft, kgrid, nocc,
+    nextra, temperature, xc).  ``ground_state``: "compute" (library's own
+    GPU eigensolver) or a pair (eps [nk][nbands], coeffs [nk][nbands][nb_max]
+    complex) in the library's basis order, or None to import later.
+    """
+
+    def __init__(self, spec, ground_state="compute", stream=None):
+        import torch
+        self._torch = torch
+        L = lib()
+        self.spec = spec
+        self.fft = tuple(int(x) for x in spec.fft)
+        pos = np.ascontiguousarray(np.asarray(spec.frac_pos, float).reshape(-1))
+        amp = np.ascontiguousarray(np.asarray(spec.amp, float).reshape(-1))
+        self._keep = (pos, amp)
+        d = SystemDesc()
+        d.lattice[:] = [float(x) for x in spec.lattice]
+        d.natoms = len(amp)
+        d.frac_pos = _dptr(pos)
+        d.amp = _dptr(amp)
+        d.sigma_loc, d.sigma_proj, d.d_proj = spec.sigma_loc, spec.sigma_proj, spec.d_proj
+        d.ecut = spec.ecut
+        d.fft[:] = list(self.fft)
+        d.kgrid[:] = [int(x) for x in spec.kgrid]
+        d.nocc, d.nextra = int(spec.nocc), int(spec.nextra)
+        d.temperature = float(spec.temperature)
+        d.xc = int(spec.xc)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = C.c_void_p()
+        compute = 1 if isinstance(ground_state, str) and ground_state == "compute" else 0
+        code = L.ikr_setup_system(C.byref(d), C.c_void_p(stream), compute, C.byref(h))
+        self.h = h
+        if code not in (0,):
+            if h.value is None:
+                _check(code)
+            self.setup_status = code
+        else:
+            self.setup_status = 0
+        if not compute and ground_state is not None:
+            self.import_ground_state(*ground_state)
+
+    # ------------------------------------------------------------ queries
+    def info(self) -> Info:
+        nk, nb, nbm, ng = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        _check(lib().ikr_get_info(self.h, C.byref(nk), C.byref(nb), C.byref(nbm),
+                                  C.byref(ng), None))
+        return Info(nk.value, nb.value, nbm.value, ng.value)
+
+    def nocc_k(self):
+        inf = self.info()
+        out = (C.c_int * inf.nk)()
+        _check(lib().ikr_get_info(self.h, None, None, None, None, out))
+        return list(out)
+
+    def basis(self, k: int) -> np.ndarray:
+        nb = C.c_int()
+        _check(lib().ikr_get_basis(self.h, k, C.byref(nb), None))
+        m = np.zeros((nb.value, 3), np.int32)
+        _check(lib().ikr_get_basis(self.h, k, C.byref(nb),
+                                   m.ctypes.data_as(C.POINTER(C.c_int))))
+        return m
+
+    def import_ground_state(self, eps, coeffs):
+        inf = self.info()
+        eps = np.ascontiguousarray(np.asarray(eps, float).reshape(inf.nk, inf.nbands))
+        cf = np.ascontiguousarray(np.asarray(coeffs, np.complex128).reshape(
+            inf.nk, inf.nbands, inf.nb_max))
+        g = GroundStateC(_dptr(eps), cf.ctypes.data_as(C.POINTER(C.c_double)))
+        code = lib().ikr_import_ground_state(self.h, C.byref(g))
+        self.setup_status = code
+        if code not in (0, 3):
+            _check(code)
+
+    def ground_state(self):
+        inf = self.info()
+        eps = np.zeros((inf.nk, inf.nbands))
+        occ = np.zeros((inf.nk, inf.nbands))
+        cf = np.zeros((inf.nk, inf.nbands, inf.nb_max), np.complex128)
+        fermi = C.c_double()
+        _check(lib().ikr_get_ground_state(self.h, _dptr(eps), _dptr(occ),
+                                          cf.ctypes.data_as(C.POINTER(C.c_double)),
+                                          C.byref(fermi)))
+        return eps, occ, cf, fermi.value
+
+    # ------------------------------------------------------------ operators
+    def _grid(self, t):
+        torch = self._torch
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+        assert t.numel() == int(np.prod(self.fft))
+        return t
+
+    def density(self):
+        torch = self._torch
+        out = torch.empty(self.fft, dtype=torch.float64, device="cuda")
+        _check(lib().ikr_get_density(self.h, _ptr(out)))
+        return out
+
+    def apply_hamiltonian(self, k: int, x):
+        torch = self._torch
+        inf = self.info()
+        assert x.dtype == torch.complex128 and x.is_cuda and x.is_contiguous()
+        assert x.shape[-1] == inf.nb_max
+        y = torch.empty_like(x)
+        _check(lib().ikr_apply_hamiltonian(self.h, k, x.shape[0], _ptr(x), _ptr(y)))
+        return y
+
+    def apply_kernel(self, v):
+        out = self._torch.empty_like(self._grid(v))
+        _check(lib().ikr_apply_hxc_kernel(self.h, _ptr(v), _ptr(out)))
+        return out
+
+    def apply_chi0(self, dv, cg_tol: float = 1e-10, cg_tol_per_band=None):
+        out = self._torch.empty_like(self._grid(dv))
+        st = Stats()
+        per = None
+        if cg_tol_per_band is not None:
+            arr = np.ascontiguousarray(np.asarray(cg_tol_per_band, float))
+            per = _dptr(arr)
+        _check(lib().ikr_apply_chi0(self.h, _ptr(dv), _ptr(out), float(cg_tol), per,
+                                    C.byref(st)))
+        return out, st.as_dict()
+
+    def apply_dielectric(self, v, common: float, opts: Optional[SolverOpts] = None):
+        out = self._torch.empty_like(self._grid(v))
+        st = Stats()
+        o = opts or default_opts()
+        _check(lib().ikr_apply_dielectric(self.h, _ptr(v), _ptr(out), float(common),
+                                          C.byref(o), C.byref(st)))
+        return out, st.as_dict()
+
+    def solve(self, b, opts: Optional[SolverOpts] = None):
+        out = self._torch.empty_like(self._grid(b))
+        st = Stats()
+        o = opts or default_opts()
+        code = lib().ikr_solve_response(self.h, _ptr(b), _ptr(out), C.byref(o), C.byref(st))
+        if code != 0:
+            err = IkrError(code, lib().ikr_last_error().decode())
+            err.stats = st.as_dict()
+            raise err
+        return out, st.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().ikr_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

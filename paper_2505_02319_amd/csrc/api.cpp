@@ -1,0 +1,248 @@
+// extern "C" boundary of the library (declared in include/ikr.h).  Every
+// entry point validates its arguments, converts C++ exceptions to status
+// codes and records a thread-local message for ikr_last_error().
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "system.h"
+
+using ikr::Error;
+using ikr::System;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F> ikr_status guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return IKR_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return (ikr_status)e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return IKR_E_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return IKR_E_INTERNAL;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return IKR_E_INTERNAL;
+  }
+}
+
+System* sys_of(ikr_handle h) {
+  IKR_CHECK(h, IKR_E_ARG, "null handle");
+  return reinterpret_cast<System*>(h);
+}
+
+void check_opts(const ikr_solver_opts* o) {
+  IKR_CHECK(o, IKR_E_ARG, "null solver options");
+  IKR_CHECK(o->strategy >= IKR_AGR && o->strategy <= IKR_FIXED, IKR_E_ARG, "bad strategy");
+  IKR_CHECK(o->tol > 0 && std::isfinite(o->tol), IKR_E_ARG, "tolerance must be positive");
+  IKR_CHECK(o->restart_m >= 1 && o->restart_m <= 60, IKR_E_ARG, "restart size must be in [1, 60]");
+  IKR_CHECK(o->cg_min_iter >= 0 && o->cg_max_iter >= 1, IKR_E_ARG, "bad CG iteration limits");
+  IKR_CHECK(o->s0 > 0, IKR_E_ARG, "s0 must be positive");
+  IKR_CHECK(o->precision == 0 || o->precision == 1, IKR_E_ARG, "precision must be 0 or 1");
+}
+
+}  // namespace
+
+extern "C" {
+
+void ikr_default_opts(ikr_solver_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->strategy = IKR_BAL;
+  o->tol = 1e-8;
+  o->tol_is_relative = 1;
+  o->restart_m = 20;
+  o->s0 = 1.0;
+  o->max_restarts = 50;
+  o->precision = 0;
+  o->cg_min_iter = 1;
+  o->cg_max_iter = 1000;
+  o->fp32_theta = 1e-5;
+  o->b_norm = 1.0;
+  o->want_true_residual = 0;
+  o->true_res_cg_tol = 1e-14;
+}
+
+int ikr_supported_fft_size(int n) { return ikr::fft_length_supported(n) ? 1 : 0; }
+
+ikr_status ikr_setup_system(const ikr_system_desc* desc, void* stream,
+                            int compute_ground_state, ikr_handle* out) {
+  return guarded([&] {
+    IKR_CHECK(out, IKR_E_ARG, "null output handle");
+    *out = nullptr;
+    System* s = ikr::create_system(desc, reinterpret_cast<hipStream_t>(stream));
+    try {
+      if (compute_ground_state) ikr::compute_ground_state(*s);
+    } catch (...) {
+      delete s;
+      throw;
+    }
+    *out = reinterpret_cast<ikr_handle>(s);
+    if (s->have_gs)
+      for (double g : s->gap_k)
+        IKR_CHECK(!(g < 1e-6), IKR_E_NOGAP, "gap above the occupied bands below 1e-6 Ha");
+  });
+}
+
+ikr_status ikr_import_ground_state(ikr_handle h, const ikr_ground_state* gs) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(gs, IKR_E_ARG, "null ground state");
+    ikr::import_ground_state(*s, gs->eps, gs->coeffs);
+    for (double g : s->gap_k)
+      IKR_CHECK(!(g < 1e-6), IKR_E_NOGAP, "gap above the occupied bands below 1e-6 Ha");
+  });
+}
+
+ikr_status ikr_get_info(ikr_handle h, int* nk, int* nbands, int* nb_max, int* ng,
+                        int* nocc_k_host) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    if (nk) *nk = s->nk;
+    if (nbands) *nbands = s->nbands;
+    if (nb_max) *nb_max = s->nb_max;
+    if (ng) *ng = s->ng;
+    if (nocc_k_host) {
+      IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+      for (int k = 0; k < s->nk; ++k) nocc_k_host[k] = s->nocc_k[k];
+    }
+  });
+}
+
+ikr_status ikr_get_basis(ikr_handle h, int k, int* nb_k, int* miller_host) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(k >= 0 && k < s->nk, IKR_E_ARG, "k-point index out of range");
+    if (nb_k) *nb_k = s->kp[k].nb;
+    if (miller_host)
+      std::memcpy(miller_host, s->kp[k].miller.data(), s->kp[k].miller.size() * sizeof(int));
+  });
+}
+
+ikr_status ikr_get_ground_state(ikr_handle h, double* eps_host, double* occ_host,
+                                double* coeffs_host, double* fermi_host) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    if (eps_host) std::memcpy(eps_host, s->eps.data(), s->eps.size() * sizeof(double));
+    if (occ_host) std::memcpy(occ_host, s->occ.data(), s->occ.size() * sizeof(double));
+    if (fermi_host) *fermi_host = s->fermi;
+    if (coeffs_host) {
+      IKR_HIP(hipMemcpyAsync(coeffs_host, s->d_phi.get(),
+                             (size_t)s->nk * s->nbands * s->nb_max * sizeof(double2),
+                             hipMemcpyDeviceToHost, s->stream));
+      IKR_HIP(hipStreamSynchronize(s->stream));
+    }
+  });
+}
+
+ikr_status ikr_get_density(ikr_handle h, double* rho_dev) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(rho_dev, IKR_E_ARG, "null output");
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    ikr::to_external(s->L, s->d_rho.get(), rho_dev, 1.0, nullptr, 0.0, s->stream);
+    IKR_HIP(hipStreamSynchronize(s->stream));
+  });
+}
+
+ikr_status ikr_apply_hamiltonian(ikr_handle h, int k, int nvec, const double* x_dev,
+                                 double* y_dev) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(k >= 0 && k < s->nk, IKR_E_ARG, "k-point index out of range");
+    IKR_CHECK(nvec >= 1 && nvec <= 4096, IKR_E_ARG, "nvec out of range");
+    IKR_CHECK(x_dev && y_dev && x_dev != y_dev, IKR_E_ARG, "bad vector pointers");
+    ikr::apply_hamiltonian(*s, k, nvec, reinterpret_cast<const double2*>(x_dev),
+                           reinterpret_cast<double2*>(y_dev));
+  });
+}
+
+ikr_status ikr_apply_hxc_kernel(ikr_handle h, const double* v_dev, double* kv_dev) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(v_dev && kv_dev, IKR_E_ARG, "null vector");
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    ikr::to_internal(s->L, v_dev, s->d_tmpg.get(), s->stream);
+    ikr::apply_kernel(*s, s->d_tmpg.get(), s->d_u.get());
+    ikr::to_external(s->L, s->d_u.get(), kv_dev, 1.0, nullptr, 0.0, s->stream);
+    IKR_HIP(hipStreamSynchronize(s->stream));
+  });
+}
+
+ikr_status ikr_apply_chi0(ikr_handle h, const double* dv_dev, double* drho_dev, double cg_tol,
+                          const double* cg_tol_host, ikr_stats* stats) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(dv_dev && drho_dev, IKR_E_ARG, "null vector");
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    IKR_CHECK(cg_tol_host || cg_tol > 0, IKR_E_ARG, "CG tolerance must be positive");
+    std::vector<double> tol(s->J, cg_tol);
+    if (cg_tol_host)
+      for (int j = 0; j < s->J; ++j)
+        tol[j] = cg_tol_host[(size_t)s->slot_k[j] * s->nbands + s->slot_n[j]];
+    ikr::to_internal(s->L, dv_dev, s->d_tmpg.get(), s->stream);
+    ikr::Chi0Result r = ikr::apply_chi0_internal(*s, s->d_tmpg.get(), s->d_drho.get(), tol, 1, 1000);
+    ikr::to_external(s->L, s->d_drho.get(), drho_dev, 1.0, nullptr, 0.0, s->stream);
+    IKR_HIP(hipStreamSynchronize(s->stream));
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->n_ham = r.n_ham;
+      stats->n_ham_fp64 = r.n_ham64;
+      stats->n_ham_fp32 = r.n_ham32;
+      stats->cg_unconverged = r.noconv;
+      stats->true_res = -1;
+    }
+    IKR_CHECK(r.noconv == 0, IKR_E_NOCONV, "a Sternheimer CG hit the iteration cap");
+  });
+}
+
+ikr_status ikr_apply_dielectric(ikr_handle h, const double* v_dev, double* ev_dev,
+                                double common, const ikr_solver_opts* opts, ikr_stats* stats) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    check_opts(opts);
+    IKR_CHECK(v_dev && ev_dev && v_dev != ev_dev, IKR_E_ARG, "bad vector pointers");
+    IKR_CHECK(common > 0, IKR_E_ARG, "common tolerance factor must be positive");
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    ikr_stats local{};
+    ikr::apply_dielectric_ext(*s, v_dev, ev_dev, common, *opts, opts->b_norm, &local);
+    local.true_res = -1;
+    if (stats) *stats = local;
+  });
+}
+
+ikr_status ikr_solve_response(ikr_handle h, const double* b_dev, double* drho_dev,
+                              const ikr_solver_opts* opts, ikr_stats* stats) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    check_opts(opts);
+    IKR_CHECK(b_dev && drho_dev && b_dev != drho_dev, IKR_E_ARG, "bad vector pointers");
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    ikr_stats local{};
+    local.true_res = -1;
+    try {
+      ikr::solve_response(*s, b_dev, drho_dev, *opts, &local);
+    } catch (...) {
+      if (stats) *stats = local;
+      throw;
+    }
+    if (stats) *stats = local;
+  });
+}
+
+const char* ikr_last_error(void) { return g_last_error.c_str(); }
+
+void ikr_destroy(ikr_handle h) {
+  if (h) delete reinterpret_cast<System*>(h);
+}
+
+}  // extern "C"

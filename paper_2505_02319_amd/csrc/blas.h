@@ -1,0 +1,89 @@
+// Declarations of the batched vector kernels (blas.hip).
+#pragma once
+
+#include "common.h"
+
+namespace ikr {
+
+constexpr int BT = 16;     // slots per tile (bands of one k-point)
+constexpr int MAXM = 96;   // max projector rows in one update pass
+
+// Tiles of consecutive slots sharing a k-point.
+struct Tiles {
+  int n;
+  const int* k;
+  const int* slot0;
+  const int* nb;           // slots in the tile (<= BT)
+};
+
+// One term  alpha * sum_m W[k][m][g] * C[slot][m]  of an update.
+template <typename R> struct UpdTerm {
+  const cplx<R>* W = nullptr;
+  size_t wk = 0;           // k stride of W (elements)
+  int ws = 0;              // row stride of W
+  const int* Mk = nullptr; // rows per k
+  const cplx<R>* C = nullptr;
+  int cs = 0;              // slot stride of C
+  R alpha = 0;
+};
+
+template <typename R> struct CgScalars {
+  R* rz;
+  R* alpha;
+  R* beta;
+  R* rnorm2;
+  const double* tol2;      // squared absolute tolerance per slot
+  int* iters;
+  int* nactive;            // device counter of still-active slots
+  int* noconv;             // device counter of slots that hit the cap
+  int min_iter, max_iter;
+};
+
+// Internal <-> external grid layout.
+struct Layout {
+  int C, P, Q;
+  int st_c, st_p, st_q;    // external strides of the internal axes
+};
+
+size_t gram_part_elems(int ntiles, int nb_max, int Mmax);
+int update_nblocks(int nb_max);
+int vec_nblocks(int nb_max);
+int multidot_nblocks(int n);
+
+template <typename R>
+void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
+          const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
+          int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st);
+
+template <typename R>
+void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
+            cplx<R>* Y, int y_stride, R a, const UpdTerm<R>& t1,
+            const UpdTerm<R>& t2, const cplx<R>* D, R* dpart, hipStream_t st);
+
+template <typename R>
+void cg_step(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
+             const int* active, const R* alpha, const R* pshift, cplx<R>* x, cplx<R>* r,
+             const cplx<R>* p, cplx<R>* w, R* rpart, hipStream_t st);
+
+template <typename R>
+void precond(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
+             const R* pshift, const cplx<R>* r, cplx<R>* z, hipStream_t st);
+
+template <typename R>
+void cg_scalars(int nslots, int nparts, const R* part, int op, int* active,
+                const CgScalars<R>& cs, int start, hipStream_t st);
+
+void sum_groups(int n, int ngroups, const double* part, double scale, double* out,
+                hipStream_t st);
+void to_internal(const Layout& L, const double* ext, double* in, hipStream_t st);
+void to_external(const Layout& L, const double* in, double* ext, double a,
+                 const double* base, double bscale, hipStream_t st);
+void multidot(int n, int nv, const double* V, size_t vstride, const double* w,
+              double* partial, hipStream_t st);
+void multiaxpy(int n, int nv, const double* V, size_t vstride, const double* c, double a,
+               double* y, hipStream_t st);
+void scale_copy(size_t n, const double* x, double a, double* y, hipStream_t st);
+template <typename R>
+void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st);
+
+}  // namespace ikr

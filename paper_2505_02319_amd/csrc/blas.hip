@@ -1,0 +1,466 @@
+// Batched vector kernels for the Sternheimer CG and the response assembly.
+//
+// Bands are grouped in tiles of up to BT slots sharing one k-point, so that
+// a projection against the occupied orbitals Phi_k (paper: P = Phi Phi^H,
+// Q = I - P) or the nonlocal projectors reads each column of Phi_k / P_k
+// once per tile rather than once per band: the projections are the tall
+// skinny products W^H X (gram) and X + W C (update).  Every reduction is
+// two-stage (per-block partials, then a fixed-order sum), so results are
+// bitwise reproducible run to run.
+#include "blas.h"
+
+namespace ikr {
+namespace {
+
+constexpr int NT = 256;
+constexpr int CH = 64;        // elements per inner chunk of the gram kernel
+constexpr int MT = 16;        // projector rows per gram pass
+
+// part[((t * nsc + sc) * Mmax + m) * BT + b] = sum_{g in super-chunk}
+//                                 conj(W[k][m][g]) X[slot0 + b][g]
+template <typename R>
+__global__ __launch_bounds__(NT) void gram_kernel(
+    Tiles tl, const int* __restrict__ nb, const int* __restrict__ Mk, int Mmax,
+    const cplx<R>* __restrict__ W, size_t wk_stride, int w_stride,
+    const cplx<R>* __restrict__ X, int x_stride, int nsc, int sc_len,
+    cplx<R>* __restrict__ part) {
+  __shared__ cplx<R> Xs[BT][CH + 1];
+  __shared__ cplx<R> Ws[MT][CH + 1];
+  const int t = blockIdx.y, sc = blockIdx.x, tid = threadIdx.x;
+  const int k = tl.k[t], s0 = tl.slot0[t], nbt = tl.nb[t];
+  const int M = Mk[k], n = nb[k];
+  const int i_out = tid / BT, b_out = tid % BT;
+  const cplx<R>* Wk = W + (size_t)k * wk_stride;
+  for (int m0 = 0; m0 < M; m0 += MT) {
+    cplx<R> acc = mk<R>(0, 0);
+    const int gbeg = sc * sc_len, gend = min(n, gbeg + sc_len);
+    for (int g0 = gbeg; g0 < gend; g0 += CH) {
+      for (int i = tid; i < BT * CH; i += NT) {
+        const int b = i / CH, e = i % CH, gg = g0 + e;
+        Xs[b][e] = (b < nbt && gg < gend) ? X[(size_t)(s0 + b) * x_stride + gg] : mk<R>(0, 0);
+      }
+      for (int i = tid; i < MT * CH; i += NT) {
+        const int m = i / CH, e = i % CH, gg = g0 + e;
+        Ws[m][e] = (m0 + m < M && gg < gend) ? Wk[(size_t)(m0 + m) * w_stride + gg] : mk<R>(0, 0);
+      }
+      __syncthreads();
+#pragma unroll 8
+      for (int e = 0; e < CH; ++e) {
+        const cplx<R> w = Ws[i_out][e], x = Xs[b_out][e];
+        acc.x += w.x * x.x + w.y * x.y;
+        acc.y += w.x * x.y - w.y * x.x;
+      }
+      __syncthreads();
+    }
+    if (m0 + i_out < M)
+      part[(((size_t)t * nsc + sc) * Mmax + m0 + i_out) * BT + b_out] = acc;
+  }
+}
+
+// coef[(slot0 + b) * cstride + m] = sum_sc part[...]  (fixed order)
+template <typename R>
+__global__ void gram_reduce_kernel(Tiles tl, const int* __restrict__ Mk, int Mmax,
+                                   int nsc, const cplx<R>* __restrict__ part,
+                                   cplx<R>* __restrict__ coef, int cstride) {
+  const int t = blockIdx.x;
+  const int k = tl.k[t], s0 = tl.slot0[t], nbt = tl.nb[t], M = Mk[k];
+  for (int i = threadIdx.x; i < Mmax * BT; i += blockDim.x) {
+    const int m = i / BT, b = i % BT;
+    if (m >= M || b >= nbt) continue;
+    cplx<R> acc = mk<R>(0, 0);
+    for (int sc = 0; sc < nsc; ++sc) {
+      const cplx<R> v = part[(((size_t)t * nsc + sc) * Mmax + m) * BT + b];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    coef[(size_t)(s0 + b) * cstride + m] = acc;
+  }
+}
+
+// Y[slot][g] = a * Y[slot][g] + sum_j alpha_j sum_m W_j[k][m][g] coef_j[slot][m]
+// for up to two (W, coef) sets; optional per-slot mask; optional partial
+// dot <D, Y_new> (real part) per (slot, block) into dpart[slot * gridDim.x + bx].
+template <typename R>
+__global__ __launch_bounds__(NT) void update_kernel(
+    Tiles tl, const int* __restrict__ nb, const int* __restrict__ active,
+    cplx<R>* __restrict__ Y, int y_stride, R a,
+    const cplx<R>* __restrict__ W1, size_t w1k, int w1s, const int* __restrict__ M1k,
+    const cplx<R>* __restrict__ C1, int c1s, R alpha1,
+    const cplx<R>* __restrict__ W2, size_t w2k, int w2s, const int* __restrict__ M2k,
+    const cplx<R>* __restrict__ C2, int c2s, R alpha2,
+    const cplx<R>* __restrict__ D, R* __restrict__ dpart) {
+  __shared__ cplx<R> c1[BT][MAXM];
+  __shared__ cplx<R> c2[BT][MAXM];
+  __shared__ R red[NT];
+  const int t = blockIdx.y, tid = threadIdx.x;
+  const int k = tl.k[t], s0 = tl.slot0[t], nbt = tl.nb[t];
+  const int n = nb[k];
+  const int M1 = W1 ? M1k[k] : 0, M2 = W2 ? M2k[k] : 0;
+  for (int i = tid; i < BT * MAXM; i += NT) {
+    const int b = i / MAXM, m = i % MAXM;
+    c1[b][m] = (b < nbt && m < M1) ? cscale<R>(C1[(size_t)(s0 + b) * c1s + m], alpha1) : mk<R>(0, 0);
+    c2[b][m] = (b < nbt && m < M2) ? cscale<R>(C2[(size_t)(s0 + b) * c2s + m], alpha2) : mk<R>(0, 0);
+  }
+  __syncthreads();
+  const int g = blockIdx.x * NT + tid;
+  cplx<R> acc[BT];
+#pragma unroll
+  for (int b = 0; b < BT; ++b) acc[b] = mk<R>(0, 0);
+  if (g < n) {
+    const cplx<R>* w1 = W1 ? W1 + (size_t)k * w1k + g : nullptr;
+    for (int m = 0; m < M1; ++m) {
+      const cplx<R> w = w1[(size_t)m * w1s];
+#pragma unroll
+      for (int b = 0; b < BT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c1[b][m]));
+    }
+    const cplx<R>* w2 = W2 ? W2 + (size_t)k * w2k + g : nullptr;
+    for (int m = 0; m < M2; ++m) {
+      const cplx<R> w = w2[(size_t)m * w2s];
+#pragma unroll
+      for (int b = 0; b < BT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c2[b][m]));
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < BT; ++b) {
+    const int slot = s0 + b;
+    const bool on = b < nbt && (!active || active[slot]);
+    R d = 0;
+    if (on && g < n) {
+      cplx<R>* yp = Y + (size_t)slot * y_stride + g;
+      cplx<R> y = *yp;
+      y = mk<R>(a * y.x + acc[b].x, a * y.y + acc[b].y);
+      *yp = y;
+      if (D) {
+        const cplx<R> dd = D[(size_t)slot * y_stride + g];
+        d = dd.x * y.x + dd.y * y.y;
+      }
+    }
+    if (dpart && b < nbt) {
+      red[tid] = d;
+      __syncthreads();
+      for (int w = NT / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+      }
+      if (tid == 0) dpart[(size_t)slot * gridDim.x + blockIdx.x] = red[0];
+      __syncthreads();
+    }
+  }
+}
+
+// x += alpha p ; r -= alpha w ; z = r / (kin + c) ; partial |r|^2
+template <typename R>
+__global__ __launch_bounds__(NT) void cg_step_kernel(
+    const int* __restrict__ slot_k, const int* __restrict__ nb,
+    const double* __restrict__ kin, int nb_max, const int* __restrict__ active,
+    const R* __restrict__ alpha, const R* __restrict__ pshift,
+    cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
+    cplx<R>* __restrict__ w, R* __restrict__ rpart, int stride) {
+  __shared__ R red[NT];
+  const int slot = blockIdx.y, tid = threadIdx.x;
+  if (active && !active[slot]) return;
+  const int k = slot_k[slot];
+  const int g = blockIdx.x * NT + tid;
+  R s = 0;
+  if (g < nb[k]) {
+    const size_t o = (size_t)slot * stride + g;
+    const R a = alpha[slot];
+    cplx<R> xv = x[o], rv = r[o];
+    const cplx<R> pv = p[o], wv = w[o];
+    xv = mk<R>(xv.x + a * pv.x, xv.y + a * pv.y);
+    rv = mk<R>(rv.x - a * wv.x, rv.y - a * wv.y);
+    x[o] = xv;
+    r[o] = rv;
+    const R m = R(1) / (R(kin[(size_t)k * nb_max + g]) + pshift[slot]);
+    w[o] = cscale<R>(rv, m);
+    s = rv.x * rv.x + rv.y * rv.y;
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int q = NT / 2; q > 0; q >>= 1) {
+    if (tid < q) red[tid] += red[tid + q];
+    __syncthreads();
+  }
+  if (tid == 0) rpart[(size_t)slot * gridDim.x + blockIdx.x] = red[0];
+}
+
+// z = r / (kin + c) (CG start), partial |r|^2
+template <typename R>
+__global__ __launch_bounds__(NT) void precond_kernel(
+    const int* __restrict__ slot_k, const int* __restrict__ nb,
+    const double* __restrict__ kin, int nb_max, const R* __restrict__ pshift,
+    const cplx<R>* __restrict__ r, cplx<R>* __restrict__ z, int stride) {
+  const int slot = blockIdx.y;
+  const int k = slot_k[slot];
+  const int g = blockIdx.x * NT + threadIdx.x;
+  if (g < nb[k]) {
+    const size_t o = (size_t)slot * stride + g;
+    z[o] = cscale<R>(r[o], R(1) / (R(kin[(size_t)k * nb_max + g]) + pshift[slot]));
+  }
+}
+
+// Per-slot scalar logic after a reduction of partials (fixed order).
+// op 0: pAp -> alpha = rz / pAp (0 if pAp == 0)
+// op 1: rnorm2 -> iteration count, convergence flags, active counter
+// op 2: rz_new -> beta = rz_new / rz, rz = rz_new  (start: beta = 0, rz = rz_new)
+template <typename R>
+__global__ void cg_scalar_kernel(int nslots, int nparts, const R* __restrict__ part,
+                                 int op, int* __restrict__ active,
+                                 CgScalars<R> cs, int start) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= nslots) return;
+  if (active && !active[slot] && op != 3) return;
+  R s = 0;
+  for (int i = 0; i < nparts; ++i) s += part[(size_t)slot * nparts + i];
+  if (op == 0) {
+    cs.alpha[slot] = s != R(0) ? cs.rz[slot] / s : R(0);
+  } else if (op == 1) {
+    const int it = ++cs.iters[slot];
+    cs.rnorm2[slot] = s;
+    const bool conv = it >= cs.min_iter && (double)s <= cs.tol2[slot];
+    if (conv || it >= cs.max_iter) {
+      active[slot] = 0;
+      if (!conv) atomicAdd(cs.noconv, 1);
+    } else {
+      atomicAdd(cs.nactive, 1);
+    }
+  } else if (op == 2) {
+    if (start) {
+      cs.beta[slot] = 0;
+    } else {
+      cs.beta[slot] = cs.rz[slot] != R(0) ? s / cs.rz[slot] : R(0);
+    }
+    cs.rz[slot] = s;
+  }
+}
+
+// out[i] = sum_g part[g][i] (fixed order), optional scale
+__global__ void sum_groups_kernel(int n, int ngroups, const double* __restrict__ part,
+                                  double scale, double* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)n) return;
+  double s = 0;
+  for (int g = 0; g < ngroups; ++g) s += part[(size_t)g * n + i];
+  out[i] = s * scale;
+}
+
+// Layout permutes between external C order [N0][N1][N2] and internal
+// [C][P][Q]: st_c, st_p, st_q are the external strides of the internal axes.
+__global__ void to_internal_kernel(int C, int P, int Q, int st_c, int st_p, int st_q,
+                                   const double* __restrict__ ext, double* __restrict__ in) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)C * P * Q) return;
+  const int q = i % Q, p = (i / Q) % P, c = i / ((size_t)P * Q);
+  in[i] = ext[(size_t)c * st_c + (size_t)p * st_p + (size_t)q * st_q];
+}
+__global__ void to_external_kernel(int C, int P, int Q, int st_c, int st_p, int st_q,
+                                   const double* __restrict__ in, double* __restrict__ ext,
+                                   double a, const double* __restrict__ base, double bscale) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)C * P * Q) return;
+  const int q = i % Q, p = (i / Q) % P, c = i / ((size_t)P * Q);
+  const size_t e = (size_t)c * st_c + (size_t)p * st_p + (size_t)q * st_q;
+  double v = a * in[i];
+  if (base) v += bscale * base[e];
+  ext[e] = v;
+}
+
+// partial[j * nblk + b] = sum over block b of V[j] . w   (j < nv)
+__global__ __launch_bounds__(NT) void multidot_kernel(int n, int nv, const double* __restrict__ V,
+                                                      size_t vstride, const double* __restrict__ w,
+                                                      double* __restrict__ partial) {
+  __shared__ double red[NT];
+  const int tid = threadIdx.x;
+  for (int j = 0; j < nv; ++j) {
+    double s = 0;
+    for (size_t i = (size_t)blockIdx.x * NT + tid; i < (size_t)n; i += (size_t)gridDim.x * NT)
+      s += V[j * vstride + i] * w[i];
+    red[tid] = s;
+    __syncthreads();
+    for (int q = NT / 2; q > 0; q >>= 1) {
+      if (tid < q) red[tid] += red[tid + q];
+      __syncthreads();
+    }
+    if (tid == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// y = a*y + sum_j c[j] V[j]   (c in device memory, nv <= 64)
+__global__ __launch_bounds__(NT) void multiaxpy_kernel(int n, int nv, const double* __restrict__ V,
+                                                       size_t vstride, const double* __restrict__ c,
+                                                       double a, double* __restrict__ y) {
+  __shared__ double cs[64];
+  if (threadIdx.x < nv) cs[threadIdx.x] = c[threadIdx.x];
+  __syncthreads();
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= (size_t)n) return;
+  double s = a * y[i];
+  for (int j = 0; j < nv; ++j) s += cs[j] * V[j * vstride + i];
+  y[i] = s;
+}
+
+__global__ void scale_copy_kernel(size_t n, const double* __restrict__ x, double a,
+                                  double* __restrict__ y) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i];
+}
+
+template <typename R>
+__global__ void cscale_kernel(size_t n, cplx<R>* __restrict__ x, R a) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = cscale<R>(x[i], a);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+static int nsc_for(int nb_max, int& sc_len) {
+  int nch = (nb_max + CH - 1) / CH;
+  int nsc = nch < 96 ? nch : 96;
+  int per = (nch + nsc - 1) / nsc;
+  sc_len = per * CH;
+  nsc = (nb_max + sc_len - 1) / sc_len;
+  return nsc;
+}
+
+size_t gram_part_elems(int ntiles, int nb_max, int Mmax) {
+  int sc_len;
+  const int nsc = nsc_for(nb_max, sc_len);
+  return (size_t)ntiles * nsc * Mmax * BT;
+}
+
+template <typename R>
+void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
+          const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
+          int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st) {
+  IKR_CHECK(Mmax <= MAXM, 1, "too many projector rows");
+  IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Mk && W && X && part && coef, 8,
+            "gram: null device pointer");
+  int sc_len;
+  const int nsc = nsc_for(nb_max, sc_len);
+  hipLaunchKernelGGL((gram_kernel<R>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, Mk,
+                     Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part);
+  IKR_HIP(hipGetLastError());
+  hipLaunchKernelGGL((gram_reduce_kernel<R>), dim3(tl.n), dim3(256), 0, st, tl, Mk, Mmax,
+                     nsc, part, coef, cstride);
+  IKR_HIP(hipGetLastError());
+}
+
+int update_nblocks(int nb_max) { return (nb_max + NT - 1) / NT; }
+
+template <typename R>
+void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
+            cplx<R>* Y, int y_stride, R a, const UpdTerm<R>& t1,
+            const UpdTerm<R>& t2, const cplx<R>* D, R* dpart, hipStream_t st) {
+  IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Y, 8, "update: null device pointer");
+  IKR_CHECK((!t1.W || (t1.Mk && t1.C)) && (!t2.W || (t2.Mk && t2.C)), 8,
+            "update: null coefficient pointer");
+  hipLaunchKernelGGL((update_kernel<R>), dim3(update_nblocks(nb_max), tl.n), dim3(NT), 0,
+                     st, tl, nb, active, Y, y_stride, a, t1.W, t1.wk, t1.ws, t1.Mk,
+                     t1.C, t1.cs, t1.alpha, t2.W, t2.wk, t2.ws, t2.Mk, t2.C, t2.cs,
+                     t2.alpha, D, dpart);
+  IKR_HIP(hipGetLastError());
+}
+
+int vec_nblocks(int nb_max) { return (nb_max + NT - 1) / NT; }
+
+template <typename R>
+void cg_step(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
+             const int* active, const R* alpha, const R* pshift, cplx<R>* x, cplx<R>* r,
+             const cplx<R>* p, cplx<R>* w, R* rpart, hipStream_t st) {
+  hipLaunchKernelGGL((cg_step_kernel<R>), dim3(vec_nblocks(nb_max), nslots), dim3(NT), 0,
+                     st, slot_k, nb, kin, nb_max, active, alpha, pshift, x, r, p, w, rpart,
+                     nb_max);
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
+void precond(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
+             const R* pshift, const cplx<R>* r, cplx<R>* z, hipStream_t st) {
+  hipLaunchKernelGGL((precond_kernel<R>), dim3(vec_nblocks(nb_max), nslots), dim3(NT), 0, st,
+                     slot_k, nb, kin, nb_max, pshift, r, z, nb_max);
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
+void cg_scalars(int nslots, int nparts, const R* part, int op, int* active,
+                const CgScalars<R>& cs, int start, hipStream_t st) {
+  hipLaunchKernelGGL((cg_scalar_kernel<R>), dim3((nslots + 127) / 128), dim3(128), 0, st,
+                     nslots, nparts, part, op, active, cs, start);
+  IKR_HIP(hipGetLastError());
+}
+
+void sum_groups(int n, int ngroups, const double* part, double scale, double* out,
+                hipStream_t st) {
+  hipLaunchKernelGGL(sum_groups_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, ngroups,
+                     part, scale, out);
+  IKR_HIP(hipGetLastError());
+}
+
+void to_internal(const Layout& L, const double* ext, double* in, hipStream_t st) {
+  const size_t n = (size_t)L.C * L.P * L.Q;
+  hipLaunchKernelGGL(to_internal_kernel, dim3((n + 255) / 256), dim3(256), 0, st, L.C, L.P,
+                     L.Q, L.st_c, L.st_p, L.st_q, ext, in);
+  IKR_HIP(hipGetLastError());
+}
+
+void to_external(const Layout& L, const double* in, double* ext, double a,
+                 const double* base, double bscale, hipStream_t st) {
+  const size_t n = (size_t)L.C * L.P * L.Q;
+  hipLaunchKernelGGL(to_external_kernel, dim3((n + 255) / 256), dim3(256), 0, st, L.C, L.P,
+                     L.Q, L.st_c, L.st_p, L.st_q, in, ext, a, base, bscale);
+  IKR_HIP(hipGetLastError());
+}
+
+int multidot_nblocks(int n) {
+  int b = (n + NT * 4 - 1) / (NT * 4);
+  return b < 256 ? b : 256;
+}
+
+void multidot(int n, int nv, const double* V, size_t vstride, const double* w,
+              double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(multidot_kernel, dim3(multidot_nblocks(n)), dim3(NT), 0, st, n, nv, V,
+                     vstride, w, partial);
+  IKR_HIP(hipGetLastError());
+}
+
+void multiaxpy(int n, int nv, const double* V, size_t vstride, const double* c, double a,
+               double* y, hipStream_t st) {
+  IKR_CHECK(nv <= 64, 1, "too many vectors in multiaxpy");
+  hipLaunchKernelGGL(multiaxpy_kernel, dim3((n + NT - 1) / NT), dim3(NT), 0, st, n, nv, V,
+                     vstride, c, a, y);
+  IKR_HIP(hipGetLastError());
+}
+
+void scale_copy(size_t n, const double* x, double a, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(scale_copy_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, x, a, y);
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
+void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st) {
+  hipLaunchKernelGGL((cscale_kernel<R>), dim3((n + 255) / 256), dim3(256), 0, st, n, x, a);
+  IKR_HIP(hipGetLastError());
+}
+
+#define IKR_INST(R)                                                                       \
+  template void gram<R>(const Tiles&, const int*, int, const int*, int, const cplx<R>*,   \
+                        size_t, int, const cplx<R>*, int, cplx<R>*, cplx<R>*, int,        \
+                        hipStream_t);                                                     \
+  template void update<R>(const Tiles&, const int*, int, const int*, cplx<R>*, int, R,    \
+                          const UpdTerm<R>&, const UpdTerm<R>&, const cplx<R>*, R*,       \
+                          hipStream_t);                                                   \
+  template void cg_step<R>(int, const int*, const int*, const double*, int, const int*,   \
+                           const R*, const R*, cplx<R>*, cplx<R>*, const cplx<R>*,        \
+                           cplx<R>*, R*, hipStream_t);                                    \
+  template void precond<R>(int, const int*, const int*, const double*, int, const R*,     \
+                           const cplx<R>*, cplx<R>*, hipStream_t);                        \
+  template void cg_scalars<R>(int, int, const R*, int, int*, const CgScalars<R>&, int,    \
+                              hipStream_t);                                               \
+  template void cscale_vec<R>(size_t, cplx<R>*, R, hipStream_t);
+IKR_INST(double)
+IKR_INST(float)
+#undef IKR_INST
+
+}  // namespace ikr

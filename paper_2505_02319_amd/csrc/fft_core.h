@@ -1,0 +1,180 @@
+// In-LDS batched 1D FFTs for gfx950: mixed-radix (2, 3, 4, 5) Stockham
+// autosort stages, each thread holding its butterflies in registers for the
+// duration of a stage, so that a stage reads every element of the line,
+// synchronises, then writes every element back in place (no ping-pong
+// buffer: a 60 x 108 FP64 plane already takes 101 KiB of the 160 KiB LDS).
+//
+// Transforms are unnormalised.  FWD: X_k = sum_j x_j e^{-2 pi i jk/N};
+// INV uses e^{+...}.  Twiddle table tw[m] = e^{-2 pi i m/N}, m < N.
+#pragma once
+
+#include "common.h"
+
+namespace ikr {
+
+// ------------------------------------------------------------ factorisation
+// Radix order per supported length (first stage has no twiddles).
+template <int N> struct Rad;
+#define IKR_RAD(N, ...)                                                        \
+  template <> struct Rad<N> {                                                  \
+    static constexpr int r[] = {__VA_ARGS__};                                  \
+    static constexpr int S = sizeof(r) / sizeof(int);                          \
+  };
+IKR_RAD(8, 4, 2)
+IKR_RAD(12, 4, 3)
+IKR_RAD(16, 4, 4)
+IKR_RAD(18, 3, 3, 2)
+IKR_RAD(20, 4, 5)
+IKR_RAD(24, 4, 3, 2)
+IKR_RAD(30, 5, 3, 2)
+IKR_RAD(32, 4, 4, 2)
+IKR_RAD(36, 4, 3, 3)
+IKR_RAD(40, 4, 5, 2)
+IKR_RAD(48, 4, 4, 3)
+IKR_RAD(60, 4, 5, 3)
+IKR_RAD(64, 4, 4, 4)
+IKR_RAD(72, 4, 3, 3, 2)
+IKR_RAD(80, 4, 4, 5)
+IKR_RAD(90, 5, 3, 3, 2)
+IKR_RAD(96, 4, 4, 3, 2)
+IKR_RAD(100, 4, 5, 5)
+IKR_RAD(108, 4, 3, 3, 3)
+IKR_RAD(120, 4, 5, 3, 2)
+IKR_RAD(128, 4, 4, 4, 2)
+#undef IKR_RAD
+
+// ------------------------------------------------------------ small DFTs
+template <typename R, bool INV>
+__device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) {  // a * (-i) forward, a * (+i) inverse
+  return INV ? mk<R>(-a.y, a.x) : mk<R>(a.y, -a.x);
+}
+
+template <typename R, int RAD, bool INV> struct Dft;
+
+template <typename R, bool INV> struct Dft<R, 2, INV> {
+  __device__ __forceinline__ static void run(cplx<R>* v) {
+    cplx<R> a = v[0], b = v[1];
+    v[0] = cadd<R>(a, b);
+    v[1] = csub<R>(a, b);
+  }
+};
+
+template <typename R, bool INV> struct Dft<R, 3, INV> {
+  __device__ __forceinline__ static void run(cplx<R>* v) {
+    const R s = R(0.86602540378443864676372317075294);   // sqrt(3)/2
+    cplx<R> a = v[0], b = v[1], c = v[2];
+    cplx<R> t1 = cadd<R>(b, c);
+    cplx<R> t2 = mk<R>(a.x - R(0.5) * t1.x, a.y - R(0.5) * t1.y);
+    cplx<R> t3 = mul_mi<R, INV>(cscale<R>(csub<R>(b, c), s));
+    v[0] = cadd<R>(a, t1);
+    v[1] = cadd<R>(t2, t3);
+    v[2] = csub<R>(t2, t3);
+  }
+};
+
+template <typename R, bool INV> struct Dft<R, 4, INV> {
+  __device__ __forceinline__ static void run(cplx<R>* v) {
+    cplx<R> a = v[0], b = v[1], c = v[2], d = v[3];
+    cplx<R> t0 = cadd<R>(a, c), t1 = csub<R>(a, c);
+    cplx<R> t2 = cadd<R>(b, d), t3 = mul_mi<R, INV>(csub<R>(b, d));
+    v[0] = cadd<R>(t0, t2);
+    v[2] = csub<R>(t0, t2);
+    v[1] = cadd<R>(t1, t3);
+    v[3] = csub<R>(t1, t3);
+  }
+};
+
+template <typename R, bool INV> struct Dft<R, 5, INV> {
+  __device__ __forceinline__ static void run(cplx<R>* v) {
+    // c1 = cos(2pi/5), c2 = cos(4pi/5), s1 = sin(2pi/5), s2 = sin(4pi/5)
+    const R c1 = R(0.30901699437494742410229341718282);
+    const R c2 = R(-0.80901699437494742410229341718282);
+    const R s1 = R(0.95105651629515357211643933337938);
+    const R s2 = R(0.58778525229247312916870595463907);
+    cplx<R> a = v[0];
+    cplx<R> t1 = cadd<R>(v[1], v[4]), t2 = cadd<R>(v[2], v[3]);
+    cplx<R> t3 = csub<R>(v[1], v[4]), t4 = csub<R>(v[2], v[3]);
+    cplx<R> u1 = mk<R>(a.x + c1 * t1.x + c2 * t2.x, a.y + c1 * t1.y + c2 * t2.y);
+    cplx<R> u2 = mk<R>(a.x + c2 * t1.x + c1 * t2.x, a.y + c2 * t1.y + c1 * t2.y);
+    cplx<R> w1 = mul_mi<R, INV>(mk<R>(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y));
+    cplx<R> w2 = mul_mi<R, INV>(mk<R>(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y));
+    v[0] = mk<R>(a.x + t1.x + t2.x, a.y + t1.y + t2.y);
+    v[1] = cadd<R>(u1, w1);
+    v[4] = csub<R>(u1, w1);
+    v[2] = cadd<R>(u2, w2);
+    v[3] = csub<R>(u2, w2);
+  }
+};
+
+// ------------------------------------------------------------ stage driver
+// Lines live in LDS at buf[l * lstride + e * estride], l < nlines.
+// NT threads, TPL threads per line, MAXV = max lines per thread group.
+template <typename R, int N, int TPL, int NT, int MAXV, bool INV, int STAGE, int NS>
+struct Stages {
+  __device__ __forceinline__ static void run(cplx<R>* buf, int nlines,
+                                             int lstride, int estride,
+                                             const cplx<R>* __restrict__ tw) {
+    constexpr int RAD = Rad<N>::r[STAGE];
+    constexpr int NB = N / RAD;                   // butterflies per line
+    constexpr int BPT = (NB + TPL - 1) / TPL;     // butterflies per thread
+    constexpr int G = NT / TPL;                   // thread groups
+    const int tid = threadIdx.x;
+    const int grp = tid / TPL, lane = tid % TPL;
+    cplx<R> v[MAXV][BPT][RAD];
+#pragma unroll
+    for (int vl = 0; vl < MAXV; ++vl) {
+      const int l = grp + G * vl;
+#pragma unroll
+      for (int u = 0; u < BPT; ++u) {
+        const int b = lane + TPL * u;
+        if (grp < G && l < nlines && b < NB) {
+          cplx<R>* line = buf + l * lstride;
+#pragma unroll
+          for (int r = 0; r < RAD; ++r) {
+            cplx<R> x = line[(b + r * NB) * estride];
+            if (NS > 1 && r > 0) {
+              cplx<R> w = tw[(r * (b % NS)) * (N / (NS * RAD))];
+              if (INV) w.y = -w.y;
+              x = cmul<R>(x, w);
+            }
+            v[vl][u][r] = x;
+          }
+          Dft<R, RAD, INV>::run(v[vl][u]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int vl = 0; vl < MAXV; ++vl) {
+      const int l = grp + G * vl;
+#pragma unroll
+      for (int u = 0; u < BPT; ++u) {
+        const int b = lane + TPL * u;
+        if (grp < G && l < nlines && b < NB) {
+          cplx<R>* line = buf + l * lstride;
+          const int d = (b / NS) * NS * RAD + (b % NS);
+#pragma unroll
+          for (int r = 0; r < RAD; ++r) line[(d + r * NS) * estride] = v[vl][u][r];
+        }
+      }
+    }
+    __syncthreads();
+    if constexpr (STAGE + 1 < Rad<N>::S)
+      Stages<R, N, TPL, NT, MAXV, INV, STAGE + 1, NS * RAD>::run(buf, nlines, lstride, estride, tw);
+  }
+};
+
+// Entry point: all lines transformed; caller must __syncthreads() before
+// (data written) -- the first stage's reads happen without a barrier.
+template <typename R, int N, int TPL, int NT, int MAXV, bool INV>
+__device__ __forceinline__ void lds_fft(cplx<R>* buf, int nlines, int lstride,
+                                        int estride, const cplx<R>* tw) {
+  Stages<R, N, TPL, NT, MAXV, INV, 0, 1>::run(buf, nlines, lstride, estride, tw);
+}
+
+// Threads per line: enough to keep per-thread register arrays small.
+template <int N> constexpr int tpl_for() {
+  return N <= 16 ? 4 : (N <= 40 ? 4 : (N <= 72 ? 6 : 9));
+}
+
+}  // namespace ikr

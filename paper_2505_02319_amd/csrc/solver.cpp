@@ -1,0 +1,482 @@
+// Response solver: chi0 through batched Sternheimer CG (paper eq. kchi0,
+// eq. delta_phi_P, eq. sternheimer_equation, eq. delta_f), the dielectric
+// adjoint E v = v - ||Kv|| chi0(Kv/||Kv||) (eq. op_discretised), the CG
+// tolerance strategies of Table 1 / Table strategies_k, and inexact
+// GMRES(m) with the adaptive estimate s (Algorithm 1).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "system.h"
+
+namespace ikr {
+
+namespace {
+
+constexpr double DEGEN_TOL = 1e-8;
+
+double focc_dx(double x) {
+  const double e = std::exp(-std::fabs(x));
+  return -2.0 * e / ((1.0 + e) * (1.0 + e));
+}
+
+template <typename T> std::vector<T> download(const T* d, size_t n, hipStream_t st) {
+  std::vector<T> h(n);
+  if (n) IKR_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, st));
+  IKR_HIP(hipStreamSynchronize(st));
+  return h;
+}
+
+// Smallest singular value of an (r x c) row-major matrix, one-sided Jacobi.
+double sigma_min(const std::vector<double>& H, int r, int c) {
+  std::vector<double> A(H);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0;
+    for (int p = 0; p < c; ++p)
+      for (int q = p + 1; q < c; ++q) {
+        double al = 0, be = 0, ga = 0;
+        for (int i = 0; i < r; ++i) {
+          al += A[i * c + p] * A[i * c + p];
+          be += A[i * c + q] * A[i * c + q];
+          ga += A[i * c + p] * A[i * c + q];
+        }
+        if (ga == 0) continue;
+        off = std::max(off, std::fabs(ga) / std::sqrt(al * be));
+        const double zeta = (be - al) / (2 * ga);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1 + zeta * zeta));
+        const double cs = 1 / std::sqrt(1 + t * t), sn = cs * t;
+        for (int i = 0; i < r; ++i) {
+          const double x = A[i * c + p], y = A[i * c + q];
+          A[i * c + p] = cs * x - sn * y;
+          A[i * c + q] = sn * x + cs * y;
+        }
+      }
+    if (off < 1e-15) break;
+  }
+  double mn = 1e300;
+  for (int p = 0; p < c; ++p) {
+    double n2 = 0;
+    for (int i = 0; i < r; ++i) n2 += A[i * c + p] * A[i * c + p];
+    mn = std::min(mn, std::sqrt(n2));
+  }
+  return mn;
+}
+
+// min_y ||beta e1 - H y|| for the (i+1) x i Hessenberg (row-major, ld = m)
+// by Givens rotations; returns the residual norm and y.
+double small_ls(const std::vector<double>& H, int ld, int i, double beta,
+                std::vector<double>& y) {
+  std::vector<double> R((size_t)(i + 1) * i), g(i + 1, 0.0);
+  for (int a = 0; a <= i; ++a)
+    for (int b = 0; b < i; ++b) R[a * i + b] = H[a * ld + b];
+  g[0] = beta;
+  for (int j = 0; j < i; ++j) {
+    const double a = R[j * i + j], b = R[(j + 1) * i + j];
+    const double rr = std::hypot(a, b);
+    const double c = rr > 0 ? a / rr : 1.0, sn = rr > 0 ? b / rr : 0.0;
+    for (int col = j; col < i; ++col) {
+      const double x = R[j * i + col], z = R[(j + 1) * i + col];
+      R[j * i + col] = c * x + sn * z;
+      R[(j + 1) * i + col] = -sn * x + c * z;
+    }
+    const double x = g[j], z = g[j + 1];
+    g[j] = c * x + sn * z;
+    g[j + 1] = -sn * x + c * z;
+  }
+  y.assign(i, 0.0);
+  for (int j = i - 1; j >= 0; --j) {
+    double v = g[j];
+    for (int col = j + 1; col < i; ++col) v -= R[j * i + col] * y[col];
+    y[j] = R[j * i + j] != 0 ? v / R[j * i + j] : 0.0;
+  }
+  return std::fabs(g[i]);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- H psi
+void apply_hamiltonian(System& s, int k, int nvec, const double2* x, double2* y) {
+  const hipStream_t st = s.stream;
+  std::vector<int> sk(nvec, k);
+  DBuf<int> dsk, dtk, dts, dtn;
+  dsk.upload(sk, st);
+  std::vector<int> tk, ts, tn;
+  for (int v0 = 0; v0 < nvec; v0 += BT) {
+    tk.push_back(k);
+    ts.push_back(v0);
+    tn.push_back(std::min(BT, nvec - v0));
+  }
+  dtk.upload(tk, st); dts.upload(ts, st); dtn.upload(tn, st);
+  Tiles tl{(int)tk.size(), dtk.get(), dts.get(), dtn.get()};
+  DBuf<double2> T1, T2, coef, part;
+  T1.alloc((size_t)nvec * s.L.C * s.ncol_max);
+  T2.alloc((size_t)nvec * s.L.C * s.ncol_max);
+  Slots sl{nvec, dsk.get(), nullptr};
+  launch_col_inv<double>(s.geom, s.fft, sl, x, s.nb_max, T1.get(), nullptr, nullptr, nullptr, st);
+  launch_plane_hv<double>(s.geom, s.fft, sl, T1.get(), T2.get(), s.d_vloc.get(), 0, st);
+  launch_col_fwd<double>(s.geom, s.fft, sl, T2.get(), y, s.nb_max, x, nullptr, 1.0 / s.ng, st);
+  if (s.natoms > 0) {
+    coef.alloc((size_t)nvec * MAXM);
+    part.alloc(gram_part_elems(tl.n, s.nb_max, s.natoms));
+    gram<double>(tl, s.d_nb.get(), s.nb_max, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
+                 (size_t)s.natoms * s.nb_max, s.nb_max, x, s.nb_max, part.get(), coef.get(),
+                 MAXM, st);
+    UpdTerm<double> t1{s.d_proj.get(), (size_t)s.natoms * s.nb_max, s.nb_max,
+                       s.d_natoms_k.get(), coef.get(), MAXM, s.dnl};
+    update<double>(tl, s.d_nb.get(), s.nb_max, nullptr, y, s.nb_max, 1.0, t1, UpdTerm<double>{},
+                   nullptr, nullptr, st);
+  }
+  IKR_HIP(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------- K
+double apply_kernel(System& s, const double* v_int, double* kv_int) {
+  launch_kernel_apply(s.geom, s.fft, v_int, s.d_khat.get(), s.xc ? s.d_fx.get() : nullptr,
+                      kv_int, s.d_kw1.get(), s.d_kw2.get(), s.d_kpart.get(), s.stream);
+  const std::vector<double> part = download(s.d_kpart.get(), s.L.C, s.stream);
+  double ss = 0;
+  for (double v : part) ss += v;
+  return std::sqrt(ss);
+}
+
+// ---------------------------------------------------------------- chi0
+Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
+                               const std::vector<double>& tol_slot, int min_iter,
+                               int max_iter) {
+  IKR_CHECK(s.have_gs, 2, "ground state not set up");
+  const hipStream_t st = s.stream;
+  CgWork<double>& w = s.w64;
+  const int J = s.J, nbm = s.nb_max, nbn = s.nbands;
+  const double inv_ng = 1.0 / s.ng;
+  Slots all{J, s.d_slot_k.get(), nullptr};
+  Slots act{J, s.d_slot_k.get(), s.d_active.get()};
+  const size_t phik = (size_t)nbn * nbm;
+  UpdTerm<double> none{};
+  Chi0Result res;
+
+  // right-hand sides t_j = F(u F^-1 phi_j) into r
+  launch_plane_hv<double>(s.geom, s.fft, all, s.d_Tphi.get(), w.T2.get(), u_int, 0, st);
+  launch_col_fwd<double>(s.geom, s.fft, all, w.T2.get(), w.r.get(), nbm, nullptr, nullptr,
+                         inv_ng, st);
+  // M[j][m] = <phi_m, t_j>
+  gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
+               nbm, w.r.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+  const std::vector<double2> M = download(w.coefA.get(), (size_t)J * MAXM, st);
+
+  // occupation response and occupied-space part (minimal gauge)
+  std::vector<double> de(J), df(J, 0.0);
+  std::vector<double2> dp((size_t)J * MAXM, mk<double>(0, 0));
+  double num = 0, den = 0;
+  for (int j = 0; j < J; ++j) {
+    const int k = s.slot_k[j], n = s.slot_n[j];
+    de[j] = M[(size_t)j * MAXM + n].x;
+    const double fpn = s.docc[(size_t)k * nbn + n];
+    num += s.kp[k].weight * fpn * de[j];
+    den += s.kp[k].weight * fpn;
+    const double fn = s.occ[(size_t)k * nbn + n], en = s.eps[(size_t)k * nbn + n];
+    for (int m = 0; m < s.nocc_k[k]; ++m) {
+      if (m == n) continue;
+      const double fm = s.occ[(size_t)k * nbn + m], em = s.eps[(size_t)k * nbn + m];
+      double d;
+      if (std::fabs(en - em) < DEGEN_TOL) {
+        d = s.temperature > 0
+                ? focc_dx((0.5 * (en + em) - s.fermi) / s.temperature) / s.temperature
+                : 0.0;
+      } else {
+        d = (fn - fm) / (en - em);
+      }
+      if (d == 0.0) continue;
+      const double al = fn * d / (fn * fn + fm * fm);
+      dp[(size_t)j * MAXM + m] = cscale<double>(M[(size_t)j * MAXM + m], al);
+    }
+  }
+  const double defermi = den != 0.0 ? num / den : 0.0;
+  for (int j = 0; j < J; ++j)
+    df[j] = s.docc[(size_t)s.slot_k[j] * nbn + s.slot_n[j]] * (de[j] - defermi);
+
+  // b = -Q t   (r = -t + Phi M)
+  UpdTerm<double> phiM{s.d_phi.get(), phik, nbm, s.d_nocc_k.get(), w.coefA.get(), MAXM, 1.0};
+  update<double>(s.tiles, s.d_nb.get(), nbm, nullptr, w.r.get(), nbm, -1.0, phiM, none,
+                 nullptr, nullptr, st);
+
+  // CG start: x = 0, p = 0, z = Q M^-1 r, rz = <r, z>
+  IKR_HIP(hipMemsetAsync(w.x.get(), 0, (size_t)J * nbm * sizeof(double2), st));
+  IKR_HIP(hipMemsetAsync(w.p.get(), 0, (size_t)J * nbm * sizeof(double2), st));
+  std::vector<double> tol2(J);
+  for (int j = 0; j < J; ++j) tol2[j] = tol_slot[j] * tol_slot[j];
+  IKR_HIP(hipMemcpyAsync(s.d_tol2.get(), tol2.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<int> ones(J, 1);
+  IKR_HIP(hipMemcpyAsync(s.d_active.get(), ones.data(), J * sizeof(int), hipMemcpyHostToDevice, st));
+  IKR_HIP(hipMemsetAsync(s.d_iters.get(), 0, J * sizeof(int), st));
+  IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, 4 * sizeof(int), st));
+  CgScalars<double> cs{w.rz.get(), w.alpha.get(), w.beta.get(), w.rnorm2.get(), s.d_tol2.get(),
+                       s.d_iters.get(), s.d_counters.get(), s.d_counters.get() + 1,
+                       min_iter, max_iter};
+  const int nup = update_nblocks(nbm), nvb = vec_nblocks(nbm);
+  UpdTerm<double> phiA{s.d_phi.get(), phik, nbm, s.d_nocc_k.get(), w.coefA.get(), MAXM, -1.0};
+  UpdTerm<double> projB{s.d_proj.get(), (size_t)s.natoms * nbm, nbm, s.d_natoms_k.get(),
+                        w.coefB.get(), MAXM, s.dnl};
+
+  precond<double>(J, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, w.pshift.get(),
+                  w.r.get(), w.w.get(), st);
+  gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
+               nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+  update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA, none,
+                 w.r.get(), w.dpart.get(), st);
+  cg_scalars<double>(J, nup, w.dpart.get(), 2, s.d_active.get(), cs, 1, st);
+
+  int nact = J;
+  for (int it = 0; it < max_iter && nact > 0; ++it) {
+    // p = z + beta p ; w = (H - e) p  (local part through the pruned FFT)
+    launch_col_inv<double>(s.geom, s.fft, act, w.p.get(), nbm, w.T1.get(), w.w.get(),
+                           w.beta.get(), w.p.get(), st);
+    launch_plane_hv<double>(s.geom, s.fft, act, w.T1.get(), w.T2.get(), s.d_vloc.get(), 0, st);
+    launch_col_fwd<double>(s.geom, s.fft, act, w.T2.get(), w.w.get(), nbm, w.p.get(),
+                           w.shift.get(), inv_ng, st);
+    if (s.natoms > 0) {
+      gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
+                   (size_t)s.natoms * nbm, nbm, w.p.get(), nbm, w.part.get(), w.coefB.get(),
+                   MAXM, st);
+      update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, projB,
+                     none, nullptr, nullptr, st);
+    }
+    // Ap = Q w ; pAp
+    gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
+                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+    update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
+                   none, w.p.get(), w.dpart.get(), st);
+    cg_scalars<double>(J, nup, w.dpart.get(), 0, s.d_active.get(), cs, 0, st);
+    // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, convergence
+    cg_step<double>(J, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, s.d_active.get(),
+                    w.alpha.get(), w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(),
+                    w.dpart.get(), st);
+    IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, sizeof(int), st));
+    cg_scalars<double>(J, nvb, w.dpart.get(), 1, s.d_active.get(), cs, 0, st);
+    // z = Q M^-1 r, rz = <r, z>, beta
+    gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
+                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+    update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
+                   none, w.r.get(), w.dpart.get(), st);
+    cg_scalars<double>(J, nup, w.dpart.get(), 2, s.d_active.get(), cs, 0, st);
+    res.n_ham += nact;
+    int cnt = 0;
+    IKR_HIP(hipMemcpyAsync(&cnt, s.d_counters.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    IKR_HIP(hipStreamSynchronize(st));
+    nact = cnt;
+  }
+  res.n_ham64 = res.n_ham;
+  int noconv = 0;
+  IKR_HIP(hipMemcpyAsync(&noconv, s.d_counters.get() + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  IKR_HIP(hipStreamSynchronize(st));
+  res.noconv = noconv + nact;
+
+  // final projection and occupied part: dphi = x - Phi Phi^H x + Phi dP
+  gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
+               nbm, w.x.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+  IKR_HIP(hipMemcpyAsync(w.coefB.get(), dp.data(), dp.size() * sizeof(double2),
+                         hipMemcpyHostToDevice, st));
+  UpdTerm<double> phiB{s.d_phi.get(), phik, nbm, s.d_nocc_k.get(), w.coefB.get(), MAXM, 1.0};
+  update<double>(s.tiles, s.d_nb.get(), nbm, nullptr, w.x.get(), nbm, 1.0, phiA, phiB, nullptr,
+                 nullptr, st);
+
+  // drho = sum_k w_k sum_n 2 f Re(conj psi dpsi) + df |psi|^2
+  launch_col_inv<double>(s.geom, s.fft, all, w.x.get(), nbm, w.T1.get(), nullptr, nullptr,
+                         nullptr, st);
+  std::vector<double> wa(J), wb(J);
+  for (int j = 0; j < J; ++j) {
+    const int k = s.slot_k[j];
+    wa[j] = 2.0 * s.kp[k].weight * s.occ[(size_t)k * nbn + s.slot_n[j]] / s.volume;
+    wb[j] = s.kp[k].weight * df[j] / s.volume;
+  }
+  IKR_HIP(hipMemcpyAsync(s.d_wa.get(), wa.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
+  IKR_HIP(hipMemcpyAsync(s.d_wb.get(), wb.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
+  const int gsz = 8;
+  launch_plane_rho(s.geom, s.fft, J, s.d_slot_k.get(), s.d_Tphi.get(), w.T1.get(), s.d_wa.get(),
+                   s.d_wb.get(), gsz, s.d_rhopart.get(), st);
+  sum_groups(s.ng, (J + gsz - 1) / gsz, s.d_rhopart.get(), 1.0, drho_int, st);
+  IKR_HIP(hipStreamSynchronize(st));
+  return res;
+}
+
+// ---------------------------------------------------------------- tolerances
+// Prefactor of Table 1 in its k-point form (Table strategies_k, with the
+// per-k occupied counts replaced by the total N_occ as in the paper's runs).
+static std::vector<double> prefactors(const System& s, int strategy, double knorm,
+                                      double bnorm) {
+  std::vector<double> p(s.J, 1.0);
+  const double nocc_tot = s.J;
+  for (int j = 0; j < s.J; ++j) {
+    const int k = s.slot_k[j];
+    const double f = s.occ[(size_t)k * s.nbands + s.slot_n[j]];
+    const double wk = s.kp[k].weight;
+    switch (strategy) {
+      case IKR_AGR: p[j] = 1.0; break;
+      case IKR_BAL: p[j] = s.volume / (2.0 * f * wk * nocc_tot * std::sqrt((double)s.ng)); break;
+      case IKR_GRT:
+        p[j] = std::sqrt(s.volume) / (2.0 * f * wk * std::sqrt((double)s.ng) *
+                                      std::sqrt(nocc_tot) * knorm * s.orbnorm_k[k]);
+        break;
+      case IKR_D10: p[j] = 0.1; break;
+      case IKR_D100: p[j] = 0.01; break;
+      case IKR_D10N: p[j] = 0.1 / bnorm; break;
+      default: p[j] = 1.0;
+    }
+  }
+  return p;
+}
+
+// ---------------------------------------------------------------- E v
+void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext, double common,
+                          const ikr_solver_opts& o, double bnorm, ikr_stats* stt) {
+  const hipStream_t st = s.stream;
+  to_internal(s.L, v_ext, s.d_tmpg.get(), st);
+  const double nu = apply_kernel(s, s.d_tmpg.get(), s.d_u.get());
+  s.knorm_hist.push_back(nu);
+  if (stt) stt->knorm_last = nu;
+  if (nu == 0.0) {
+    IKR_HIP(hipMemcpyAsync(ev_ext, v_ext, s.ng * sizeof(double), hipMemcpyDeviceToDevice, st));
+    IKR_HIP(hipStreamSynchronize(st));
+    return;
+  }
+  scale_copy(s.ng, s.d_u.get(), 1.0 / nu, s.d_u.get(), st);
+  std::vector<double> tol = prefactors(s, o.strategy, nu, bnorm);
+  for (double& t : tol) t *= common;
+  Chi0Result r = apply_chi0_internal(s, s.d_u.get(), s.d_drho.get(), tol, o.cg_min_iter,
+                                     o.cg_max_iter);
+  if (stt) {
+    stt->n_ham += r.n_ham;
+    stt->n_ham_fp64 += r.n_ham64;
+    stt->n_ham_fp32 += r.n_ham32;
+    stt->cg_unconverged += r.noconv;
+  }
+  to_external(s.L, s.d_drho.get(), ev_ext, -nu, v_ext, 1.0, st);
+  IKR_HIP(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------- Alg. 1
+void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_solver_opts& o,
+                    ikr_stats* stt) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const hipStream_t st = s.stream;
+  const int n = s.ng, m = o.restart_m;
+  IKR_CHECK(m >= 1 && m <= 60, 1, "restart size out of range");
+  const bool adaptive = o.strategy == IKR_AGR || o.strategy == IKR_BAL || o.strategy == IKR_GRT;
+  DBuf<double> V, coef, part, tmp;
+  V.alloc((size_t)(m + 1) * n);
+  coef.alloc(64);
+  const int nbl = multidot_nblocks(n);
+  part.alloc((size_t)(m + 1) * nbl);
+  tmp.alloc(n);
+
+  auto dots = [&](int nv, const double* Vp, const double* w) {
+    multidot(n, nv, Vp, n, w, part.get(), st);
+    const std::vector<double> h = download(part.get(), (size_t)nv * nbl, st);
+    std::vector<double> out(nv, 0.0);
+    for (int j = 0; j < nv; ++j)
+      for (int b = 0; b < nbl; ++b) out[j] += h[(size_t)j * nbl + b];
+    return out;
+  };
+  auto axpy = [&](int nv, const double* Vp, const std::vector<double>& c, double a, double* y) {
+    IKR_HIP(hipMemcpyAsync(coef.get(), c.data(), nv * sizeof(double), hipMemcpyHostToDevice, st));
+    IKR_HIP(hipStreamSynchronize(st));
+    multiaxpy(n, nv, Vp, n, coef.get(), a, y, st);
+  };
+
+  const double bnorm = std::sqrt(dots(1, b_ext, b_ext)[0]);
+  const double tau = o.tol_is_relative ? o.tol * bnorm : o.tol;
+  IKR_CHECK(std::isfinite(bnorm), 5, "non-finite right-hand side");
+  IKR_HIP(hipMemsetAsync(x_ext, 0, (size_t)n * sizeof(double), st));
+  double s_est = o.s0;
+  bool x0_zero = true;
+  int restarts = 0, iters = 0;
+  double resid = bnorm;
+  std::vector<double> H((size_t)(m + 1) * m);
+  bool done = bnorm == 0.0;
+  while (!done) {
+    // line 1: r0 = b - E~(0) x0 with tolerance tau/3
+    double* v0 = V.get();
+    if (x0_zero) {
+      IKR_HIP(hipMemcpyAsync(v0, b_ext, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else {
+      apply_dielectric_ext(s, x_ext, v0, adaptive ? tau / 3.0 : tau, o, bnorm, stt);
+      axpy(1, b_ext, {1.0}, -1.0, v0);
+    }
+    const double beta = std::sqrt(dots(1, v0, v0)[0]);
+    if (beta == 0.0) break;
+    scale_copy(n, v0, 1.0 / beta, v0, st);
+    std::fill(H.begin(), H.end(), 0.0);
+    resid = beta;
+    bool conv = false;
+    int i_used = 0;
+    std::vector<double> y;
+    for (int i = 1; i <= m; ++i) {
+      const double common = adaptive ? (s_est / (3.0 * m)) * tau / resid : tau;
+      double* vi = V.get() + (size_t)i * n;
+      apply_dielectric_ext(s, V.get() + (size_t)(i - 1) * n, vi, common, o, bnorm, stt);
+      ++iters;
+      // classical Gram-Schmidt, twice
+      std::vector<double> h = dots(i, V.get(), vi);
+      std::vector<double> neg(i);
+      for (int j = 0; j < i; ++j) neg[j] = -h[j];
+      axpy(i, V.get(), neg, 1.0, vi);
+      std::vector<double> h2 = dots(i, V.get(), vi);
+      for (int j = 0; j < i; ++j) { neg[j] = -h2[j]; h[j] += h2[j]; }
+      axpy(i, V.get(), neg, 1.0, vi);
+      const double hn = std::sqrt(dots(1, vi, vi)[0]);
+      for (int j = 0; j < i; ++j) H[(size_t)j * m + (i - 1)] = h[j];
+      H[(size_t)i * m + (i - 1)] = hn;
+      if (hn > 0) scale_copy(n, vi, 1.0 / hn, vi, st);
+      resid = small_ls(H, m, i, beta, y);
+      i_used = i;
+      if (resid <= tau / 3.0) {
+        std::vector<double> Hi((size_t)(i + 1) * i);
+        for (int a = 0; a <= i; ++a)
+          for (int c = 0; c < i; ++c) Hi[(size_t)a * i + c] = H[(size_t)a * m + c];
+        const double sig = sigma_min(Hi, i + 1, i);
+        axpy(i, V.get(), y, 1.0, x_ext);
+        x0_zero = false;
+        if (stt) stt->sigma_min = sig;
+        if (s_est <= sig) { done = true; conv = true; break; }
+        s_est = sig;            // line: restart with s = sigma_i(H_i)
+        conv = true;
+        break;
+      }
+      if (hn == 0.0) break;     // exact invariant subspace
+    }
+    if (!conv) {
+      std::vector<double> Hm((size_t)(i_used + 1) * i_used);
+      for (int a = 0; a <= i_used; ++a)
+        for (int c = 0; c < i_used; ++c) Hm[(size_t)a * i_used + c] = H[(size_t)a * m + c];
+      const double sig = sigma_min(Hm, i_used + 1, i_used);
+      axpy(i_used, V.get(), y, 1.0, x_ext);
+      x0_zero = false;
+      s_est = sig;
+      if (stt) stt->sigma_min = sig;
+    }
+    if (done) break;
+    if (++restarts > o.max_restarts) {
+      if (stt) { stt->restarts = restarts; stt->gmres_iters = iters; }
+      throw Error(4, "GMRES restart cap reached");
+    }
+  }
+  if (stt) {
+    stt->gmres_iters = iters;
+    stt->restarts = restarts;
+    stt->est_res = resid;
+    stt->s_final = s_est;
+    stt->true_res = -1;
+  }
+  if (o.want_true_residual && stt) {
+    ikr_solver_opts ot = o;
+    ot.strategy = IKR_FIXED;
+    ikr_stats dummy{};
+    apply_dielectric_ext(s, x_ext, tmp.get(), o.true_res_cg_tol, ot, bnorm, &dummy);
+    axpy(1, b_ext, {1.0}, -1.0, tmp.get());
+    stt->true_res = std::sqrt(dots(1, tmp.get(), tmp.get())[0]);
+  }
+  IKR_HIP(hipStreamSynchronize(st));
+  if (stt)
+    stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace ikr

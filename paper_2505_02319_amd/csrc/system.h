@@ -1,0 +1,142 @@
+// Host-side state of one response system (opaque ikr_handle).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/ikr.h"
+#include "blas.h"
+#include "common.h"
+
+namespace ikr {
+
+// Owning device buffer.
+template <typename T> struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { if (p) (void)hipFree(p); }
+  void alloc(size_t count) {
+    if (p) { (void)hipFree(p); p = nullptr; }
+    n = count;
+    if (count) IKR_HIP(hipMalloc(&p, count * sizeof(T)));
+  }
+  // Copies from pageable host memory complete before returning, so the
+  // source vector may be released right after the call.
+  void upload(const std::vector<T>& h, hipStream_t st) {
+    alloc(h.size());
+    if (n) {
+      IKR_HIP(hipMemcpyAsync(p, h.data(), n * sizeof(T), hipMemcpyHostToDevice, st));
+      IKR_HIP(hipStreamSynchronize(st));
+    }
+  }
+  T* get() const { return p; }
+};
+
+struct KPoint {
+  double kfrac[3];
+  double kcart[3];
+  double weight;
+  int nb = 0;
+  int ncol = 0;
+  std::vector<int> miller;   // [nb][3] external axes
+  std::vector<double> kin;   // [nb]
+  std::vector<int> col_start, col_pq, col_clo;
+};
+
+// Per-precision Sternheimer CG work space.
+template <typename R> struct CgWork {
+  DBuf<cplx<R>> x, r, p, w, T1, T2, coefA, coefB, part;
+  DBuf<R> rz, alpha, beta, rnorm2, dpart, pshift, shift;
+  DBuf<cplx<R>> phi, proj;     // copies of Phi / projectors in this precision
+  DBuf<R> vloc;
+};
+
+struct System {
+  // model
+  double a[3], b[3], volume = 0;
+  int N[3], ng = 0;
+  int natoms = 0;
+  std::vector<double> pos, amp;   // cartesian [natoms][3]
+  double sigma_loc = 0, sigma_proj = 0, dnl = 0, ecut = 0, temperature = 0;
+  int kgrid[3];
+  int nocc = 0, nextra = 0, nbands = 0, xc = 0;
+  hipStream_t stream = nullptr;
+
+  // layout
+  int cax = 0, pax = 1, qax = 2;
+  Layout L{};
+  Geom geom{};
+  FftTables fft{};
+  DBuf<double2> tw64;
+  DBuf<float2> tw32;
+
+  // k-points and spheres
+  int nk = 0, nb_max = 0, ncol_max = 0;
+  std::vector<KPoint> kp;
+  DBuf<int> d_nb, d_ncol, d_col_start, d_col_pq, d_col_clo;
+  DBuf<double> d_kin;
+  DBuf<double> d_vloc;             // internal layout
+  DBuf<double2> d_proj;            // [nk][natoms][nb_max]
+
+  // ground state
+  bool have_gs = false;
+  std::vector<double> eps, occ, docc;   // [nk][nbands]
+  double fermi = 0;
+  std::vector<int> nocc_k;
+  std::vector<double> gap_k;
+  DBuf<double2> d_phi;             // [nk][nbands][nb_max]
+
+  // occupied slots and tiles
+  int J = 0;
+  std::vector<int> slot_k, slot_n, slot0_k;   // slot0_k: first slot of each k
+  DBuf<int> d_slot_k, d_nocc_k, d_natoms_k;
+  std::vector<int> tile_k, tile_slot0, tile_nb;
+  DBuf<int> d_tile_k, d_tile_slot0, d_tile_nb;
+  Tiles tiles{};
+  int nocc_max = 0;
+
+  // caches
+  DBuf<double2> d_Tphi;            // [J][C][ncol_max] column transforms of occupied phi
+  DBuf<double> d_rho, d_fx, d_khat;   // internal layout
+  std::vector<double> orbnorm_k;   // ||Re F_k^-1 Phi_k||_{2,inf}
+
+  // work
+  CgWork<double> w64;
+  CgWork<float> w32;
+  DBuf<double> d_u, d_drho, d_tmpg, d_kpart, d_rhopart, d_wa, d_wb, d_multi;
+  DBuf<double2> d_kw1, d_kw2;
+  DBuf<int> d_active, d_iters, d_counters;
+  DBuf<double> d_tol2;
+  std::vector<double> knorm_hist;
+
+  std::string name;
+};
+
+// setup.cpp
+System* create_system(const ikr_system_desc* d, hipStream_t st);
+void import_ground_state(System& s, const double* eps, const double* coeffs);
+void finish_setup(System& s);
+
+// groundstate.cpp
+void compute_ground_state(System& s);
+
+// solver.cpp
+void apply_hamiltonian(System& s, int k, int nvec, const double2* x, double2* y);
+double apply_kernel(System& s, const double* v_int, double* kv_int);
+struct Chi0Result {
+  long long n_ham = 0, n_ham32 = 0, n_ham64 = 0;
+  int noconv = 0;
+};
+Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
+                               const std::vector<double>& tol_slot, int min_iter,
+                               int max_iter);
+void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext,
+                          double common, const ikr_solver_opts& o, double bnorm,
+                          ikr_stats* st);
+void solve_response(System& s, const double* b_ext, double* x_ext,
+                    const ikr_solver_opts& o, ikr_stats* st);
+
+}  // namespace ikr

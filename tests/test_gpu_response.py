@@ -1,0 +1,114 @@
+"""GPU parity of the response path against the oracle: chi0 through the
+batched Sternheimer CG (insulators, several k-points, a smeared cell with
+fractional occupations), the dielectric operator, and the full inexact
+GMRES solve against the oracle's dense LU solution of E drho = b."""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_system, rel, to_dev, to_host
+from workloads import random_field
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", ["cfg1", "small_rect", "small_metal", "tiny_k"])
+def test_chi0_matches_sum_over_states(name):
+    from oracle.response import SumOverStates, chi0_sternheimer
+    rs, osys, ogs, perms = gpu_system(name)
+    dv = random_field(osys.spec, 1)
+    got, st = rs.apply_chi0(to_dev(dv), cg_tol=1e-12)
+    got = to_host(got)
+    sos = SumOverStates(osys, ogs).apply(dv)
+    assert rel(got, sos) < 1e-9, rel(got, sos)
+    assert st["n_ham"] > 0 and st["cg_unconverged"] == 0
+    # charge conservation of the response
+    assert abs(got.sum()) < 1e-10 * np.abs(got).sum()
+
+
+@pytest.mark.parametrize("tol", [1e-3, 1e-5, 1e-7])
+def test_chi0_loose_tolerance_within_lemma_bound(tol):
+    """At a loose CG tolerance the error against the exact chi0 stays below
+    the bound of Lemma cgtol_E (unit-norm perturbation, Gamma only):
+    2 ||F^-1 Phi||_{2,inf} sqrt(N_g N_occ)/sqrt|Omega| max_n f_n tau/(e_{N+1}-e_n).
+    Iteration counts are reported next to the oracle's (parity unpinned)."""
+    from oracle.response import (Chi0Stats, SumOverStates, chi0_sternheimer,
+                                 orbital_row_norm)
+    rs, osys, ogs, perms = gpu_system("cfg1")
+    dv = random_field(osys.spec, 1)
+    got, st = rs.apply_chi0(to_dev(dv), cg_tol=tol)
+    sos = SumOverStates(osys, ogs).apply(dv)
+    nocc = ogs.nocc_k[0]
+    gap = ogs.eps[0][nocc] - ogs.eps[0][:nocc]
+    bound = 2 * orbital_row_norm(osys, ogs, 0, real_part=False) * \
+        np.sqrt(osys.ng * nocc) / np.sqrt(osys.volume) * np.max(ogs.occ[0][:nocc] * tol / gap)
+    err = np.linalg.norm(to_host(got) - sos)
+    assert err <= bound
+    ost = Chi0Stats()
+    chi0_sternheimer(osys, ogs, dv, tol, stats=ost)
+    print(f"tol {tol:g}: N_ham gpu {st['n_ham']} oracle {ost.n_ham}; err {err:.2e} bound {bound:.2e}")
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_metal"])
+def test_dielectric_matches_dense(name):
+    from oracle.response import HxcKernel, SumOverStates
+    rs, osys, ogs, perms = gpu_system(name)
+    kern = HxcKernel(osys, ogs.rho, xc=1)
+    chi = SumOverStates(osys, ogs).dense_matrix()
+    v = random_field(osys.spec, 2)
+    from paper_2505_02319_amd import default_opts
+    ev, st = rs.apply_dielectric(to_dev(v), 1e-13, default_opts(strategy="fixed"))
+    ref = v.ravel() - chi @ kern.apply(v).ravel()
+    assert rel(to_host(ev), ref) < 1e-9
+    assert abs(st["knorm_last"] - np.linalg.norm(kern.apply(v))) < 1e-10 * st["knorm_last"]
+
+
+@pytest.fixture(scope="module")
+def tiny_dense():
+    from oracle.response import HxcKernel, SumOverStates
+    rs, osys, ogs, perms = gpu_system("tiny")
+    kern = HxcKernel(osys, ogs.rho, xc=1)
+    chi = SumOverStates(osys, ogs).dense_matrix()
+    kmat = np.zeros((osys.ng, osys.ng))
+    for j in range(osys.ng):
+        e = np.zeros(osys.ng)
+        e[j] = 1
+        kmat[:, j] = kern.apply(e.reshape(osys.n)).ravel()
+    emat = np.eye(osys.ng) - chi @ kmat
+    return rs, osys, emat
+
+
+@pytest.mark.parametrize("strategy", ["agr", "bal", "grt", "D10", "D100", "D10n"])
+def test_solve_response_matches_dense_solve(tiny_dense, strategy):
+    from paper_2505_02319_amd import default_opts
+    rs, osys, emat = tiny_dense
+    b = random_field(osys.spec, 2)
+    x, st = rs.solve(to_dev(b), default_opts(strategy=strategy, tol=1e-8,
+                                             want_true_residual=1))
+    x = to_host(x).ravel()
+    tau = 1e-8 * np.linalg.norm(b)
+    true_r = np.linalg.norm(b.ravel() - emat @ x)
+    ref = np.linalg.solve(emat, b.ravel())
+    assert abs(true_r - st["true_res"]) < 1e-3 * tau + 1e-13
+    if strategy == "grt":
+        assert true_r <= tau
+    if strategy in ("bal", "grt"):
+        assert true_r <= 3 * tau
+        assert rel(x, ref) < 1e-7
+    assert st["est_res"] <= tau / 3
+    assert abs(x.sum()) < 1e-9 * np.abs(x).sum()
+
+
+def test_solve_response_cfg1_against_oracle_gmres():
+    """cfg1: the library's solve and the oracle's Alg. 1 reach the same drho
+    (both at tau = 1e-10 ||b||; a difference bounded by the conditioning)."""
+    from oracle.gmres import inexact_gmres
+    from oracle.response import HxcKernel
+    from paper_2505_02319_amd import default_opts
+    rs, osys, ogs, perms = gpu_system("cfg1")
+    kern = HxcKernel(osys, ogs.rho, xc=1)
+    b = random_field(osys.spec, 2)
+    tau = 1e-10 * np.linalg.norm(b)
+    ref = inexact_gmres(osys, ogs, kern, b, tau, strategy="grt")
+    x, st = rs.solve(to_dev(b), default_opts(strategy="grt", tol=1e-10))
+    assert rel(to_host(x), ref.x) < 1e-8
+    assert st["gmres_iters"] > 0
