@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Throughput of the inexact-GMRES Dyson solve on one MI355X.
+
+One step = one full solve of E drho = b (Alg. 1, bal strategy, tau = 1e-8 ||b||,
+m = 20, s0 = 1, x0 = 0) on the 8-atom cubic cell (a = 20.52 bohr, Ecut = 15 Ha,
+FFT 48^3, 2x2x2 k-points, 16 occupied + 4 extra bands, Hartree + Slater
+kernel), with b the seeded smooth random field.  Inputs and the ground state
+(computed by the library's own GPU eigensolver during setup) are resident in
+HBM before the timed region.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(spec, n_ham_per_solve, seconds):
+    """Oracle Sternheimer CG timed on the host: per band-iteration cost on
+    k-point 0 of the workload (a bounded sample), scaled to solves/s by the
+    Hamiltonian applications one GPU solve needs."""
+    import numpy as np
+
+    from oracle.groundstate import eigenpairs
+    from oracle.response import sternheimer_cg
+    from oracle.system import WORKERS, System
+
+    class _GS:   # the oracle's ground-state record for k-point 0 only
+        pass
+    t0 = time.perf_counter()
+    sys_ = System(spec)
+    e, v = eigenpairs(sys_, 0, spec.nbands)
+    gs = _GS()
+    gs.eps, gs.phi, gs.nocc_k = [e], [v], [spec.nocc]
+    t_gs = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    phi = v[:spec.nocc]
+    iters, t_cg, n = 0, 0.0, 0
+    while t_cg < seconds and n < spec.nocc:
+        rhs = rng.standard_normal(phi.shape[1]) + 1j * rng.standard_normal(phi.shape[1])
+        rhs -= (phi.conj() @ rhs) @ phi
+        rhs /= np.linalg.norm(rhs)
+        t1 = time.perf_counter()
+        res = sternheimer_cg(sys_, gs, 0, n, rhs, tol=0.0, maxiter=20)
+        t_cg += time.perf_counter() - t1
+        iters += res.iterations
+        n += 1
+    per_iter = t_cg / iters
+    return {"value": 1.0 / (per_iter * n_ham_per_solve), "unit": "solves/s",
+            "cores": WORKERS, "kind": "oracle",
+            "sample": (f"oracle preconditioned Sternheimer CG on k-point 0 of the workload, "
+                       f"{n} bands x 20 iterations ({iters} band-iterations, {t_cg:.1f} s; "
+                       f"k-point-0 eigensolve {t_gs:.1f} s untimed), scaled by the "
+                       f"{n_ham_per_solve:.0f} H applications of one GPU solve"),
+            "seconds_per_band_iteration": per_iter}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--strategy", default="bal")
+    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the response path here is single-GPU "
+              "(k-point sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2505_02319_amd import (ResponseSystem, default_opts, profile_enable,
+                                      profile_query, profile_reset)
+    from workloads import B_SEED, config, random_field
+
+    spec = config(args.workload)
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    rs = ResponseSystem(spec, ground_state="compute")
+    info = rs.setup_info()
+    t_setup = time.perf_counter() - t0
+    log(f"setup {spec.name}: {t_setup:.1f} s, eigensolver steps {info['gs_iters']}, "
+        f"residual {info['gs_residual']:.1e}, min gap {min(info['gaps']):.2e}")
+    b = torch.from_numpy(random_field(spec, B_SEED)).cuda()
+    opts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
+                        precision=args.precision)
+
+    for w in range(args.warmup):
+        _, st = rs.solve(b, opts)
+        log(f"warmup {w}: {st['seconds']:.3f} s, N_ham {st['n_ham']}, "
+            f"GMRES iters {st['gmres_iters']}")
+
+    profile_reset()
+    profile_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    n_ham = 0
+    gm = 0
+    for s in range(args.steps):
+        x, st = rs.solve(b, opts)
+        n_ham += st["n_ham"]
+        gm += st["gmres_iters"]
+        log(f"step {s}: {st['seconds']:.3f} s, N_ham {st['n_ham']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    profile_enable(False)
+    prof = profile_query()
+
+    # accuracy of the returned solution (untimed): true residual with tight CG
+    vopts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
+                         precision=args.precision, want_true_residual=1)
+    _, vst = rs.solve(b, vopts)
+    bnorm = float(torch.linalg.norm(b))
+    true_rel = vst["true_res"] / bnorm
+    log(f"true relative residual {true_rel:.2e}")
+
+    dom = max(prof, key=lambda k: prof[k][1])
+    launches, ms, by = prof[dom]
+    achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
+                   "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+               for k, v in prof.items()}
+    value = args.steps / elapsed
+    out = {
+        "metric": "drho solves/s at rel. res 1e-8",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": f"{spec.name}: 8-atom cubic cell a=20.52 bohr, Ecut 15 Ha, "
+                               f"FFT 48^3, 2x2x2 k, 16+4 bands, K_H + Slater, "
+                               f"strategy {args.strategy}, m 20, tau 1e-8||b||",
+                   "global_batch": 1, "parallelism": "single-gpu"},
+        "hpsi_band_applies_per_s": n_ham / elapsed,
+        "n_ham_per_solve": n_ham / args.steps,
+        "gmres_iters_per_solve": gm / args.steps,
+        "true_rel_residual": true_rel,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "avg_launch_us": 1e3 * ms / max(launches, 1),
+                     "bytes_per_launch": by / max(launches, 1)},
+        "kernels": kernels,
+        "setup_seconds": t_setup,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(spec, n_ham / args.steps, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    rs.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -157,6 +157,13 @@ ikr_status ikr_get_ground_state(ikr_handle h, double* eps_host,
                                 double* occ_host, double* coeffs_host,
                                 double* fermi_host);
 
+/* Setup diagnostics (host): gaps_host [nk] = e_{Nocc,k + 1} - e_{Nocc,k}
+ * (NaN where every computed band is occupied), the number of outer steps of
+ * the library's eigensolver (0 for an imported ground state) and the largest
+ * eigen-residual norm ||H phi - e phi|| it reached.  Any pointer may be NULL. */
+ikr_status ikr_get_setup_info(ikr_handle h, double* gaps_host, int* gs_iters,
+                              double* gs_residual);
+
 /* Ground-state density on the grid (device, C order). */
 ikr_status ikr_get_density(ikr_handle h, double* rho_dev);
 
@@ -189,6 +196,18 @@ ikr_status ikr_apply_dielectric(ikr_handle h, const double* v_dev,
 ikr_status ikr_solve_response(ikr_handle h, const double* b_dev,
                               double* drho_dev, const ikr_solver_opts* opts,
                               ikr_stats* stats);
+
+/* Opt-in kernel timing (process-wide).  When enabled, the hot kernels of the
+ * Sternheimer CG are bracketed by HIP events on the launching stream and
+ * each launch carries its algorithmic byte count (bytes the kernel must move
+ * to or from HBM by its definition, not by measurement).  kernel_id indexes
+ * ikr_profile_kernel_name (0 .. ikr_profile_kernel_count()-1). */
+ikr_status ikr_profile_enable(int on);
+ikr_status ikr_profile_reset(void);
+int ikr_profile_kernel_count(void);
+const char* ikr_profile_kernel_name(int kernel_id);
+ikr_status ikr_profile_query(int kernel_id, long long* launches, double* total_ms,
+                             double* total_bytes);
 
 const char* ikr_last_error(void);
 void ikr_destroy(ikr_handle h);

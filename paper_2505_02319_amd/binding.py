@@ -75,6 +75,8 @@ SIGNATURES = {
     "ikr_get_basis": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
     "ikr_get_ground_state": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "ikr_get_setup_info": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_double)]),
     "ikr_get_density": (C.c_int, [_VP, _VP]),
     "ikr_apply_hamiltonian": (C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "ikr_apply_hxc_kernel": (C.c_int, [_VP, _VP, _VP]),
@@ -83,6 +85,12 @@ SIGNATURES = {
     "ikr_apply_dielectric": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(SolverOpts),
                                        C.POINTER(Stats)]),
     "ikr_solve_response": (C.c_int, [_VP, _VP, _VP, C.POINTER(SolverOpts), C.POINTER(Stats)]),
+    "ikr_profile_enable": (C.c_int, [C.c_int]),
+    "ikr_profile_reset": (C.c_int, []),
+    "ikr_profile_kernel_count": (C.c_int, []),
+    "ikr_profile_kernel_name": (C.c_char_p, [C.c_int]),
+    "ikr_profile_query": (C.c_int, [C.c_int, C.POINTER(C.c_longlong), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double)]),
     "ikr_last_error": (C.c_char_p, []),
     "ikr_destroy": (None, [_VP]),
 }
@@ -118,6 +126,25 @@ def default_opts(**kw) -> SolverOpts:
             val = STRATEGY[val]
         setattr(o, key, val)
     return o
+
+
+def profile_enable(on: bool = True):
+    _check(lib().ikr_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().ikr_profile_reset())
+
+
+def profile_query():
+    """{kernel name: (launches, total_ms, total_algorithmic_bytes)}"""
+    L = lib()
+    out = {}
+    for i in range(L.ikr_profile_kernel_count()):
+        n, ms, by = C.c_longlong(), C.c_double(), C.c_double()
+        _check(L.ikr_profile_query(i, C.byref(n), C.byref(ms), C.byref(by)))
+        out[L.ikr_profile_kernel_name(i).decode()] = (n.value, ms.value, by.value)
+    return out
 
 
 def _dptr(a: np.ndarray):
@@ -225,6 +252,14 @@ class ResponseSystem:
                                           cf.ctypes.data_as(C.POINTER(C.c_double)),
                                           C.byref(fermi)))
         return eps, occ, cf, fermi.value
+
+    def setup_info(self):
+        inf = self.info()
+        gaps = np.zeros(inf.nk)
+        it = C.c_int()
+        res = C.c_double()
+        _check(lib().ikr_get_setup_info(self.h, _dptr(gaps), C.byref(it), C.byref(res)))
+        return {"gaps": gaps, "gs_iters": it.value, "gs_residual": res.value}
 
     # ------------------------------------------------------------ operators
     def _grid(self, t):

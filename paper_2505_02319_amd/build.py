@@ -15,7 +15,8 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libikr.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["fft.hip", "blas.hip", "setup.cpp", "groundstate.cpp", "solver.cpp", "api.cpp"]
+SOURCES = ["fft.hip", "blas.hip", "setup.cpp", "groundstate.cpp", "solver.cpp", "ktimer.cpp",
+           "api.cpp"]
 
 FLAGS = [
     "-std=c++17", "-O3", "-fPIC", "--offload-arch=gfx950",

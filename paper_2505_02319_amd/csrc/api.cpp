@@ -5,6 +5,7 @@
 #include <cstring>
 #include <string>
 
+#include "ktimer.h"
 #include "system.h"
 
 using ikr::Error;
@@ -144,6 +145,17 @@ ikr_status ikr_get_ground_state(ikr_handle h, double* eps_host, double* occ_host
   });
 }
 
+ikr_status ikr_get_setup_info(ikr_handle h, double* gaps_host, int* gs_iters,
+                              double* gs_residual) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    if (gaps_host) std::memcpy(gaps_host, s->gap_k.data(), s->gap_k.size() * sizeof(double));
+    if (gs_iters) *gs_iters = s->gs_outer_iters;
+    if (gs_residual) *gs_residual = s->gs_residual;
+  });
+}
+
 ikr_status ikr_get_density(ikr_handle h, double* rho_dev) {
   return guarded([&] {
     System* s = sys_of(h);
@@ -236,6 +248,26 @@ ikr_status ikr_solve_response(ikr_handle h, const double* b_dev, double* drho_de
       throw;
     }
     if (stats) *stats = local;
+  });
+}
+
+ikr_status ikr_profile_enable(int on) {
+  return guarded([&] { ikr::KTimer::enable(on != 0); });
+}
+
+ikr_status ikr_profile_reset(void) {
+  return guarded([&] { ikr::KTimer::reset(); });
+}
+
+int ikr_profile_kernel_count(void) { return ikr::K_COUNT; }
+
+const char* ikr_profile_kernel_name(int kernel_id) { return ikr::kernel_name(kernel_id); }
+
+ikr_status ikr_profile_query(int kernel_id, long long* launches, double* total_ms,
+                             double* total_bytes) {
+  return guarded([&] {
+    IKR_CHECK(kernel_id >= 0 && kernel_id < ikr::K_COUNT, IKR_E_ARG, "kernel id out of range");
+    ikr::KTimer::query(kernel_id, launches, total_ms, total_bytes);
   });
 }
 

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(NT) void update_kernel(
     R d = 0;
     if (on && g < n) {
       cplx<R>* yp = Y + (size_t)slot * y_stride + g;
-      cplx<R> y = *yp;
+      cplx<R> y = a != R(0) ? *yp : mk<R>(0, 0);     // a = 0: Y is write-only
       y = mk<R>(a * y.x + acc[b].x, a * y.y + acc[b].y);
       *yp = y;
       if (D) {
@@ -306,6 +306,45 @@ __global__ void scale_copy_kernel(size_t n, const double* __restrict__ x, double
   if (i < n) y[i] = a * x[i];
 }
 
+// X = alpha[slot] * Z + beta[slot] * X  over the sphere of each slot
+__global__ __launch_bounds__(NT) void cheb_combine_kernel(
+    int nb_max, const int* __restrict__ slot_k, const int* __restrict__ nb,
+    const double2* __restrict__ Z, double2* __restrict__ X, const double* __restrict__ alpha,
+    const double* __restrict__ beta) {
+  const int slot = blockIdx.y;
+  const int g = blockIdx.x * NT + threadIdx.x;
+  if (g >= nb[slot_k[slot]]) return;
+  const size_t o = (size_t)slot * nb_max + g;
+  const double a = alpha[slot], b = beta[slot];
+  const double2 z = Z[o], x = X[o];
+  X[o] = mk<double>(a * z.x + b * x.x, a * z.y + b * x.y);
+}
+
+// partial |HX - lam X|^2 per (slot, block)
+__global__ __launch_bounds__(NT) void resid_kernel(
+    int nb_max, const int* __restrict__ slot_k, const int* __restrict__ nb,
+    const double2* __restrict__ HX, const double2* __restrict__ X,
+    const double* __restrict__ lam, double* __restrict__ part) {
+  __shared__ double red[NT];
+  const int slot = blockIdx.y, tid = threadIdx.x;
+  const int g = blockIdx.x * NT + tid;
+  double s = 0;
+  if (g < nb[slot_k[slot]]) {
+    const size_t o = (size_t)slot * nb_max + g;
+    const double l = lam[slot];
+    const double2 h = HX[o], x = X[o];
+    const double rx = h.x - l * x.x, ry = h.y - l * x.y;
+    s = rx * rx + ry * ry;
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int q = NT / 2; q > 0; q >>= 1) {
+    if (tid < q) red[tid] += red[tid + q];
+    __syncthreads();
+  }
+  if (tid == 0) part[(size_t)slot * gridDim.x + blockIdx.x] = red[0];
+}
+
 template <typename R>
 __global__ void cscale_kernel(size_t n, cplx<R>* __restrict__ x, R a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -435,6 +474,20 @@ void multiaxpy(int n, int nv, const double* V, size_t vstride, const double* c, 
 
 void scale_copy(size_t n, const double* x, double a, double* y, hipStream_t st) {
   hipLaunchKernelGGL(scale_copy_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, x, a, y);
+  IKR_HIP(hipGetLastError());
+}
+
+void cheb_combine(int nslots, int nb_max, const int* slot_k, const int* nb, const double2* Z,
+                  double2* X, const double* alpha, const double* beta, hipStream_t st) {
+  hipLaunchKernelGGL(cheb_combine_kernel, dim3(vec_nblocks(nb_max), nslots), dim3(NT), 0, st,
+                     nb_max, slot_k, nb, Z, X, alpha, beta);
+  IKR_HIP(hipGetLastError());
+}
+
+void resid_norms(int nslots, int nb_max, const int* slot_k, const int* nb, const double2* HX,
+                 const double2* X, const double* lam, double* part, hipStream_t st) {
+  hipLaunchKernelGGL(resid_kernel, dim3(vec_nblocks(nb_max), nslots), dim3(NT), 0, st, nb_max,
+                     slot_k, nb, HX, X, lam, part);
   IKR_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,33 @@
+// Opt-in per-kernel timing with HIP events on the launching stream.
+// When enabled, begin()/end() bracket a launch with two events and attach
+// the launch's algorithmic byte count; query() resolves the pending events.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ikr {
+
+enum KernelId : int {
+  K_COL_INV = 0,    // sphere -> column transforms (with fused p update)
+  K_PLANE_HV = 1,   // plane 2D FFT pair with the local-potential multiply
+  K_COL_FWD = 2,    // column forward transforms -> sphere, H epilogue
+  K_GRAM = 3,       // projection coefficients W^H X
+  K_UPDATE = 4,     // projection updates X + W C (with dot partials)
+  K_CG_STEP = 5,    // fused CG vector update
+  K_PLANE_RHO = 6,  // density accumulation
+  K_COUNT = 7
+};
+
+const char* kernel_name(int id);
+
+struct KTimer {
+  static void enable(bool on);
+  static bool enabled();
+  static void begin(int id, hipStream_t st);
+  static void end(int id, hipStream_t st, double bytes);
+  // launches, total milliseconds and total algorithmic bytes since reset
+  static void query(int id, long long* launches, double* ms, double* bytes);
+  static void reset();
+};
+
+}  // namespace ikr

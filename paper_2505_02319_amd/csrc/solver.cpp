@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 
+#include "ktimer.h"
 #include "system.h"
 
 namespace ikr {
@@ -225,38 +226,73 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
                  w.r.get(), w.dpart.get(), st);
   cg_scalars<double>(J, nup, w.dpart.get(), 2, s.d_active.get(), cs, 1, st);
 
+  // Algorithmic bytes per band (FP64 complex = 16 B) for the kernel timer:
+  // mean sphere size and footprint over the slots.
+  double nb_avg = 0, ncol_avg = 0;
+  for (int j = 0; j < J; ++j) {
+    nb_avg += s.kp[s.slot_k[j]].nb;
+    ncol_avg += s.kp[s.slot_k[j]].ncol;
+  }
+  nb_avg /= J;
+  ncol_avg /= J;
+  const double S16 = 16.0, colC = ncol_avg * s.L.C;
+  const double ntiles = s.tiles.n;
+  auto tile_bytes = [&](double M, bool upd, bool dot) {
+    // W read once per tile, X read (gram) or Y read+write (+ D read) per slot
+    return ntiles * M * nb_avg * S16 + J * nb_avg * S16 * (upd ? (dot ? 3.0 : 2.0) : 1.0);
+  };
   int nact = J;
   for (int it = 0; it < max_iter && nact > 0; ++it) {
     // p = z + beta p ; w = (H - e) p  (local part through the pruned FFT)
+    KTimer::begin(K_COL_INV, st);
     launch_col_inv<double>(s.geom, s.fft, act, w.p.get(), nbm, w.T1.get(), w.w.get(),
                            w.beta.get(), w.p.get(), st);
+    KTimer::end(K_COL_INV, st, nact * (3.0 * nb_avg + colC) * S16);
+    KTimer::begin(K_PLANE_HV, st);
     launch_plane_hv<double>(s.geom, s.fft, act, w.T1.get(), w.T2.get(), s.d_vloc.get(), 0, st);
+    KTimer::end(K_PLANE_HV, st, nact * 2.0 * colC * S16 + 8.0 * s.ng);
+    KTimer::begin(K_COL_FWD, st);
     launch_col_fwd<double>(s.geom, s.fft, act, w.T2.get(), w.w.get(), nbm, w.p.get(),
                            w.shift.get(), inv_ng, st);
+    KTimer::end(K_COL_FWD, st, nact * (colC * S16 + nb_avg * (2.0 * S16 + 8.0)));
     if (s.natoms > 0) {
+      KTimer::begin(K_GRAM, st);
       gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
                    (size_t)s.natoms * nbm, nbm, w.p.get(), nbm, w.part.get(), w.coefB.get(),
                    MAXM, st);
+      KTimer::end(K_GRAM, st, tile_bytes(s.natoms, false, false));
+      KTimer::begin(K_UPDATE, st);
       update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, projB,
                      none, nullptr, nullptr, st);
+      KTimer::end(K_UPDATE, st, tile_bytes(s.natoms, true, false));
     }
     // Ap = Q w ; pAp
+    KTimer::begin(K_GRAM, st);
     gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
                  nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+    KTimer::end(K_GRAM, st, tile_bytes(s.nocc_max, false, false));
+    KTimer::begin(K_UPDATE, st);
     update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
                    none, w.p.get(), w.dpart.get(), st);
+    KTimer::end(K_UPDATE, st, tile_bytes(s.nocc_max, true, true));
     cg_scalars<double>(J, nup, w.dpart.get(), 0, s.d_active.get(), cs, 0, st);
     // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, convergence
+    KTimer::begin(K_CG_STEP, st);
     cg_step<double>(J, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, s.d_active.get(),
                     w.alpha.get(), w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(),
                     w.dpart.get(), st);
+    KTimer::end(K_CG_STEP, st, nact * nb_avg * (7.0 * S16 + 8.0));
     IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, sizeof(int), st));
     cg_scalars<double>(J, nvb, w.dpart.get(), 1, s.d_active.get(), cs, 0, st);
     // z = Q M^-1 r, rz = <r, z>, beta
+    KTimer::begin(K_GRAM, st);
     gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
                  nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+    KTimer::end(K_GRAM, st, tile_bytes(s.nocc_max, false, false));
+    KTimer::begin(K_UPDATE, st);
     update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
                    none, w.r.get(), w.dpart.get(), st);
+    KTimer::end(K_UPDATE, st, tile_bytes(s.nocc_max, true, true));
     cg_scalars<double>(J, nup, w.dpart.get(), 2, s.d_active.get(), cs, 0, st);
     res.n_ham += nact;
     int cnt = 0;
@@ -291,8 +327,10 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   IKR_HIP(hipMemcpyAsync(s.d_wa.get(), wa.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
   IKR_HIP(hipMemcpyAsync(s.d_wb.get(), wb.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
   const int gsz = 8;
+  KTimer::begin(K_PLANE_RHO, st);
   launch_plane_rho(s.geom, s.fft, J, s.d_slot_k.get(), s.d_Tphi.get(), w.T1.get(), s.d_wa.get(),
                    s.d_wb.get(), gsz, s.d_rhopart.get(), st);
+  KTimer::end(K_PLANE_RHO, st, J * 2.0 * colC * S16 + (J + gsz - 1) / gsz * 8.0 * s.ng);
   sum_groups(s.ng, (J + gsz - 1) / gsz, s.d_rhopart.get(), 1.0, drho_int, st);
   IKR_HIP(hipStreamSynchronize(st));
   return res;

@@ -83,6 +83,8 @@ struct System {
 
   // ground state
   bool have_gs = false;
+  int gs_outer_iters = 0;          // eigensolver outer steps (0 if imported)
+  double gs_residual = 0;          // largest eigen-residual norm at exit
   std::vector<double> eps, occ, docc;   // [nk][nbands]
   double fermi = 0;
   std::vector<int> nocc_k;
