@@ -50,10 +50,14 @@ typedef enum {
 
 /* CG-tolerance strategies: paper Table 1 (agr, bal, grt and the baselines
  * D10, D100, D10n) in the k-point form of Table strategies_k.  IKR_FIXED
- * applies the common factor unchanged to every band. */
+ * applies the common factor unchanged to every band.  IKR_THM2 is the
+ * prefactor C_{i,nk} of Theorem 2 itself (k-point form of the supplement:
+ * gap e_{Nocc,k + 1} - e_{nk}, ||K v_i||, the full ||F_k^-1 Phi_k||_{2,inf},
+ * N_mp sqrt(N_g Nocc,k)), i.e. the guarantee without the approximations
+ * behind grt. */
 typedef enum {
   IKR_AGR = 0, IKR_BAL = 1, IKR_GRT = 2, IKR_D10 = 3, IKR_D100 = 4,
-  IKR_D10N = 5, IKR_FIXED = 6
+  IKR_D10N = 5, IKR_FIXED = 6, IKR_THM2 = 7
 } ikr_strategy;
 
 /* Model system (host memory, read during ikr_setup_system only).

@@ -29,12 +29,13 @@ from .response import (Chi0Stats, HxcKernel, apply_dielectric,
                        orbital_row_norm)
 from .system import System
 
-STRATEGIES = ("agr", "bal", "grt", "D10", "D100", "D10n")
+STRATEGIES = ("agr", "bal", "grt", "D10", "D100", "D10n", "thm2")
 
 
 def strategy_prefactors(sys: System, gs: GroundState, strategy: str,
                         knorm: float, bnorm: float,
-                        orb_norms: Optional[List[float]] = None):
+                        orb_norms: Optional[List[float]] = None,
+                        orb_full: Optional[List[float]] = None):
     """Per-(k, n) prefactor of Table 1 / Table strategies_k.
 
     The CG tolerance is prefactor x common factor, the common factor being
@@ -57,6 +58,15 @@ def strategy_prefactors(sys: System, gs: GroundState, strategy: str,
             on = orb_norms[ik]
             p = np.sqrt(omega) / (2.0 * f * wk * np.sqrt(ng) *
                                   np.sqrt(nocc_tot) * knorm * on)
+        elif strategy == "thm2":
+            # C_{i,nk} of Theorem 2, k-point form (supplement on perfect
+            # crystals): gap to the first unoccupied band, the full orbital
+            # row norm, N_mp sqrt(N_g N_occ,k)
+            eps = gs.eps[ik]
+            eup = eps[nocc] if nocc < len(eps) else eps[-1]
+            gap = eup - eps[:nocc] if nocc < len(eps) else np.maximum(eup - eps[:nocc], 1e-4)
+            p = np.sqrt(omega) * gap / (2.0 * f * wk * knorm * orb_full[ik] *
+                                         len(sys.bases) * np.sqrt(ng * nocc))
         elif strategy == "D10":
             p = np.full(nocc, 0.1)
         elif strategy == "D100":
@@ -96,6 +106,8 @@ def inexact_gmres(sys: System, gs: GroundState, kern: HxcKernel,
     s = float(s0)
     orb = [orbital_row_norm(sys, gs, ik) for ik in range(len(sys.bases))] \
         if strategy == "grt" else None
+    orb_full = [orbital_row_norm(sys, gs, ik, real_part=False)
+                for ik in range(len(sys.bases))] if strategy == "thm2" else None
     stats = Chi0Stats()
     history = []
     adaptive = strategy in ("agr", "bal", "grt")
@@ -103,7 +115,7 @@ def inexact_gmres(sys: System, gs: GroundState, kern: HxcKernel,
 
     def eop(v, common):
         def tol_fn(knorm):
-            pref = strategy_prefactors(sys, gs, strategy, knorm, bnorm, orb)
+            pref = strategy_prefactors(sys, gs, strategy, knorm, bnorm, orb, orb_full)
             return [p * common for p in pref]
         ev, _ = apply_dielectric(sys, gs, kern, v.reshape(shape), tol_fn,
                                  stats=stats)

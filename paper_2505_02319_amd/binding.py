@@ -17,9 +17,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libikr.so")
 
-IKR_AGR, IKR_BAL, IKR_GRT, IKR_D10, IKR_D100, IKR_D10N, IKR_FIXED = range(7)
+IKR_AGR, IKR_BAL, IKR_GRT, IKR_D10, IKR_D100, IKR_D10N, IKR_FIXED, IKR_THM2 = range(8)
 STRATEGY = {"agr": IKR_AGR, "bal": IKR_BAL, "grt": IKR_GRT, "D10": IKR_D10,
-            "D100": IKR_D100, "D10n": IKR_D10N, "fixed": IKR_FIXED}
+            "D100": IKR_D100, "D10n": IKR_D10N, "fixed": IKR_FIXED, "thm2": IKR_THM2}
 STATUS = {0: "OK", 1: "E_ARG", 2: "E_STATE", 3: "E_NOGAP", 4: "E_NOCONV",
           5: "E_NAN", 6: "E_OOM", 7: "E_HIP", 8: "E_INTERNAL"}
 

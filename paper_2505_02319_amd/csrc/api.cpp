@@ -42,7 +42,7 @@ System* sys_of(ikr_handle h) {
 
 void check_opts(const ikr_solver_opts* o) {
   IKR_CHECK(o, IKR_E_ARG, "null solver options");
-  IKR_CHECK(o->strategy >= IKR_AGR && o->strategy <= IKR_FIXED, IKR_E_ARG, "bad strategy");
+  IKR_CHECK(o->strategy >= IKR_AGR && o->strategy <= IKR_THM2, IKR_E_ARG, "bad strategy");
   IKR_CHECK(o->tol > 0 && std::isfinite(o->tol), IKR_E_ARG, "tolerance must be positive");
   IKR_CHECK(o->restart_m >= 1 && o->restart_m <= 60, IKR_E_ARG, "restart size must be in [1, 60]");
   IKR_CHECK(o->cg_min_iter >= 0 && o->cg_max_iter >= 1, IKR_E_ARG, "bad CG iteration limits");

@@ -53,7 +53,8 @@ int multidot_nblocks(int n);
 template <typename R>
 void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
           const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
-          int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st);
+          int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st,
+          const int* active = nullptr);
 
 template <typename R>
 void update(const Tiles& tl, const int* nb, int nb_max, const int* active,

@@ -18,15 +18,31 @@ constexpr int MT = 16;        // projector rows per gram pass
 
 // part[((t * nsc + sc) * Mmax + m) * BT + b] = sum_{g in super-chunk}
 //                                 conj(W[k][m][g]) X[slot0 + b][g]
+// True when some slot of tile t takes part (active == null: all do).
+__device__ __forceinline__ bool tile_live(const Tiles& tl, int t, const int* active) {
+  if (!active) return true;
+  const int s0 = tl.slot0[t], nbt = tl.nb[t];
+  bool any = false;
+  for (int b = 0; b < nbt; ++b) any |= active[s0 + b] != 0;
+  return any;
+}
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
 template <typename R>
 __global__ __launch_bounds__(NT) void gram_kernel(
     Tiles tl, const int* __restrict__ nb, const int* __restrict__ Mk, int Mmax,
     const cplx<R>* __restrict__ W, size_t wk_stride, int w_stride,
     const cplx<R>* __restrict__ X, int x_stride, int nsc, int sc_len,
-    cplx<R>* __restrict__ part) {
+    cplx<R>* __restrict__ part, const int* __restrict__ active) {
   __shared__ cplx<R> Xs[BT][CH + 1];
   __shared__ cplx<R> Ws[MT][CH + 1];
   const int t = blockIdx.y, sc = blockIdx.x, tid = threadIdx.x;
+  if (!tile_live(tl, t, active)) return;
   const int k = tl.k[t], s0 = tl.slot0[t], nbt = tl.nb[t];
   const int M = Mk[k], n = nb[k];
   const int i_out = tid / BT, b_out = tid % BT;
@@ -57,24 +73,30 @@ __global__ __launch_bounds__(NT) void gram_kernel(
   }
 }
 
-// coef[(slot0 + b) * cstride + m] = sum_sc part[...]  (fixed order)
+// coef[(slot0 + b) * cstride + m] = sum_sc part[...]: one wavefront per
+// output, lanes take super-chunks lane, lane + 64, ... (fixed order), then
+// a fixed shuffle tree.
 template <typename R>
-__global__ void gram_reduce_kernel(Tiles tl, const int* __restrict__ Mk, int Mmax,
-                                   int nsc, const cplx<R>* __restrict__ part,
-                                   cplx<R>* __restrict__ coef, int cstride) {
+__global__ __launch_bounds__(NT) void gram_reduce_kernel(
+    Tiles tl, const int* __restrict__ Mk, int Mmax, int nsc,
+    const cplx<R>* __restrict__ part, cplx<R>* __restrict__ coef, int cstride,
+    const int* __restrict__ active) {
   const int t = blockIdx.x;
+  if (!tile_live(tl, t, active)) return;
   const int k = tl.k[t], s0 = tl.slot0[t], nbt = tl.nb[t], M = Mk[k];
-  for (int i = threadIdx.x; i < Mmax * BT; i += blockDim.x) {
-    const int m = i / BT, b = i % BT;
-    if (m >= M || b >= nbt) continue;
-    cplx<R> acc = mk<R>(0, 0);
-    for (int sc = 0; sc < nsc; ++sc) {
-      const cplx<R> v = part[(((size_t)t * nsc + sc) * Mmax + m) * BT + b];
-      acc.x += v.x;
-      acc.y += v.y;
-    }
-    coef[(size_t)(s0 + b) * cstride + m] = acc;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int o = blockIdx.y * (NT / 64) + wave;
+  const int m = o / BT, b = o % BT;
+  if (m >= M || b >= nbt) return;
+  R sx = 0, sy = 0;
+  for (int sc = lane; sc < nsc; sc += 64) {
+    const cplx<R> v = part[(((size_t)t * nsc + sc) * Mmax + m) * BT + b];
+    sx += v.x;
+    sy += v.y;
   }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  if (lane == 0) coef[(size_t)(s0 + b) * cstride + m] = mk<R>(sx, sy);
 }
 
 // Y[slot][g] = a * Y[slot][g] + sum_j alpha_j sum_m W_j[k][m][g] coef_j[slot][m]
@@ -93,6 +115,7 @@ __global__ __launch_bounds__(NT) void update_kernel(
   __shared__ cplx<R> c2[BT][MAXM];
   __shared__ R red[NT];
   const int t = blockIdx.y, tid = threadIdx.x;
+  if (!tile_live(tl, t, active)) return;
   const int k = tl.k[t], s0 = tl.slot0[t], nbt = tl.nb[t];
   const int n = nb[k];
   const int M1 = W1 ? M1k[k] : 0, M2 = W2 ? M2k[k] : 0;
@@ -203,15 +226,23 @@ __global__ __launch_bounds__(NT) void precond_kernel(
 // op 0: pAp -> alpha = rz / pAp (0 if pAp == 0)
 // op 1: rnorm2 -> iteration count, convergence flags, active counter
 // op 2: rz_new -> beta = rz_new / rz, rz = rz_new  (start: beta = 0, rz = rz_new)
+// One wavefront per slot: lanes sum partials lane, lane + 64, ... then a
+// fixed shuffle tree.  op 0 also clears the active counter that op 1 of the
+// same iteration increments.
 template <typename R>
-__global__ void cg_scalar_kernel(int nslots, int nparts, const R* __restrict__ part,
-                                 int op, int* __restrict__ active,
-                                 CgScalars<R> cs, int start) {
-  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(NT) void cg_scalar_kernel(int nslots, int nparts,
+                                                      const R* __restrict__ part, int op,
+                                                      int* __restrict__ active,
+                                                      CgScalars<R> cs, int start) {
+  if (op == 0 && blockIdx.x == 0 && threadIdx.x == 0) *cs.nactive = 0;
+  const int slot = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (slot >= nslots) return;
-  if (active && !active[slot] && op != 3) return;
+  if (active && !active[slot]) return;
   R s = 0;
-  for (int i = 0; i < nparts; ++i) s += part[(size_t)slot * nparts + i];
+  for (int i = lane; i < nparts; i += 64) s += part[(size_t)slot * nparts + i];
+  s = wave_sum(s);
+  if (lane != 0) return;
   if (op == 0) {
     cs.alpha[slot] = s != R(0) ? cs.rz[slot] / s : R(0);
   } else if (op == 1) {
@@ -372,17 +403,20 @@ size_t gram_part_elems(int ntiles, int nb_max, int Mmax) {
 template <typename R>
 void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
           const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
-          int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st) {
+          int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st,
+          const int* active) {
   IKR_CHECK(Mmax <= MAXM, 1, "too many projector rows");
   IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Mk && W && X && part && coef, 8,
             "gram: null device pointer");
   int sc_len;
   const int nsc = nsc_for(nb_max, sc_len);
   hipLaunchKernelGGL((gram_kernel<R>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, Mk,
-                     Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part);
+                     Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part, active);
   IKR_HIP(hipGetLastError());
-  hipLaunchKernelGGL((gram_reduce_kernel<R>), dim3(tl.n), dim3(256), 0, st, tl, Mk, Mmax,
-                     nsc, part, coef, cstride);
+  const int outs_per_block = NT / 64;
+  hipLaunchKernelGGL((gram_reduce_kernel<R>),
+                     dim3(tl.n, (Mmax * BT + outs_per_block - 1) / outs_per_block), dim3(NT),
+                     0, st, tl, Mk, Mmax, nsc, part, coef, cstride, active);
   IKR_HIP(hipGetLastError());
 }
 
@@ -425,8 +459,9 @@ void precond(int nslots, const int* slot_k, const int* nb, const double* kin, in
 template <typename R>
 void cg_scalars(int nslots, int nparts, const R* part, int op, int* active,
                 const CgScalars<R>& cs, int start, hipStream_t st) {
-  hipLaunchKernelGGL((cg_scalar_kernel<R>), dim3((nslots + 127) / 128), dim3(128), 0, st,
-                     nslots, nparts, part, op, active, cs, start);
+  const int per_block = NT / 64;
+  hipLaunchKernelGGL((cg_scalar_kernel<R>), dim3((nslots + per_block - 1) / per_block),
+                     dim3(NT), 0, st, nslots, nparts, part, op, active, cs, start);
   IKR_HIP(hipGetLastError());
 }
 
@@ -500,7 +535,7 @@ void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st) {
 #define IKR_INST(R)                                                                       \
   template void gram<R>(const Tiles&, const int*, int, const int*, int, const cplx<R>*,   \
                         size_t, int, const cplx<R>*, int, cplx<R>*, cplx<R>*, int,        \
-                        hipStream_t);                                                     \
+                        hipStream_t, const int*);                                         \
   template void update<R>(const Tiles&, const int*, int, const int*, cplx<R>*, int, R,    \
                           const UpdTerm<R>&, const UpdTerm<R>&, const cplx<R>*, R*,       \
                           hipStream_t);                                                   \

@@ -455,6 +455,7 @@ void finish_setup(System& s) {
   // -- ||Re F_k^-1 Phi_k||_{2,inf} per k (grt strategy)
   {
     s.orbnorm_k.assign(nk, 0.0);
+    s.orbnorm_full_k.assign(nk, 0.0);
     DBuf<double2> grid;
     int maxo = s.nocc_max;
     grid.alloc((size_t)maxo * s.ng);
@@ -466,16 +467,19 @@ void finish_setup(System& s) {
       IKR_HIP(hipMemcpyAsync(hg.data(), grid.get(), (size_t)no * s.ng * sizeof(double2),
                              hipMemcpyDeviceToHost, st));
       IKR_HIP(hipStreamSynchronize(st));
-      double mx = 0;
+      double mx = 0, mxf = 0;
       for (int i = 0; i < s.ng; ++i) {
-        double acc = 0;
+        double acc = 0, accf = 0;
         for (int n = 0; n < no; ++n) {
-          const double re = hg[(size_t)n * s.ng + i].x;
-          acc += re * re;
+          const double2 v = hg[(size_t)n * s.ng + i];
+          acc += v.x * v.x;
+          accf += v.x * v.x + v.y * v.y;
         }
         mx = std::max(mx, acc);
+        mxf = std::max(mxf, accf);
       }
       s.orbnorm_k[k] = std::sqrt(mx / s.volume);
+      s.orbnorm_full_k[k] = std::sqrt(mxf / s.volume);
     }
   }
   IKR_HIP(hipStreamSynchronize(st));

@@ -259,7 +259,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
       KTimer::begin(K_GRAM, st);
       gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
                    (size_t)s.natoms * nbm, nbm, w.p.get(), nbm, w.part.get(), w.coefB.get(),
-                   MAXM, st);
+                   MAXM, st, s.d_active.get());
       KTimer::end(K_GRAM, st, tile_bytes(s.natoms, false, false));
       KTimer::begin(K_UPDATE, st);
       update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, projB,
@@ -269,7 +269,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     // Ap = Q w ; pAp
     KTimer::begin(K_GRAM, st);
     gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
-                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st, s.d_active.get());
     KTimer::end(K_GRAM, st, tile_bytes(s.nocc_max, false, false));
     KTimer::begin(K_UPDATE, st);
     update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
@@ -282,12 +282,11 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
                     w.alpha.get(), w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(),
                     w.dpart.get(), st);
     KTimer::end(K_CG_STEP, st, nact * nb_avg * (7.0 * S16 + 8.0));
-    IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, sizeof(int), st));
     cg_scalars<double>(J, nvb, w.dpart.get(), 1, s.d_active.get(), cs, 0, st);
     // z = Q M^-1 r, rz = <r, z>, beta
     KTimer::begin(K_GRAM, st);
     gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
-                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st, s.d_active.get());
     KTimer::end(K_GRAM, st, tile_bytes(s.nocc_max, false, false));
     KTimer::begin(K_UPDATE, st);
     update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
@@ -354,6 +353,19 @@ static std::vector<double> prefactors(const System& s, int strategy, double knor
         p[j] = std::sqrt(s.volume) / (2.0 * f * wk * std::sqrt((double)s.ng) *
                                       std::sqrt(nocc_tot) * knorm * s.orbnorm_k[k]);
         break;
+      case IKR_THM2: {
+        // C_{i,nk} of Theorem 2 in its k-point form; where every computed band
+        // is occupied the gap is taken to the highest computed band (>= 1e-4 Ha)
+        const int n = s.slot_n[j], no = s.nocc_k[k];
+        const double en = s.eps[(size_t)k * s.nbands + n];
+        const double eup = no < s.nbands ? s.eps[(size_t)k * s.nbands + no]
+                                         : s.eps[(size_t)k * s.nbands + s.nbands - 1];
+        const double gap = std::max(eup - en, no < s.nbands ? 0.0 : 1e-4);
+        p[j] = std::sqrt(s.volume) * gap /
+               (2.0 * f * wk * knorm * s.orbnorm_full_k[k] * s.nk *
+                std::sqrt((double)s.ng * no));
+        break;
+      }
       case IKR_D10: p[j] = 0.1; break;
       case IKR_D100: p[j] = 0.01; break;
       case IKR_D10N: p[j] = 0.1 / bnorm; break;

@@ -104,6 +104,7 @@ struct System {
   DBuf<double2> d_Tphi;            // [J][C][ncol_max] column transforms of occupied phi
   DBuf<double> d_rho, d_fx, d_khat;   // internal layout
   std::vector<double> orbnorm_k;   // ||Re F_k^-1 Phi_k||_{2,inf}
+  std::vector<double> orbnorm_full_k;  // ||F_k^-1 Phi_k||_{2,inf}
 
   // work
   CgWork<double> w64;

@@ -77,7 +77,7 @@ def tiny_dense():
     return rs, osys, emat
 
 
-@pytest.mark.parametrize("strategy", ["agr", "bal", "grt", "D10", "D100", "D10n"])
+@pytest.mark.parametrize("strategy", ["agr", "bal", "grt", "D10", "D100", "D10n", "thm2"])
 def test_solve_response_matches_dense_solve(tiny_dense, strategy):
     from paper_2505_02319_amd import default_opts
     rs, osys, emat = tiny_dense
@@ -89,9 +89,9 @@ def test_solve_response_matches_dense_solve(tiny_dense, strategy):
     true_r = np.linalg.norm(b.ravel() - emat @ x)
     ref = np.linalg.solve(emat, b.ravel())
     assert abs(true_r - st["true_res"]) < 1e-3 * tau + 1e-13
-    if strategy == "grt":
+    if strategy in ("grt", "thm2"):
         assert true_r <= tau
-    if strategy in ("bal", "grt"):
+    if strategy in ("bal", "grt", "thm2"):
         assert true_r <= 3 * tau
         assert rel(x, ref) < 1e-7
     assert st["est_res"] <= tau / 3

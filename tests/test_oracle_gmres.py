@@ -63,9 +63,9 @@ def test_gmres_matches_dense_solve(tiny_dense, strategy):
     assert abs(true_r - true_residual(sys, gs, kern, b, res.x)) < 1e-12
     cond = np.linalg.cond(emat)
     assert np.linalg.norm(x - ref) <= cond * 10 * true_r + 1e-14
-    if strategy == "grt":
+    if strategy in ("grt", "thm2"):
         assert true_r <= tau                      # Theorem 2 guarantee
-    if strategy in ("bal", "grt"):
+    if strategy in ("bal", "grt", "thm2"):
         assert true_r <= 3 * tau
     # estimated residual decreases monotonically inside a cycle
     for a_, b_ in zip(res.history, res.history[1:]):
