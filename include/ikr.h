@@ -201,12 +201,13 @@ ikr_status ikr_solve_response(ikr_handle h, const double* b_dev,
                               double* drho_dev, const ikr_solver_opts* opts,
                               ikr_stats* stats);
 
-/* Opt-in kernel timing (process-wide).  When enabled, the hot kernels of the
- * Sternheimer CG are bracketed by HIP events on the launching stream and
- * each launch carries its algorithmic byte count (bytes the kernel must move
- * to or from HBM by its definition, not by measurement).  kernel_id indexes
- * ikr_profile_kernel_name (0 .. ikr_profile_kernel_count()-1). */
-ikr_status ikr_profile_enable(int on);
+/* Opt-in kernel timing (process-wide).  Bit i of kernel_mask brackets every
+ * launch of hot kernel i of the Sternheimer CG by HIP events on the launching
+ * stream (0 disables, -1 times all); each launch carries its algorithmic
+ * byte count (bytes the kernel must move to or from HBM by its definition,
+ * not by measurement).  kernel_id indexes ikr_profile_kernel_name
+ * (0 .. ikr_profile_kernel_count()-1). */
+ikr_status ikr_profile_enable(int kernel_mask);
 ikr_status ikr_profile_reset(void);
 int ikr_profile_kernel_count(void);
 const char* ikr_profile_kernel_name(int kernel_id);

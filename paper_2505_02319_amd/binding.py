@@ -128,8 +128,15 @@ def default_opts(**kw) -> SolverOpts:
     return o
 
 
-def profile_enable(on: bool = True):
-    _check(lib().ikr_profile_enable(1 if on else 0))
+def profile_enable(on=True):
+    """True: time every hot kernel; False: none; a kernel name: only that one."""
+    L = lib()
+    if isinstance(on, str):
+        names = [L.ikr_profile_kernel_name(i).decode() for i in range(L.ikr_profile_kernel_count())]
+        mask = 1 << names.index(on)
+    else:
+        mask = -1 if on else 0
+    _check(L.ikr_profile_enable(mask))
 
 
 def profile_reset():

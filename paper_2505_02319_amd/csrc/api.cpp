@@ -251,8 +251,8 @@ ikr_status ikr_solve_response(ikr_handle h, const double* b_dev, double* drho_de
   });
 }
 
-ikr_status ikr_profile_enable(int on) {
-  return guarded([&] { ikr::KTimer::enable(on != 0); });
+ikr_status ikr_profile_enable(int kernel_mask) {
+  return guarded([&] { ikr::KTimer::enable((unsigned)kernel_mask); });
 }
 
 ikr_status ikr_profile_reset(void) {

@@ -8,13 +8,19 @@ namespace ikr {
 constexpr int BT = 16;     // slots per tile (bands of one k-point)
 constexpr int MAXM = 96;   // max projector rows in one update pass
 
-// Tiles of consecutive slots sharing a k-point.
+// Tiles of up to BT slots sharing a k-point.  Slot b of tile t is
+// slot0[t] + b, or idx[slot0[t] + b] when a compact index list is given.
 struct Tiles {
   int n;
   const int* k;
   const int* slot0;
   const int* nb;           // slots in the tile (<= BT)
+  const int* idx = nullptr;
 };
+
+__device__ __forceinline__ int tslot(const Tiles& tl, int t, int b) {
+  return tl.idx ? tl.idx[tl.slot0[t] + b] : tl.slot0[t] + b;
+}
 
 // One term  alpha * sum_m W[k][m][g] * C[slot][m]  of an update.
 template <typename R> struct UpdTerm {
@@ -64,7 +70,8 @@ void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
 template <typename R>
 void cg_step(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
              const int* active, const R* alpha, const R* pshift, cplx<R>* x, cplx<R>* r,
-             const cplx<R>* p, cplx<R>* w, R* rpart, hipStream_t st);
+             const cplx<R>* p, cplx<R>* w, R* rpart, hipStream_t st,
+             const int* list = nullptr);
 
 template <typename R>
 void precond(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
@@ -72,7 +79,8 @@ void precond(int nslots, const int* slot_k, const int* nb, const double* kin, in
 
 template <typename R>
 void cg_scalars(int nslots, int nparts, const R* part, int op, int* active,
-                const CgScalars<R>& cs, int start, hipStream_t st);
+                const CgScalars<R>& cs, int start, hipStream_t st,
+                const int* list = nullptr);
 
 void sum_groups(int n, int ngroups, const double* part, double scale, double* out,
                 hipStream_t st);

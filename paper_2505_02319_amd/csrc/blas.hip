@@ -21,9 +21,9 @@ constexpr int MT = 16;        // projector rows per gram pass
 // True when some slot of tile t takes part (active == null: all do).
 __device__ __forceinline__ bool tile_live(const Tiles& tl, int t, const int* active) {
   if (!active) return true;
-  const int s0 = tl.slot0[t], nbt = tl.nb[t];
+  const int nbt = tl.nb[t];
   bool any = false;
-  for (int b = 0; b < nbt; ++b) any |= active[s0 + b] != 0;
+  for (int b = 0; b < nbt; ++b) any |= active[tslot(tl, t, b)] != 0;
   return any;
 }
 
@@ -41,10 +41,13 @@ __global__ __launch_bounds__(NT) void gram_kernel(
     cplx<R>* __restrict__ part, const int* __restrict__ active) {
   __shared__ cplx<R> Xs[BT][CH + 1];
   __shared__ cplx<R> Ws[MT][CH + 1];
+  __shared__ int ss[BT];
   const int t = blockIdx.y, sc = blockIdx.x, tid = threadIdx.x;
   if (!tile_live(tl, t, active)) return;
-  const int k = tl.k[t], s0 = tl.slot0[t], nbt = tl.nb[t];
+  const int k = tl.k[t], nbt = tl.nb[t];
   const int M = Mk[k], n = nb[k];
+  if (tid < BT) ss[tid] = tid < nbt ? tslot(tl, t, tid) : 0;
+  __syncthreads();
   const int i_out = tid / BT, b_out = tid % BT;
   const cplx<R>* Wk = W + (size_t)k * wk_stride;
   for (int m0 = 0; m0 < M; m0 += MT) {
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(NT) void gram_kernel(
     for (int g0 = gbeg; g0 < gend; g0 += CH) {
       for (int i = tid; i < BT * CH; i += NT) {
         const int b = i / CH, e = i % CH, gg = g0 + e;
-        Xs[b][e] = (b < nbt && gg < gend) ? X[(size_t)(s0 + b) * x_stride + gg] : mk<R>(0, 0);
+        Xs[b][e] = (b < nbt && gg < gend) ? X[(size_t)ss[b] * x_stride + gg] : mk<R>(0, 0);
       }
       for (int i = tid; i < MT * CH; i += NT) {
         const int m = i / CH, e = i % CH, gg = g0 + e;
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(NT) void gram_reduce_kernel(
     const int* __restrict__ active) {
   const int t = blockIdx.x;
   if (!tile_live(tl, t, active)) return;
-  const int k = tl.k[t], s0 = tl.slot0[t], nbt = tl.nb[t], M = Mk[k];
+  const int k = tl.k[t], nbt = tl.nb[t], M = Mk[k];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int o = blockIdx.y * (NT / 64) + wave;
   const int m = o / BT, b = o % BT;
@@ -96,7 +99,7 @@ __global__ __launch_bounds__(NT) void gram_reduce_kernel(
   }
   sx = wave_sum(sx);
   sy = wave_sum(sy);
-  if (lane == 0) coef[(size_t)(s0 + b) * cstride + m] = mk<R>(sx, sy);
+  if (lane == 0) coef[(size_t)tslot(tl, t, b) * cstride + m] = mk<R>(sx, sy);
 }
 
 // Y[slot][g] = a * Y[slot][g] + sum_j alpha_j sum_m W_j[k][m][g] coef_j[slot][m]
@@ -114,15 +117,18 @@ __global__ __launch_bounds__(NT) void update_kernel(
   __shared__ cplx<R> c1[BT][MAXM];
   __shared__ cplx<R> c2[BT][MAXM];
   __shared__ R red[NT];
+  __shared__ int ss[BT];
   const int t = blockIdx.y, tid = threadIdx.x;
   if (!tile_live(tl, t, active)) return;
-  const int k = tl.k[t], s0 = tl.slot0[t], nbt = tl.nb[t];
+  const int k = tl.k[t], nbt = tl.nb[t];
   const int n = nb[k];
   const int M1 = W1 ? M1k[k] : 0, M2 = W2 ? M2k[k] : 0;
+  if (tid < BT) ss[tid] = tid < nbt ? tslot(tl, t, tid) : 0;
+  __syncthreads();
   for (int i = tid; i < BT * MAXM; i += NT) {
     const int b = i / MAXM, m = i % MAXM;
-    c1[b][m] = (b < nbt && m < M1) ? cscale<R>(C1[(size_t)(s0 + b) * c1s + m], alpha1) : mk<R>(0, 0);
-    c2[b][m] = (b < nbt && m < M2) ? cscale<R>(C2[(size_t)(s0 + b) * c2s + m], alpha2) : mk<R>(0, 0);
+    c1[b][m] = (b < nbt && m < M1) ? cscale<R>(C1[(size_t)ss[b] * c1s + m], alpha1) : mk<R>(0, 0);
+    c2[b][m] = (b < nbt && m < M2) ? cscale<R>(C2[(size_t)ss[b] * c2s + m], alpha2) : mk<R>(0, 0);
   }
   __syncthreads();
   const int g = blockIdx.x * NT + tid;
@@ -145,7 +151,7 @@ __global__ __launch_bounds__(NT) void update_kernel(
   }
 #pragma unroll
   for (int b = 0; b < BT; ++b) {
-    const int slot = s0 + b;
+    const int slot = ss[b];
     const bool on = b < nbt && (!active || active[slot]);
     R d = 0;
     if (on && g < n) {
@@ -178,9 +184,9 @@ __global__ __launch_bounds__(NT) void cg_step_kernel(
     const double* __restrict__ kin, int nb_max, const int* __restrict__ active,
     const R* __restrict__ alpha, const R* __restrict__ pshift,
     cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
-    cplx<R>* __restrict__ w, R* __restrict__ rpart, int stride) {
+    cplx<R>* __restrict__ w, R* __restrict__ rpart, int stride, const int* __restrict__ list) {
   __shared__ R red[NT];
-  const int slot = blockIdx.y, tid = threadIdx.x;
+  const int slot = list ? list[blockIdx.y] : blockIdx.y, tid = threadIdx.x;
   if (active && !active[slot]) return;
   const int k = slot_k[slot];
   const int g = blockIdx.x * NT + tid;
@@ -233,11 +239,13 @@ template <typename R>
 __global__ __launch_bounds__(NT) void cg_scalar_kernel(int nslots, int nparts,
                                                       const R* __restrict__ part, int op,
                                                       int* __restrict__ active,
-                                                      CgScalars<R> cs, int start) {
+                                                      CgScalars<R> cs, int start,
+                                                      const int* __restrict__ list) {
   if (op == 0 && blockIdx.x == 0 && threadIdx.x == 0) *cs.nactive = 0;
-  const int slot = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  const int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (slot >= nslots) return;
+  if (row >= nslots) return;
+  const int slot = list ? list[row] : row;
   if (active && !active[slot]) return;
   R s = 0;
   for (int i = lane; i < nparts; i += 64) s += part[(size_t)slot * nparts + i];
@@ -441,10 +449,11 @@ int vec_nblocks(int nb_max) { return (nb_max + NT - 1) / NT; }
 template <typename R>
 void cg_step(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
              const int* active, const R* alpha, const R* pshift, cplx<R>* x, cplx<R>* r,
-             const cplx<R>* p, cplx<R>* w, R* rpart, hipStream_t st) {
+             const cplx<R>* p, cplx<R>* w, R* rpart, hipStream_t st, const int* list) {
+  if (nslots <= 0) return;
   hipLaunchKernelGGL((cg_step_kernel<R>), dim3(vec_nblocks(nb_max), nslots), dim3(NT), 0,
                      st, slot_k, nb, kin, nb_max, active, alpha, pshift, x, r, p, w, rpart,
-                     nb_max);
+                     nb_max, list);
   IKR_HIP(hipGetLastError());
 }
 
@@ -458,10 +467,11 @@ void precond(int nslots, const int* slot_k, const int* nb, const double* kin, in
 
 template <typename R>
 void cg_scalars(int nslots, int nparts, const R* part, int op, int* active,
-                const CgScalars<R>& cs, int start, hipStream_t st) {
+                const CgScalars<R>& cs, int start, hipStream_t st, const int* list) {
+  if (nslots <= 0) return;
   const int per_block = NT / 64;
   hipLaunchKernelGGL((cg_scalar_kernel<R>), dim3((nslots + per_block - 1) / per_block),
-                     dim3(NT), 0, st, nslots, nparts, part, op, active, cs, start);
+                     dim3(NT), 0, st, nslots, nparts, part, op, active, cs, start, list);
   IKR_HIP(hipGetLastError());
 }
 
@@ -541,11 +551,11 @@ void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st) {
                           hipStream_t);                                                   \
   template void cg_step<R>(int, const int*, const int*, const double*, int, const int*,   \
                            const R*, const R*, cplx<R>*, cplx<R>*, const cplx<R>*,        \
-                           cplx<R>*, R*, hipStream_t);                                    \
+                           cplx<R>*, R*, hipStream_t, const int*);                        \
   template void precond<R>(int, const int*, const int*, const double*, int, const R*,     \
                            const cplx<R>*, cplx<R>*, hipStream_t);                        \
   template void cg_scalars<R>(int, int, const R*, int, int*, const CgScalars<R>&, int,    \
-                              hipStream_t);                                               \
+                              hipStream_t, const int*);                                   \
   template void cscale_vec<R>(size_t, cplx<R>*, R, hipStream_t);
 IKR_INST(double)
 IKR_INST(float)

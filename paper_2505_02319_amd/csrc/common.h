@@ -72,12 +72,18 @@ struct Geom {
   const double* kin;     // [nk][nb_max] |G+k|^2/2, 0 beyond nb
 };
 
-// Per-slot (band of the batch) metadata for batched kernels.
+// Per-slot (band of the batch) metadata for batched kernels.  A launch
+// covers n grid rows; row y works on slot list[y] (list may be null: y).
 struct Slots {
-  int n;                 // number of slots
-  const int* k;          // [n] k-point of the slot
-  const int* active;     // [n] nonzero when the slot takes part (may be null)
+  int n;                 // number of grid rows
+  const int* k;          // [slots] k-point of the slot
+  const int* active;     // [slots] nonzero when the slot takes part (may be null)
+  const int* list = nullptr;   // [n] compact list of slots (may be null)
 };
+
+__device__ __forceinline__ int slot_of(const Slots& s, int row) {
+  return s.list ? s.list[row] : row;
+}
 
 // ---------------------------------------------------------------- FFT API
 // All transforms are unnormalised: inverse = sum_G x_G e^{+iG.r},

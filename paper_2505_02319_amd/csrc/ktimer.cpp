@@ -17,7 +17,7 @@ struct Pending {
 
 struct State {
   std::mutex mu;
-  bool on = false;
+  unsigned mask = 0;
   std::vector<Pending> pending;
   std::vector<hipEvent_t> pool;
   hipEvent_t open[K_COUNT] = {};
@@ -64,16 +64,16 @@ const char* kernel_name(int id) {
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
-void KTimer::enable(bool on) {
+void KTimer::enable(unsigned mask) {
   std::lock_guard<std::mutex> g(S().mu);
-  S().on = on;
+  S().mask = mask;
 }
 
-bool KTimer::enabled() { return S().on; }
+bool KTimer::enabled() { return S().mask != 0; }
 
 void KTimer::begin(int id, hipStream_t st) {
   State& s = S();
-  if (!s.on) return;
+  if (!((s.mask >> id) & 1u)) return;
   std::lock_guard<std::mutex> g(s.mu);
   hipEvent_t e = get_event(s);
   IKR_HIP(hipEventRecord(e, st));
@@ -82,7 +82,7 @@ void KTimer::begin(int id, hipStream_t st) {
 
 void KTimer::end(int id, hipStream_t st, double bytes) {
   State& s = S();
-  if (!s.on) return;
+  if (!((s.mask >> id) & 1u)) return;
   std::lock_guard<std::mutex> g(s.mu);
   if (!s.open[id]) return;
   hipEvent_t e = get_event(s);

@@ -21,7 +21,7 @@ enum KernelId : int {
 const char* kernel_name(int id);
 
 struct KTimer {
-  static void enable(bool on);
+  static void enable(unsigned kernel_mask);   // bit i times kernel i
   static bool enabled();
   static void begin(int id, hipStream_t st);
   static void end(int id, hipStream_t st, double bytes);

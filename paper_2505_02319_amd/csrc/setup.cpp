@@ -388,6 +388,10 @@ void finish_setup(System& s) {
   w.dpart.alloc((size_t)s.J * std::max(update_nblocks(s.nb_max), vec_nblocks(s.nb_max)));
   w.pshift.alloc(s.J); w.shift.alloc(s.J);
   s.d_active.alloc(s.J);
+  s.d_list.alloc(s.J);
+  s.d_ctk.alloc(s.tiles.n);
+  s.d_cto.alloc(s.tiles.n);
+  s.d_ctn.alloc(s.tiles.n);
   s.d_iters.alloc(s.J);
   s.d_counters.alloc(4);
   s.d_tol2.alloc(s.J);

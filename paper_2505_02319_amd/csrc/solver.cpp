@@ -150,7 +150,6 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   const int J = s.J, nbm = s.nb_max, nbn = s.nbands;
   const double inv_ng = 1.0 / s.ng;
   Slots all{J, s.d_slot_k.get(), nullptr};
-  Slots act{J, s.d_slot_k.get(), s.d_active.get()};
   const size_t phik = (size_t)nbn * nbm;
   UpdTerm<double> none{};
   Chi0Result res;
@@ -236,13 +235,43 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   nb_avg /= J;
   ncol_avg /= J;
   const double S16 = 16.0, colC = ncol_avg * s.L.C;
-  const double ntiles = s.tiles.n;
-  auto tile_bytes = [&](double M, bool upd, bool dot) {
-    // W read once per tile, X read (gram) or Y read+write (+ D read) per slot
-    return ntiles * M * nb_avg * S16 + J * nb_avg * S16 * (upd ? (dot ? 3.0 : 2.0) : 1.0);
+  // Compact active set: the slots still iterating and per-k tiles of them.
+  std::vector<int> hflag(J, 1), hlist(J), htk, hto, htn;
+  int nct = 0;
+  auto rebuild = [&]() {
+    int na = 0;
+    htk.clear(); hto.clear(); htn.clear();
+    for (int k = 0; k < s.nk; ++k) {
+      const int j0 = s.slot0_k[k], j1 = j0 + s.nocc_k[k];
+      int cnt = 0;
+      for (int j = j0; j < j1; ++j) {
+        if (!hflag[j]) continue;
+        if (cnt % BT == 0) {
+          htk.push_back(k);
+          hto.push_back(na);
+          htn.push_back(0);
+        }
+        hlist[na++] = j;
+        ++htn.back();
+        ++cnt;
+      }
+    }
+    nct = (int)htk.size();
+    IKR_HIP(hipMemcpyAsync(s.d_list.get(), hlist.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+    IKR_HIP(hipMemcpyAsync(s.d_ctk.get(), htk.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
+    IKR_HIP(hipMemcpyAsync(s.d_cto.get(), hto.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
+    IKR_HIP(hipMemcpyAsync(s.d_ctn.get(), htn.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
+    IKR_HIP(hipStreamSynchronize(st));
+    return na;
   };
-  int nact = J;
+  int nact = rebuild();
   for (int it = 0; it < max_iter && nact > 0; ++it) {
+    Slots act{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get()};
+    Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get()};
+    auto tile_bytes = [&](double M, bool upd, bool dot) {
+      // W read once per tile, X read (gram) or Y read+write (+ D read) per slot
+      return nct * M * nb_avg * S16 + nact * nb_avg * S16 * (upd ? (dot ? 3.0 : 2.0) : 1.0);
+    };
     // p = z + beta p ; w = (H - e) p  (local part through the pruned FFT)
     KTimer::begin(K_COL_INV, st);
     launch_col_inv<double>(s.geom, s.fft, act, w.p.get(), nbm, w.T1.get(), w.w.get(),
@@ -257,47 +286,50 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     KTimer::end(K_COL_FWD, st, nact * (colC * S16 + nb_avg * (2.0 * S16 + 8.0)));
     if (s.natoms > 0) {
       KTimer::begin(K_GRAM, st);
-      gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
+      gram<double>(ctl, s.d_nb.get(), nbm, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
                    (size_t)s.natoms * nbm, nbm, w.p.get(), nbm, w.part.get(), w.coefB.get(),
-                   MAXM, st, s.d_active.get());
+                   MAXM, st);
       KTimer::end(K_GRAM, st, tile_bytes(s.natoms, false, false));
       KTimer::begin(K_UPDATE, st);
-      update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, projB,
+      update<double>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, 1.0, projB,
                      none, nullptr, nullptr, st);
       KTimer::end(K_UPDATE, st, tile_bytes(s.natoms, true, false));
     }
     // Ap = Q w ; pAp
     KTimer::begin(K_GRAM, st);
-    gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
-                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st, s.d_active.get());
+    gram<double>(ctl, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
+                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
     KTimer::end(K_GRAM, st, tile_bytes(s.nocc_max, false, false));
     KTimer::begin(K_UPDATE, st);
-    update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
+    update<double>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, 1.0, phiA,
                    none, w.p.get(), w.dpart.get(), st);
     KTimer::end(K_UPDATE, st, tile_bytes(s.nocc_max, true, true));
-    cg_scalars<double>(J, nup, w.dpart.get(), 0, s.d_active.get(), cs, 0, st);
+    cg_scalars<double>(nact, nup, w.dpart.get(), 0, s.d_active.get(), cs, 0, st,
+                       s.d_list.get());
     // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, convergence
     KTimer::begin(K_CG_STEP, st);
-    cg_step<double>(J, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, s.d_active.get(),
+    cg_step<double>(nact, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, nullptr,
                     w.alpha.get(), w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(),
-                    w.dpart.get(), st);
+                    w.dpart.get(), st, s.d_list.get());
     KTimer::end(K_CG_STEP, st, nact * nb_avg * (7.0 * S16 + 8.0));
-    cg_scalars<double>(J, nvb, w.dpart.get(), 1, s.d_active.get(), cs, 0, st);
-    // z = Q M^-1 r, rz = <r, z>, beta
+    cg_scalars<double>(nact, nvb, w.dpart.get(), 1, s.d_active.get(), cs, 0, st,
+                       s.d_list.get());
+    // z = Q M^-1 r, rz = <r, z>, beta (bands that just converged are skipped)
     KTimer::begin(K_GRAM, st);
-    gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
+    gram<double>(ctl, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
                  nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st, s.d_active.get());
     KTimer::end(K_GRAM, st, tile_bytes(s.nocc_max, false, false));
     KTimer::begin(K_UPDATE, st);
-    update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
+    update<double>(ctl, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
                    none, w.r.get(), w.dpart.get(), st);
     KTimer::end(K_UPDATE, st, tile_bytes(s.nocc_max, true, true));
-    cg_scalars<double>(J, nup, w.dpart.get(), 2, s.d_active.get(), cs, 0, st);
+    cg_scalars<double>(nact, nup, w.dpart.get(), 2, s.d_active.get(), cs, 0, st,
+                       s.d_list.get());
     res.n_ham += nact;
-    int cnt = 0;
-    IKR_HIP(hipMemcpyAsync(&cnt, s.d_counters.get(), sizeof(int), hipMemcpyDeviceToHost, st));
+    IKR_HIP(hipMemcpyAsync(hflag.data(), s.d_active.get(), J * sizeof(int),
+                           hipMemcpyDeviceToHost, st));
     IKR_HIP(hipStreamSynchronize(st));
-    nact = cnt;
+    nact = rebuild();
   }
   res.n_ham64 = res.n_ham;
   int noconv = 0;

@@ -112,6 +112,7 @@ struct System {
   DBuf<double> d_u, d_drho, d_tmpg, d_kpart, d_rhopart, d_wa, d_wb, d_multi;
   DBuf<double2> d_kw1, d_kw2;
   DBuf<int> d_active, d_iters, d_counters;
+  DBuf<int> d_list, d_ctk, d_cto, d_ctn;   // compact active slots and their tiles
   DBuf<double> d_tol2;
   std::vector<double> knorm_hist;
 
