@@ -1,8 +1,9 @@
 #!/usr/bin/env python3
 """Throughput of the inexact-GMRES Dyson solve on one MI355X.
 
-One step = one full solve of E drho = b (Alg. 1, bal strategy, tau = 1e-8 ||b||,
-m = 20, s0 = 1, x0 = 0) on the 8-atom cubic cell (a = 20.52 bohr, Ecut = 15 Ha,
+One step = one full solve of E drho = b (Alg. 1, grt strategy, tau = 1e-8 ||b||,
+m = 20, s0 = 1, x0 = 0; computed unoccupied bands by sum over states; FP32
+Sternheimer CG where the band's tolerance allows) on the 8-atom cubic cell (a = 20.52 bohr, Ecut = 15 Ha,
 FFT 48^3, 2x2x2 k-points, 16 occupied + 4 extra bands, Hartree + Slater
 kernel), with b the seeded smooth random field.  Inputs and the ground state
 (computed by the library's own GPU eigensolver during setup) are resident in
@@ -71,8 +72,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg2")
-    ap.add_argument("--strategy", default="thm2")
-    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--strategy", default="grt")
+    ap.add_argument("--precision", type=int, default=1)
+    ap.add_argument("--schur", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -97,7 +99,7 @@ def main():
         f"residual {info['gs_residual']:.1e}, min gap {min(info['gaps']):.2e}")
     b = torch.from_numpy(random_field(spec, B_SEED)).cuda()
     opts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
-                        precision=args.precision)
+                        precision=args.precision, schur=args.schur)
 
     # warmup; the last warmup step times every hot kernel to find the dominant
     # one, whose launches alone are then timed live inside the timed region
@@ -133,11 +135,20 @@ def main():
 
     # accuracy of the returned solution (untimed): true residual with tight CG
     vopts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
-                         precision=args.precision, want_true_residual=1)
-    _, vst = rs.solve(b, vopts)
+                         precision=args.precision, schur=args.schur, want_true_residual=1)
+    xv, vst = rs.solve(b, vopts)
     bnorm = float(torch.linalg.norm(b))
     true_rel = vst["true_res"] / bnorm
     log(f"true relative residual {true_rel:.2e}")
+    # the same solve with the Sternheimer CG in FP64 throughout (untimed
+    # reference for the mixed-precision error and speed-up)
+    popts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1, precision=0,
+                         schur=args.schur, want_true_residual=1)
+    xp, pst = rs.solve(b, popts)
+    fp64 = {"seconds": pst["seconds"], "n_ham": pst["n_ham"],
+            "true_rel_residual": pst["true_res"] / bnorm,
+            "rel_diff_vs_mixed": float(torch.linalg.norm(xv - xp) / torch.linalg.norm(xp))}
+    log(f"fp64 CG: {pst['seconds']:.3f} s, true rel. residual {fp64['true_rel_residual']:.2e}")
 
     launches, ms, by = prof[dom]
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -157,10 +168,15 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 0 else "f32/f64",
+        "fp64_cg_solve": fp64,
+        "n_ham_fp32_per_solve": vst["n_ham_fp32"],
         "data": "synthetic",
         "config": {"workload": f"{spec.name}: 8-atom cubic cell a=20.52 bohr, Ecut 15 Ha, "
                                f"FFT 48^3, 2x2x2 k, 16+4 bands, K_H + Slater, "
-                               f"strategy {args.strategy}, m 20, tau 1e-8||b||",
+                               f"strategy {args.strategy}, extra bands by sum over states "
+                               f"{'on' if args.schur else 'off'}, "
+                               f"CG precision {'mixed' if args.precision else 'fp64'}, "
+                               f"m 20, tau 1e-8||b||",
                    "global_batch": 1, "parallelism": "single-gpu"},
         "hpsi_band_applies_per_s": n_ham / elapsed,
         "n_ham_per_solve": n_ham / args.steps,

@@ -109,6 +109,12 @@ typedef struct {
   double b_norm;            /* ||b|| for D10n inside ikr_apply_dielectric */
   int want_true_residual;   /* 1: report ||b - E x|| with tight CG at exit */
   double true_res_cg_tol;   /* CG tolerance of the true-residual apply (1e-14) */
+  int schur;                /* 1: the computed unoccupied bands take their part of
+                               the orbital response by sum over states and the CG
+                               runs on the complement of all computed bands (the
+                               extra-band / Schur-complement treatment the paper's
+                               runs use, Sec. 4.1.2); 0: CG on the complement of
+                               the occupied bands only (default 1) */
 } ikr_solver_opts;
 
 typedef struct {

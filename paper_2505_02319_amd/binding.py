@@ -48,7 +48,8 @@ class SolverOpts(C.Structure):
                 ("restart_m", C.c_int), ("s0", C.c_double), ("max_restarts", C.c_int),
                 ("precision", C.c_int), ("cg_min_iter", C.c_int), ("cg_max_iter", C.c_int),
                 ("fp32_theta", C.c_double), ("b_norm", C.c_double),
-                ("want_true_residual", C.c_int), ("true_res_cg_tol", C.c_double)]
+                ("want_true_residual", C.c_int), ("true_res_cg_tol", C.c_double),
+                ("schur", C.c_int)]
 
 
 class Stats(C.Structure):

@@ -70,6 +70,7 @@ void ikr_default_opts(ikr_solver_opts* o) {
   o->b_norm = 1.0;
   o->want_true_residual = 0;
   o->true_res_cg_tol = 1e-14;
+  o->schur = 1;
 }
 
 int ikr_supported_fft_size(int n) { return ikr::fft_length_supported(n) ? 1 : 0; }

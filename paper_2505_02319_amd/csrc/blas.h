@@ -84,6 +84,15 @@ void cg_scalars(int nslots, int nparts, const R* part, int op, int* active,
 
 void sum_groups(int n, int ngroups, const double* part, double scale, double* out,
                 hipStream_t st);
+// precision changes: listed slots over their spheres, or whole arrays
+void convert_slots(int n, const int* list, const int* slot_k, const int* nb, int nb_max,
+                   const double2* in, float2* out, hipStream_t st);
+void convert_slots(int n, const int* list, const int* slot_k, const int* nb, int nb_max,
+                   const float2* in, double2* out, hipStream_t st);
+void convert_array(size_t n, const double* in, float* out, hipStream_t st);
+void convert_array(size_t n, const double2* in, float2* out, hipStream_t st);
+void resid_norms(int nslots, int nb_max, const int* slot_k, const int* nb, const double2* HX,
+                 const double2* X, const double* lam, double* part, hipStream_t st);
 void to_internal(const Layout& L, const double* ext, double* in, hipStream_t st);
 void to_external(const Layout& L, const double* in, double* ext, double a,
                  const double* base, double bscale, hipStream_t st);

@@ -384,6 +384,38 @@ __global__ __launch_bounds__(NT) void resid_kernel(
   if (tid == 0) part[(size_t)slot * gridDim.x + blockIdx.x] = red[0];
 }
 
+// out[slot] = in[slot] over the sphere of the listed slots (precision change)
+template <typename A, typename B>
+__global__ __launch_bounds__(NT) void cvt_slots_kernel(
+    const int* __restrict__ list, const int* __restrict__ slot_k, const int* __restrict__ nb,
+    int nb_max, const A* __restrict__ in, B* __restrict__ out) {
+  const int slot = list[blockIdx.y];
+  const int g = blockIdx.x * NT + threadIdx.x;
+  if (g >= nb[slot_k[slot]]) return;
+  const size_t o = (size_t)slot * nb_max + g;
+  const A v = in[o];
+  B w;
+  w.x = v.x;
+  w.y = v.y;
+  out[o] = w;
+}
+
+template <typename A, typename B>
+__global__ void cvt_array_kernel(size_t n, const A* __restrict__ in, B* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (B)in[i];
+}
+
+template <typename A, typename B>
+__global__ void cvt_carray_kernel(size_t n, const A* __restrict__ in, B* __restrict__ out) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  B w;
+  w.x = in[i].x;
+  w.y = in[i].y;
+  out[i] = w;
+}
+
 template <typename R>
 __global__ void cscale_kernel(size_t n, cplx<R>* __restrict__ x, R a) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -519,6 +551,36 @@ void multiaxpy(int n, int nv, const double* V, size_t vstride, const double* c, 
 
 void scale_copy(size_t n, const double* x, double a, double* y, hipStream_t st) {
   hipLaunchKernelGGL(scale_copy_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, x, a, y);
+  IKR_HIP(hipGetLastError());
+}
+
+void convert_slots(int n, const int* list, const int* slot_k, const int* nb, int nb_max,
+                   const double2* in, float2* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((cvt_slots_kernel<double2, float2>), dim3(vec_nblocks(nb_max), n),
+                     dim3(NT), 0, st, list, slot_k, nb, nb_max, in, out);
+  IKR_HIP(hipGetLastError());
+}
+
+void convert_slots(int n, const int* list, const int* slot_k, const int* nb, int nb_max,
+                   const float2* in, double2* out, hipStream_t st) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((cvt_slots_kernel<float2, double2>), dim3(vec_nblocks(nb_max), n),
+                     dim3(NT), 0, st, list, slot_k, nb, nb_max, in, out);
+  IKR_HIP(hipGetLastError());
+}
+
+void convert_array(size_t n, const double* in, float* out, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL((cvt_array_kernel<double, float>), dim3((n + 255) / 256), dim3(256), 0, st,
+                     n, in, out);
+  IKR_HIP(hipGetLastError());
+}
+
+void convert_array(size_t n, const double2* in, float2* out, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL((cvt_carray_kernel<double2, float2>), dim3((n + 255) / 256), dim3(256), 0,
+                     st, n, in, out);
   IKR_HIP(hipGetLastError());
 }
 

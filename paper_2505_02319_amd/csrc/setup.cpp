@@ -276,6 +276,31 @@ System* create_system(const ikr_system_desc* d, hipStream_t st) {
   return sp.release();
 }
 
+// FP32 copies of the operator data and an FP32 CG work space, made on first
+// use of the mixed-precision path.
+void ensure_fp32(System& s) {
+  if (s.w32.x.get()) return;
+  const hipStream_t st = s.stream;
+  const CgWork<double>& d = s.w64;
+  CgWork<float>& w = s.w32;
+  const size_t vec = (size_t)s.J * s.nb_max, tbuf = (size_t)s.J * s.L.C * s.ncol_max;
+  w.x.alloc(vec); w.r.alloc(vec); w.p.alloc(vec); w.w.alloc(vec);
+  w.T1.alloc(tbuf); w.T2.alloc(tbuf);
+  w.coefA.alloc(d.coefA.n); w.coefB.alloc(d.coefB.n); w.part.alloc(d.part.n);
+  w.rz.alloc(s.J); w.alpha.alloc(s.J); w.beta.alloc(s.J); w.rnorm2.alloc(s.J);
+  w.dpart.alloc(d.dpart.n);
+  w.pshift.alloc(s.J); w.shift.alloc(s.J);
+  convert_array(s.J, d.pshift.get(), w.pshift.get(), st);
+  convert_array(s.J, d.shift.get(), w.shift.get(), st);
+  w.phi.alloc(s.d_phi.n);
+  convert_array(s.d_phi.n, s.d_phi.get(), w.phi.get(), st);
+  w.proj.alloc(s.d_proj.n);
+  convert_array(s.d_proj.n, s.d_proj.get(), w.proj.get(), st);
+  w.vloc.alloc(s.ng);
+  convert_array(s.ng, s.d_vloc.get(), w.vloc.get(), st);
+  IKR_HIP(hipStreamSynchronize(st));
+}
+
 void import_ground_state(System& s, const double* eps, const double* coeffs) {
   IKR_CHECK(eps && coeffs, 1, "null ground-state arrays");
   s.eps.assign(eps, eps + (size_t)s.nk * s.nbands);
@@ -368,6 +393,7 @@ void finish_setup(System& s) {
   const hipStream_t st = s.stream;
   s.d_slot_k.upload(s.slot_k, st);
   s.d_nocc_k.upload(s.nocc_k, st);
+  s.d_nbands_k.upload(std::vector<int>(nk, s.nbands), st);
   s.d_tile_k.upload(s.tile_k, st);
   s.d_tile_slot0.upload(s.tile_slot0, st);
   s.d_tile_nb.upload(s.tile_nb, st);

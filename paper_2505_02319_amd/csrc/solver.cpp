@@ -140,10 +140,206 @@ double apply_kernel(System& s, const double* v_int, double* kv_int) {
   return std::sqrt(ss);
 }
 
+// ---------------------------------------------------------------- CG
+namespace {
+
+struct CgOut {
+  long long n_ham = 0;
+  int noconv = 0;
+};
+
+template <typename R> const cplx<R>* phi_of(const System& s);
+template <> const double2* phi_of<double>(const System& s) { return s.d_phi.get(); }
+template <> const float2* phi_of<float>(const System& s) { return s.w32.phi.get(); }
+template <typename R> const cplx<R>* proj_of(const System& s);
+template <> const double2* proj_of<double>(const System& s) { return s.d_proj.get(); }
+template <> const float2* proj_of<float>(const System& s) { return s.w32.proj.get(); }
+template <typename R> const R* vloc_of(const System& s);
+template <> const double* vloc_of<double>(const System& s) { return s.d_vloc.get(); }
+template <> const float* vloc_of<float>(const System& s) { return s.w32.vloc.get(); }
+
+// ||r_j|| of every slot (host vector)
+std::vector<double> slot_norms(System& s, const double2* r) {
+  const int J = s.J, nrb = vec_nblocks(s.nb_max);
+  DBuf<double> zero, part;
+  zero.upload(std::vector<double>(J, 0.0), s.stream);
+  part.alloc((size_t)J * nrb);
+  resid_norms(J, s.nb_max, s.d_slot_k.get(), s.d_nb.get(), r, r, zero.get(), part.get(),
+              s.stream);
+  const std::vector<double> p = download(part.get(), (size_t)J * nrb, s.stream);
+  std::vector<double> out(J, 0.0);
+  for (int j = 0; j < J; ++j) {
+    double a = 0;
+    for (int b = 0; b < nrb; ++b) a += p[(size_t)j * nrb + b];
+    out[j] = std::sqrt(a);
+  }
+  return out;
+}
+
+// Preconditioned CG on Q (H - e_n) Q x = r for the member slots, all at once,
+// with per-band convergence masks and a compact active set rebuilt after
+// every iteration (Remark after Lemma cgtol_E: Ap and z re-projected onto
+// range Q; zero initial guess; at least min_iter iterations).
+template <typename R>
+CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>& member,
+             const std::vector<double>& tol_slot, int min_iter, int max_iter,
+             const int* dMq, int Mq_max) {
+  const hipStream_t st = s.stream;
+  const int J = s.J, nbm = s.nb_max, nbn = s.nbands;
+  const R inv_ng = R(1.0 / s.ng);
+  const size_t phik = (size_t)nbn * nbm;
+  const cplx<R>* phi = phi_of<R>(s);
+  const cplx<R>* proj = proj_of<R>(s);
+  const R* vloc = vloc_of<R>(s);
+  UpdTerm<R> none{};
+  CgOut out;
+  if (w.r.get() != rhs)
+    IKR_HIP(hipMemcpyAsync(w.r.get(), rhs, (size_t)J * nbm * sizeof(cplx<R>),
+                           hipMemcpyDeviceToDevice, st));
+  IKR_HIP(hipMemsetAsync(w.x.get(), 0, (size_t)J * nbm * sizeof(cplx<R>), st));
+  IKR_HIP(hipMemsetAsync(w.p.get(), 0, (size_t)J * nbm * sizeof(cplx<R>), st));
+  std::vector<double> tol2(J);
+  for (int j = 0; j < J; ++j) tol2[j] = tol_slot[j] * tol_slot[j];
+  IKR_HIP(hipMemcpyAsync(s.d_tol2.get(), tol2.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
+  IKR_HIP(hipMemcpyAsync(s.d_active.get(), member.data(), J * sizeof(int), hipMemcpyHostToDevice, st));
+  IKR_HIP(hipMemsetAsync(s.d_iters.get(), 0, J * sizeof(int), st));
+  IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, 4 * sizeof(int), st));
+  CgScalars<R> cs{w.rz.get(), w.alpha.get(), w.beta.get(), w.rnorm2.get(), s.d_tol2.get(),
+                  s.d_iters.get(), s.d_counters.get(), s.d_counters.get() + 1,
+                  min_iter, max_iter};
+  const int nup = update_nblocks(nbm), nvb = vec_nblocks(nbm);
+  UpdTerm<R> phiA{phi, phik, nbm, dMq, w.coefA.get(), MAXM, R(-1)};
+  UpdTerm<R> projB{proj, (size_t)s.natoms * nbm, nbm, s.d_natoms_k.get(), w.coefB.get(), MAXM,
+                   R(s.dnl)};
+
+  // Algorithmic bytes per band for the kernel timer: mean sphere and footprint.
+  double nb_avg = 0, ncol_avg = 0;
+  for (int j = 0; j < J; ++j) {
+    nb_avg += s.kp[s.slot_k[j]].nb;
+    ncol_avg += s.kp[s.slot_k[j]].ncol;
+  }
+  nb_avg /= J;
+  ncol_avg /= J;
+  const double SZ = sizeof(cplx<R>), colC = ncol_avg * s.L.C;
+  // Compact active set: the slots still iterating and per-k tiles of them.
+  std::vector<int> hflag(member), hlist(J), htk, hto, htn;
+  int nct = 0;
+  auto rebuild = [&]() {
+    int na = 0;
+    htk.clear(); hto.clear(); htn.clear();
+    for (int k = 0; k < s.nk; ++k) {
+      const int j0 = s.slot0_k[k], j1 = j0 + s.nocc_k[k];
+      int cnt = 0;
+      for (int j = j0; j < j1; ++j) {
+        if (!hflag[j]) continue;
+        if (cnt % BT == 0) {
+          htk.push_back(k);
+          hto.push_back(na);
+          htn.push_back(0);
+        }
+        hlist[na++] = j;
+        ++htn.back();
+        ++cnt;
+      }
+    }
+    nct = (int)htk.size();
+    if (na > 0) {
+      IKR_HIP(hipMemcpyAsync(s.d_list.get(), hlist.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+      IKR_HIP(hipMemcpyAsync(s.d_ctk.get(), htk.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
+      IKR_HIP(hipMemcpyAsync(s.d_cto.get(), hto.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
+      IKR_HIP(hipMemcpyAsync(s.d_ctn.get(), htn.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    IKR_HIP(hipStreamSynchronize(st));
+    return na;
+  };
+  int nact = rebuild();
+  if (nact == 0) return out;
+  {
+    // z = Q M^-1 r, rz = <r, z>, beta = 0
+    Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get()};
+    precond<R>(J, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, w.pshift.get(),
+               w.r.get(), w.w.get(), st);
+    gram<R>(ctl, s.d_nb.get(), nbm, dMq, Mq_max, phi, phik, nbm, w.w.get(),
+            nbm, w.part.get(), w.coefA.get(), MAXM, st);
+    update<R>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, R(1), phiA, none, w.r.get(),
+              w.dpart.get(), st);
+    cg_scalars<R>(nact, nup, w.dpart.get(), 2, s.d_active.get(), cs, 1, st, s.d_list.get());
+  }
+  for (int it = 0; it < max_iter && nact > 0; ++it) {
+    Slots act{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get()};
+    Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get()};
+    auto tile_bytes = [&](double M, bool upd, bool dot) {
+      // W read once per tile, X read (gram) or Y read+write (+ D read) per slot
+      return nct * M * nb_avg * SZ + nact * nb_avg * SZ * (upd ? (dot ? 3.0 : 2.0) : 1.0);
+    };
+    // p = z + beta p ; w = (H - e) p  (local part through the pruned FFT)
+    KTimer::begin(K_COL_INV, st);
+    launch_col_inv<R>(s.geom, s.fft, act, w.p.get(), nbm, w.T1.get(), w.w.get(), w.beta.get(),
+                      w.p.get(), st);
+    KTimer::end(K_COL_INV, st, nact * (3.0 * nb_avg + colC) * SZ);
+    KTimer::begin(K_PLANE_HV, st);
+    launch_plane_hv<R>(s.geom, s.fft, act, w.T1.get(), w.T2.get(), vloc, 0, st);
+    KTimer::end(K_PLANE_HV, st, nact * 2.0 * colC * SZ + sizeof(R) * (double)s.ng);
+    KTimer::begin(K_COL_FWD, st);
+    launch_col_fwd<R>(s.geom, s.fft, act, w.T2.get(), w.w.get(), nbm, w.p.get(), w.shift.get(),
+                      inv_ng, st);
+    KTimer::end(K_COL_FWD, st, nact * (colC * SZ + nb_avg * (2.0 * SZ + 8.0)));
+    if (s.natoms > 0) {
+      KTimer::begin(K_GRAM, st);
+      gram<R>(ctl, s.d_nb.get(), nbm, s.d_natoms_k.get(), s.natoms, proj, (size_t)s.natoms * nbm,
+              nbm, w.p.get(), nbm, w.part.get(), w.coefB.get(), MAXM, st);
+      KTimer::end(K_GRAM, st, tile_bytes(s.natoms, false, false));
+      KTimer::begin(K_UPDATE, st);
+      update<R>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, R(1), projB, none, nullptr,
+                nullptr, st);
+      KTimer::end(K_UPDATE, st, tile_bytes(s.natoms, true, false));
+    }
+    // Ap = Q w ; pAp
+    KTimer::begin(K_GRAM, st);
+    gram<R>(ctl, s.d_nb.get(), nbm, dMq, Mq_max, phi, phik, nbm, w.w.get(), nbm,
+            w.part.get(), w.coefA.get(), MAXM, st);
+    KTimer::end(K_GRAM, st, tile_bytes(Mq_max, false, false));
+    KTimer::begin(K_UPDATE, st);
+    update<R>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, R(1), phiA, none, w.p.get(),
+              w.dpart.get(), st);
+    KTimer::end(K_UPDATE, st, tile_bytes(Mq_max, true, true));
+    cg_scalars<R>(nact, nup, w.dpart.get(), 0, s.d_active.get(), cs, 0, st, s.d_list.get());
+    // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, convergence
+    KTimer::begin(K_CG_STEP, st);
+    cg_step<R>(nact, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, nullptr, w.alpha.get(),
+               w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(), w.dpart.get(), st,
+               s.d_list.get());
+    KTimer::end(K_CG_STEP, st, nact * nb_avg * (7.0 * SZ + 8.0));
+    cg_scalars<R>(nact, nvb, w.dpart.get(), 1, s.d_active.get(), cs, 0, st, s.d_list.get());
+    // z = Q M^-1 r, rz = <r, z>, beta (bands that just converged are skipped)
+    KTimer::begin(K_GRAM, st);
+    gram<R>(ctl, s.d_nb.get(), nbm, dMq, Mq_max, phi, phik, nbm, w.w.get(), nbm,
+            w.part.get(), w.coefA.get(), MAXM, st, s.d_active.get());
+    KTimer::end(K_GRAM, st, tile_bytes(Mq_max, false, false));
+    KTimer::begin(K_UPDATE, st);
+    update<R>(ctl, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, R(1), phiA, none,
+              w.r.get(), w.dpart.get(), st);
+    KTimer::end(K_UPDATE, st, tile_bytes(Mq_max, true, true));
+    cg_scalars<R>(nact, nup, w.dpart.get(), 2, s.d_active.get(), cs, 0, st, s.d_list.get());
+    out.n_ham += nact;
+    IKR_HIP(hipMemcpyAsync(hflag.data(), s.d_active.get(), J * sizeof(int),
+                           hipMemcpyDeviceToHost, st));
+    IKR_HIP(hipStreamSynchronize(st));
+    nact = rebuild();
+  }
+  int noconv = 0;
+  IKR_HIP(hipMemcpyAsync(&noconv, s.d_counters.get() + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+  IKR_HIP(hipStreamSynchronize(st));
+  out.noconv = noconv + nact;
+  return out;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------- chi0
 Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
                                const std::vector<double>& tol_slot, int min_iter,
-                               int max_iter) {
+                               int max_iter, int precision, double theta, int schur) {
   IKR_CHECK(s.have_gs, 2, "ground state not set up");
   const hipStream_t st = s.stream;
   CgWork<double>& w = s.w64;
@@ -153,13 +349,18 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   const size_t phik = (size_t)nbn * nbm;
   UpdTerm<double> none{};
   Chi0Result res;
+  // Q-projection rows: the occupied bands, or every computed band when the
+  // extra bands are treated by sum over states.
+  const bool use_schur = schur && s.nbands > s.nocc_max;
+  const int* dMq = use_schur ? s.d_nbands_k.get() : s.d_nocc_k.get();
+  const int Mq_max = use_schur ? s.nbands : s.nocc_max;
 
   // right-hand sides t_j = F(u F^-1 phi_j) into r
   launch_plane_hv<double>(s.geom, s.fft, all, s.d_Tphi.get(), w.T2.get(), u_int, 0, st);
   launch_col_fwd<double>(s.geom, s.fft, all, w.T2.get(), w.r.get(), nbm, nullptr, nullptr,
                          inv_ng, st);
   // M[j][m] = <phi_m, t_j>
-  gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
+  gram<double>(s.tiles, s.d_nb.get(), nbm, dMq, Mq_max, s.d_phi.get(), phik,
                nbm, w.r.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
   const std::vector<double2> M = download(w.coefA.get(), (size_t)J * MAXM, st);
 
@@ -189,160 +390,65 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
       const double al = fn * d / (fn * fn + fm * fm);
       dp[(size_t)j * MAXM + m] = cscale<double>(M[(size_t)j * MAXM + m], al);
     }
+    // extra computed bands: their part of the unoccupied response,
+    // <phi_m, t_n> / (e_n - e_m), by sum over states
+    if (use_schur)
+      for (int m = s.nocc_k[k]; m < nbn; ++m) {
+        const double em = s.eps[(size_t)k * nbn + m];
+        dp[(size_t)j * MAXM + m] = cscale<double>(M[(size_t)j * MAXM + m], 1.0 / (en - em));
+      }
   }
   const double defermi = den != 0.0 ? num / den : 0.0;
   for (int j = 0; j < J; ++j)
     df[j] = s.docc[(size_t)s.slot_k[j] * nbn + s.slot_n[j]] * (de[j] - defermi);
 
   // b = -Q t   (r = -t + Phi M)
-  UpdTerm<double> phiM{s.d_phi.get(), phik, nbm, s.d_nocc_k.get(), w.coefA.get(), MAXM, 1.0};
+  UpdTerm<double> phiM{s.d_phi.get(), phik, nbm, dMq, w.coefA.get(), MAXM, 1.0};
   update<double>(s.tiles, s.d_nb.get(), nbm, nullptr, w.r.get(), nbm, -1.0, phiM, none,
                  nullptr, nullptr, st);
 
-  // CG start: x = 0, p = 0, z = Q M^-1 r, rz = <r, z>
-  IKR_HIP(hipMemsetAsync(w.x.get(), 0, (size_t)J * nbm * sizeof(double2), st));
-  IKR_HIP(hipMemsetAsync(w.p.get(), 0, (size_t)J * nbm * sizeof(double2), st));
-  std::vector<double> tol2(J);
-  for (int j = 0; j < J; ++j) tol2[j] = tol_slot[j] * tol_slot[j];
-  IKR_HIP(hipMemcpyAsync(s.d_tol2.get(), tol2.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
-  std::vector<int> ones(J, 1);
-  IKR_HIP(hipMemcpyAsync(s.d_active.get(), ones.data(), J * sizeof(int), hipMemcpyHostToDevice, st));
-  IKR_HIP(hipMemsetAsync(s.d_iters.get(), 0, J * sizeof(int), st));
-  IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, 4 * sizeof(int), st));
-  CgScalars<double> cs{w.rz.get(), w.alpha.get(), w.beta.get(), w.rnorm2.get(), s.d_tol2.get(),
-                       s.d_iters.get(), s.d_counters.get(), s.d_counters.get() + 1,
-                       min_iter, max_iter};
-  const int nup = update_nblocks(nbm), nvb = vec_nblocks(nbm);
-  UpdTerm<double> phiA{s.d_phi.get(), phik, nbm, s.d_nocc_k.get(), w.coefA.get(), MAXM, -1.0};
-  UpdTerm<double> projB{s.d_proj.get(), (size_t)s.natoms * nbm, nbm, s.d_natoms_k.get(),
-                        w.coefB.get(), MAXM, s.dnl};
-
-  precond<double>(J, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, w.pshift.get(),
-                  w.r.get(), w.w.get(), st);
-  gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
-               nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
-  update<double>(s.tiles, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA, none,
-                 w.r.get(), w.dpart.get(), st);
-  cg_scalars<double>(J, nup, w.dpart.get(), 2, s.d_active.get(), cs, 1, st);
-
-  // Algorithmic bytes per band (FP64 complex = 16 B) for the kernel timer:
-  // mean sphere size and footprint over the slots.
-  double nb_avg = 0, ncol_avg = 0;
-  for (int j = 0; j < J; ++j) {
-    nb_avg += s.kp[s.slot_k[j]].nb;
-    ncol_avg += s.kp[s.slot_k[j]].ncol;
+  // Per-band precision: bands whose tolerance is loose relative to their
+  // right-hand side run the CG in FP32 (FP32 FFTs and projections); the
+  // others, and everything after the CG, stay in FP64.
+  std::vector<int> m64(J, 1), m32(J, 0);
+  int n32 = 0;
+  if (precision == 1) {
+    const std::vector<double> bn = slot_norms(s, w.r.get());
+    for (int j = 0; j < J; ++j)
+      if (tol_slot[j] >= theta * bn[j]) { m32[j] = 1; m64[j] = 0; ++n32; }
   }
-  nb_avg /= J;
+  const CgOut o64 = run_cg<double>(s, s.w64, w.r.get(), m64, tol_slot, min_iter, max_iter,
+                                   dMq, Mq_max);
+  res.n_ham64 = o64.n_ham;
+  res.noconv = o64.noconv;
+  if (n32 > 0) {
+    ensure_fp32(s);
+    std::vector<int> l32;
+    for (int j = 0; j < J; ++j)
+      if (m32[j]) l32.push_back(j);
+    DBuf<int> dl32;
+    dl32.upload(l32, st);
+    convert_slots(n32, dl32.get(), s.d_slot_k.get(), s.d_nb.get(), nbm, w.r.get(), s.w32.r.get(), st);
+    const CgOut o32 = run_cg<float>(s, s.w32, s.w32.r.get(), m32, tol_slot, min_iter,
+                                      max_iter, dMq, Mq_max);
+    convert_slots(n32, dl32.get(), s.d_slot_k.get(), s.d_nb.get(), nbm, s.w32.x.get(), w.x.get(), st);
+    res.n_ham32 = o32.n_ham;
+    res.noconv += o32.noconv;
+  }
+  res.n_ham = res.n_ham64 + res.n_ham32;
+  UpdTerm<double> phiA{s.d_phi.get(), phik, nbm, dMq, w.coefA.get(), MAXM, -1.0};
+  const double S16 = 16.0;
+  double ncol_avg = 0;
+  for (int j = 0; j < J; ++j) ncol_avg += s.kp[s.slot_k[j]].ncol;
   ncol_avg /= J;
-  const double S16 = 16.0, colC = ncol_avg * s.L.C;
-  // Compact active set: the slots still iterating and per-k tiles of them.
-  std::vector<int> hflag(J, 1), hlist(J), htk, hto, htn;
-  int nct = 0;
-  auto rebuild = [&]() {
-    int na = 0;
-    htk.clear(); hto.clear(); htn.clear();
-    for (int k = 0; k < s.nk; ++k) {
-      const int j0 = s.slot0_k[k], j1 = j0 + s.nocc_k[k];
-      int cnt = 0;
-      for (int j = j0; j < j1; ++j) {
-        if (!hflag[j]) continue;
-        if (cnt % BT == 0) {
-          htk.push_back(k);
-          hto.push_back(na);
-          htn.push_back(0);
-        }
-        hlist[na++] = j;
-        ++htn.back();
-        ++cnt;
-      }
-    }
-    nct = (int)htk.size();
-    IKR_HIP(hipMemcpyAsync(s.d_list.get(), hlist.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
-    IKR_HIP(hipMemcpyAsync(s.d_ctk.get(), htk.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
-    IKR_HIP(hipMemcpyAsync(s.d_cto.get(), hto.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
-    IKR_HIP(hipMemcpyAsync(s.d_ctn.get(), htn.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
-    IKR_HIP(hipStreamSynchronize(st));
-    return na;
-  };
-  int nact = rebuild();
-  for (int it = 0; it < max_iter && nact > 0; ++it) {
-    Slots act{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get()};
-    Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get()};
-    auto tile_bytes = [&](double M, bool upd, bool dot) {
-      // W read once per tile, X read (gram) or Y read+write (+ D read) per slot
-      return nct * M * nb_avg * S16 + nact * nb_avg * S16 * (upd ? (dot ? 3.0 : 2.0) : 1.0);
-    };
-    // p = z + beta p ; w = (H - e) p  (local part through the pruned FFT)
-    KTimer::begin(K_COL_INV, st);
-    launch_col_inv<double>(s.geom, s.fft, act, w.p.get(), nbm, w.T1.get(), w.w.get(),
-                           w.beta.get(), w.p.get(), st);
-    KTimer::end(K_COL_INV, st, nact * (3.0 * nb_avg + colC) * S16);
-    KTimer::begin(K_PLANE_HV, st);
-    launch_plane_hv<double>(s.geom, s.fft, act, w.T1.get(), w.T2.get(), s.d_vloc.get(), 0, st);
-    KTimer::end(K_PLANE_HV, st, nact * 2.0 * colC * S16 + 8.0 * s.ng);
-    KTimer::begin(K_COL_FWD, st);
-    launch_col_fwd<double>(s.geom, s.fft, act, w.T2.get(), w.w.get(), nbm, w.p.get(),
-                           w.shift.get(), inv_ng, st);
-    KTimer::end(K_COL_FWD, st, nact * (colC * S16 + nb_avg * (2.0 * S16 + 8.0)));
-    if (s.natoms > 0) {
-      KTimer::begin(K_GRAM, st);
-      gram<double>(ctl, s.d_nb.get(), nbm, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
-                   (size_t)s.natoms * nbm, nbm, w.p.get(), nbm, w.part.get(), w.coefB.get(),
-                   MAXM, st);
-      KTimer::end(K_GRAM, st, tile_bytes(s.natoms, false, false));
-      KTimer::begin(K_UPDATE, st);
-      update<double>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, 1.0, projB,
-                     none, nullptr, nullptr, st);
-      KTimer::end(K_UPDATE, st, tile_bytes(s.natoms, true, false));
-    }
-    // Ap = Q w ; pAp
-    KTimer::begin(K_GRAM, st);
-    gram<double>(ctl, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
-                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
-    KTimer::end(K_GRAM, st, tile_bytes(s.nocc_max, false, false));
-    KTimer::begin(K_UPDATE, st);
-    update<double>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, 1.0, phiA,
-                   none, w.p.get(), w.dpart.get(), st);
-    KTimer::end(K_UPDATE, st, tile_bytes(s.nocc_max, true, true));
-    cg_scalars<double>(nact, nup, w.dpart.get(), 0, s.d_active.get(), cs, 0, st,
-                       s.d_list.get());
-    // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, convergence
-    KTimer::begin(K_CG_STEP, st);
-    cg_step<double>(nact, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, nullptr,
-                    w.alpha.get(), w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(),
-                    w.dpart.get(), st, s.d_list.get());
-    KTimer::end(K_CG_STEP, st, nact * nb_avg * (7.0 * S16 + 8.0));
-    cg_scalars<double>(nact, nvb, w.dpart.get(), 1, s.d_active.get(), cs, 0, st,
-                       s.d_list.get());
-    // z = Q M^-1 r, rz = <r, z>, beta (bands that just converged are skipped)
-    KTimer::begin(K_GRAM, st);
-    gram<double>(ctl, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
-                 nbm, w.w.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st, s.d_active.get());
-    KTimer::end(K_GRAM, st, tile_bytes(s.nocc_max, false, false));
-    KTimer::begin(K_UPDATE, st);
-    update<double>(ctl, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, 1.0, phiA,
-                   none, w.r.get(), w.dpart.get(), st);
-    KTimer::end(K_UPDATE, st, tile_bytes(s.nocc_max, true, true));
-    cg_scalars<double>(nact, nup, w.dpart.get(), 2, s.d_active.get(), cs, 0, st,
-                       s.d_list.get());
-    res.n_ham += nact;
-    IKR_HIP(hipMemcpyAsync(hflag.data(), s.d_active.get(), J * sizeof(int),
-                           hipMemcpyDeviceToHost, st));
-    IKR_HIP(hipStreamSynchronize(st));
-    nact = rebuild();
-  }
-  res.n_ham64 = res.n_ham;
-  int noconv = 0;
-  IKR_HIP(hipMemcpyAsync(&noconv, s.d_counters.get() + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-  IKR_HIP(hipStreamSynchronize(st));
-  res.noconv = noconv + nact;
+  const double colC = ncol_avg * s.L.C;
 
   // final projection and occupied part: dphi = x - Phi Phi^H x + Phi dP
-  gram<double>(s.tiles, s.d_nb.get(), nbm, s.d_nocc_k.get(), s.nocc_max, s.d_phi.get(), phik,
+  gram<double>(s.tiles, s.d_nb.get(), nbm, dMq, Mq_max, s.d_phi.get(), phik,
                nbm, w.x.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
   IKR_HIP(hipMemcpyAsync(w.coefB.get(), dp.data(), dp.size() * sizeof(double2),
                          hipMemcpyHostToDevice, st));
-  UpdTerm<double> phiB{s.d_phi.get(), phik, nbm, s.d_nocc_k.get(), w.coefB.get(), MAXM, 1.0};
+  UpdTerm<double> phiB{s.d_phi.get(), phik, nbm, dMq, w.coefB.get(), MAXM, 1.0};
   update<double>(s.tiles, s.d_nb.get(), nbm, nullptr, w.x.get(), nbm, 1.0, phiA, phiB, nullptr,
                  nullptr, st);
 
@@ -371,7 +477,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
 // Prefactor of Table 1 in its k-point form (Table strategies_k, with the
 // per-k occupied counts replaced by the total N_occ as in the paper's runs).
 static std::vector<double> prefactors(const System& s, int strategy, double knorm,
-                                      double bnorm) {
+                                      double bnorm, bool schur) {
   std::vector<double> p(s.J, 1.0);
   const double nocc_tot = s.J;
   for (int j = 0; j < s.J; ++j) {
@@ -388,11 +494,13 @@ static std::vector<double> prefactors(const System& s, int strategy, double knor
       case IKR_THM2: {
         // C_{i,nk} of Theorem 2 in its k-point form; where every computed band
         // is occupied the gap is taken to the highest computed band (>= 1e-4 Ha)
+        // With the extra bands taken by sum over states the CG operator's
+        // smallest eigenvalue is e_{nbands+1} - e_n >= e_{nbands} - e_n.
         const int n = s.slot_n[j], no = s.nocc_k[k];
         const double en = s.eps[(size_t)k * s.nbands + n];
-        const double eup = no < s.nbands ? s.eps[(size_t)k * s.nbands + no]
-                                         : s.eps[(size_t)k * s.nbands + s.nbands - 1];
-        const double gap = std::max(eup - en, no < s.nbands ? 0.0 : 1e-4);
+        const double eup = (no < s.nbands && !schur) ? s.eps[(size_t)k * s.nbands + no]
+                                                     : s.eps[(size_t)k * s.nbands + s.nbands - 1];
+        const double gap = std::max(eup - en, (no < s.nbands && !schur) ? 0.0 : 1e-4);
         p[j] = std::sqrt(s.volume) * gap /
                (2.0 * f * wk * knorm * s.orbnorm_full_k[k] * s.nk *
                 std::sqrt((double)s.ng * no));
@@ -421,10 +529,11 @@ void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext, double
     return;
   }
   scale_copy(s.ng, s.d_u.get(), 1.0 / nu, s.d_u.get(), st);
-  std::vector<double> tol = prefactors(s, o.strategy, nu, bnorm);
+  std::vector<double> tol = prefactors(s, o.strategy, nu, bnorm,
+                                       o.schur && s.nbands > s.nocc_max);
   for (double& t : tol) t *= common;
   Chi0Result r = apply_chi0_internal(s, s.d_u.get(), s.d_drho.get(), tol, o.cg_min_iter,
-                                     o.cg_max_iter);
+                                     o.cg_max_iter, o.precision, o.fp32_theta, o.schur);
   if (stt) {
     stt->n_ham += r.n_ham;
     stt->n_ham_fp64 += r.n_ham64;

@@ -94,7 +94,7 @@ struct System {
   // occupied slots and tiles
   int J = 0;
   std::vector<int> slot_k, slot_n, slot0_k;   // slot0_k: first slot of each k
-  DBuf<int> d_slot_k, d_nocc_k, d_natoms_k;
+  DBuf<int> d_slot_k, d_nocc_k, d_natoms_k, d_nbands_k;
   std::vector<int> tile_k, tile_slot0, tile_nb;
   DBuf<int> d_tile_k, d_tile_slot0, d_tile_nb;
   Tiles tiles{};
@@ -136,7 +136,9 @@ struct Chi0Result {
 };
 Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
                                const std::vector<double>& tol_slot, int min_iter,
-                               int max_iter);
+                               int max_iter, int precision = 0, double theta = 1e-5,
+                               int schur = 0);
+void ensure_fp32(System& s);   // FP32 work space and operator copies (lazy)
 void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext,
                           double common, const ikr_solver_opts& o, double bnorm,
                           ikr_stats* st);

@@ -112,3 +112,43 @@ def test_solve_response_cfg1_against_oracle_gmres():
     x, st = rs.solve(to_dev(b), default_opts(strategy="grt", tol=1e-10))
     assert rel(to_host(x), ref.x) < 1e-8
     assert st["gmres_iters"] > 0
+
+
+@pytest.mark.parametrize("strategy", ["bal", "grt", "thm2"])
+def test_mixed_precision_solve_matches_dense(tiny_dense, strategy):
+    """FP32 Sternheimer CG where the adaptive tolerance is loose, FP64 for the
+    rest and for everything around the CG: same accuracy bounds as FP64."""
+    from paper_2505_02319_amd import default_opts
+    rs, osys, emat = tiny_dense
+    b = random_field(osys.spec, 2)
+    x, st = rs.solve(to_dev(b), default_opts(strategy=strategy, tol=1e-8, precision=1,
+                                             fp32_theta=1e-5, want_true_residual=1))
+    x = to_host(x).ravel()
+    tau = 1e-8 * np.linalg.norm(b)
+    true_r = np.linalg.norm(b.ravel() - emat @ x)
+    if strategy != "thm2":   # thm2's gap factor can keep every band below theta
+        assert st["n_ham_fp32"] > 0
+    assert st["n_ham_fp32"] + st["n_ham_fp64"] == st["n_ham"]
+    if strategy in ("grt", "thm2"):
+        assert true_r <= tau
+    assert true_r <= 3 * tau
+    assert rel(x, np.linalg.solve(emat, b.ravel())) < 1e-7
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_metal"])
+def test_extra_band_split_matches_plain_and_dense(name):
+    """The computed unoccupied bands taken by sum over states (CG on the
+    complement of all computed bands) give the same E v as the plain
+    occupied-complement CG and as the dense operator."""
+    from oracle.response import HxcKernel, SumOverStates
+    from paper_2505_02319_amd import default_opts
+    rs, osys, ogs, perms = gpu_system(name)
+    kern = HxcKernel(osys, ogs.rho, xc=1)
+    chi = SumOverStates(osys, ogs).dense_matrix()
+    v = random_field(osys.spec, 2)
+    ref = v.ravel() - chi @ kern.apply(v).ravel()
+    e1, s1 = rs.apply_dielectric(to_dev(v), 1e-13, default_opts(strategy="fixed", schur=1))
+    e0, s0 = rs.apply_dielectric(to_dev(v), 1e-13, default_opts(strategy="fixed", schur=0))
+    assert rel(to_host(e1), ref) < 1e-9
+    assert rel(to_host(e0), ref) < 1e-9
+    assert s1["n_ham"] <= s0["n_ham"]
