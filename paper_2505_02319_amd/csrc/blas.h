@@ -31,6 +31,7 @@ template <typename R> struct UpdTerm {
   const cplx<R>* C = nullptr;
   int cs = 0;              // slot stride of C
   R alpha = 0;
+  int Mmax = MAXM;         // bound on Mk over all k (sizes the coefficient LDS)
 };
 
 template <typename R> struct CgScalars {

@@ -9,15 +9,16 @@
 // bitwise reproducible run to run.
 #include "blas.h"
 
+#include <algorithm>
+
 namespace ikr {
 namespace {
 
 constexpr int NT = 256;
 constexpr int CH = 64;        // elements per inner chunk of the gram kernel
-constexpr int MT = 16;        // projector rows per gram pass
+constexpr int GRAM_BLOCKS = 2048;   // gram blocks aimed for (8 per CU)
+constexpr int UPD_BLOCKS = 1024;    // update blocks below which tiles are split
 
-// part[((t * nsc + sc) * Mmax + m) * BT + b] = sum_{g in super-chunk}
-//                                 conj(W[k][m][g]) X[slot0 + b][g]
 // True when some slot of tile t takes part (active == null: all do).
 __device__ __forceinline__ bool tile_live(const Tiles& tl, int t, const int* active) {
   if (!active) return true;
@@ -33,46 +34,99 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-template <typename R>
+// part[((t * nsc + sc) * Mmax + m) * BT + b] = sum_{g in super-chunk}
+//                                 conj(W[k][m][g]) X[slot0 + b][g]
+//
+// Chunks of CH coefficients of the tile's BT bands and of MT projector rows
+// are staged in LDS.  Each thread owns a 4 x 4 block of the MT x BT output
+// (rows 4mi.., bands 4bi..) over one of KS = NT / MT interleaved slices of
+// the chunk, so every LDS value it reads feeds four complex multiply-adds;
+// the slices are summed by shuffles inside a wavefront, then across waves.
+template <typename R, int MT>
 __global__ __launch_bounds__(NT) void gram_kernel(
     Tiles tl, const int* __restrict__ nb, const int* __restrict__ Mk, int Mmax,
     const cplx<R>* __restrict__ W, size_t wk_stride, int w_stride,
     const cplx<R>* __restrict__ X, int x_stride, int nsc, int sc_len,
     cplx<R>* __restrict__ part, const int* __restrict__ active) {
-  __shared__ cplx<R> Xs[BT][CH + 1];
-  __shared__ cplx<R> Ws[MT][CH + 1];
+  constexpr int KS = NT / MT;             // slices per chunk
+  constexpr int LW = CH + 1;
+  constexpr int NWAVE = NT / 64;
+  constexpr int STAGE = (BT + MT) * LW, RED = NWAVE * MT * BT;
+  __shared__ cplx<R> smem[STAGE > RED ? STAGE : RED];
   __shared__ int ss[BT];
+  cplx<R>* Xs = smem;                     // [BT][LW]
+  cplx<R>* Ws = smem + BT * LW;           // [MT][LW]
+  cplx<R>* red = smem;                    // [NWAVE][MT * BT], after the chunks
   const int t = blockIdx.y, sc = blockIdx.x, tid = threadIdx.x;
   if (!tile_live(tl, t, active)) return;
   const int k = tl.k[t], nbt = tl.nb[t];
   const int M = Mk[k], n = nb[k];
   if (tid < BT) ss[tid] = tid < nbt ? tslot(tl, t, tid) : 0;
   __syncthreads();
-  const int i_out = tid / BT, b_out = tid % BT;
+  const int sb = tid % MT, mi = sb >> 2, bi = sb & 3, ks = tid / MT;
+  const int wave = tid >> 6, lane = tid & 63;
   const cplx<R>* Wk = W + (size_t)k * wk_stride;
+  const int gbeg = sc * sc_len, gend = min(n, gbeg + sc_len);
   for (int m0 = 0; m0 < M; m0 += MT) {
-    cplx<R> acc = mk<R>(0, 0);
-    const int gbeg = sc * sc_len, gend = min(n, gbeg + sc_len);
+    R ar[4][4], ai[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = R(0);
     for (int g0 = gbeg; g0 < gend; g0 += CH) {
       for (int i = tid; i < BT * CH; i += NT) {
         const int b = i / CH, e = i % CH, gg = g0 + e;
-        Xs[b][e] = (b < nbt && gg < gend) ? X[(size_t)ss[b] * x_stride + gg] : mk<R>(0, 0);
+        Xs[b * LW + e] = (b < nbt && gg < gend) ? X[(size_t)ss[b] * x_stride + gg] : mk<R>(0, 0);
       }
       for (int i = tid; i < MT * CH; i += NT) {
         const int m = i / CH, e = i % CH, gg = g0 + e;
-        Ws[m][e] = (m0 + m < M && gg < gend) ? Wk[(size_t)(m0 + m) * w_stride + gg] : mk<R>(0, 0);
+        Ws[m * LW + e] = (m0 + m < M && gg < gend) ? Wk[(size_t)(m0 + m) * w_stride + gg]
+                                                   : mk<R>(0, 0);
       }
       __syncthreads();
-#pragma unroll 8
-      for (int e = 0; e < CH; ++e) {
-        const cplx<R> w = Ws[i_out][e], x = Xs[b_out][e];
-        acc.x += w.x * x.x + w.y * x.y;
-        acc.y += w.x * x.y - w.y * x.x;
+#pragma unroll
+      for (int u = 0; u < CH / KS; ++u) {
+        const int e = ks + KS * u;
+        cplx<R> w[4], x[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = Ws[(4 * mi + i) * LW + e];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[j] = Xs[(4 * bi + j) * LW + e];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            ar[i][j] += w[i].x * x[j].x + w[i].y * x[j].y;
+            ai[i][j] += w[i].x * x[j].y - w[i].y * x[j].x;
+          }
       }
       __syncthreads();
     }
-    if (m0 + i_out < M)
-      part[(((size_t)t * nsc + sc) * Mmax + m0 + i_out) * BT + b_out] = acc;
+    // the slices held by one wavefront sit in lanes sb, sb + MT, ...
+#pragma unroll
+    for (int o = MT; o < 64; o <<= 1)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          ar[i][j] += __shfl_xor(ar[i][j], o, 64);
+          ai[i][j] += __shfl_xor(ai[i][j], o, 64);
+        }
+    if (lane < MT)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          red[wave * MT * BT + (4 * mi + i) * BT + 4 * bi + j] = mk<R>(ar[i][j], ai[i][j]);
+    __syncthreads();
+    for (int o = tid; o < MT * BT; o += NT) {
+      const int m = o / BT, b = o % BT;
+      cplx<R> v = red[o];
+#pragma unroll
+      for (int w = 1; w < NWAVE; ++w) v = cadd<R>(v, red[w * MT * BT + o]);
+      if (m0 + m < M) part[(((size_t)t * nsc + sc) * Mmax + m0 + m) * BT + b] = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -104,55 +158,69 @@ __global__ __launch_bounds__(NT) void gram_reduce_kernel(
 
 // Y[slot][g] = a * Y[slot][g] + sum_j alpha_j sum_m W_j[k][m][g] coef_j[slot][m]
 // for up to two (W, coef) sets; optional per-slot mask; optional partial
-// dot <D, Y_new> (real part) per (slot, block) into dpart[slot * gridDim.x + bx].
-template <typename R>
+// dot <D, Y_new> (real part) per (slot, block) into dpart[slot * nparts + gb].
+// A block takes NT coefficients g of BPT bands of its tile: BT / BPT band
+// groups split a tile when there are few tiles.  Blocks that share a range
+// of g (and so the rows of W they read) are launched 8 apart, which puts
+// them on the same XCD and its L2.  The coefficients sit in dynamic LDS,
+// BPT * (M1max + M2max) entries.
+template <typename R, int BPT>
 __global__ __launch_bounds__(NT) void update_kernel(
     Tiles tl, const int* __restrict__ nb, const int* __restrict__ active,
     cplx<R>* __restrict__ Y, int y_stride, R a,
     const cplx<R>* __restrict__ W1, size_t w1k, int w1s, const int* __restrict__ M1k,
-    const cplx<R>* __restrict__ C1, int c1s, R alpha1,
+    const cplx<R>* __restrict__ C1, int c1s, R alpha1, int M1max,
     const cplx<R>* __restrict__ W2, size_t w2k, int w2s, const int* __restrict__ M2k,
-    const cplx<R>* __restrict__ C2, int c2s, R alpha2,
-    const cplx<R>* __restrict__ D, R* __restrict__ dpart) {
-  __shared__ cplx<R> c1[BT][MAXM];
-  __shared__ cplx<R> c2[BT][MAXM];
-  __shared__ R red[NT];
-  __shared__ int ss[BT];
+    const cplx<R>* __restrict__ C2, int c2s, R alpha2, int M2max,
+    const cplx<R>* __restrict__ D, R* __restrict__ dpart, int nparts) {
+  constexpr int G = BT / BPT;
+  extern __shared__ __align__(16) unsigned char upd_smem[];
+  cplx<R>* c1 = reinterpret_cast<cplx<R>*>(upd_smem);   // [BPT][M1max]
+  cplx<R>* c2 = c1 + BPT * M1max;                          // [BPT][M2max]
+  __shared__ R red[(NT / 64) * BPT];
+  __shared__ int ss[BPT];
   const int t = blockIdx.y, tid = threadIdx.x;
+  const int grp = (blockIdx.x >> 3) % G;
+  const int gb = (blockIdx.x / (8 * G)) * 8 + (blockIdx.x & 7);
   if (!tile_live(tl, t, active)) return;
-  const int k = tl.k[t], nbt = tl.nb[t];
+  const int k = tl.k[t];
+  const int nbg = min(BPT, tl.nb[t] - grp * BPT);     // bands of this group
+  if (nbg <= 0) return;
   const int n = nb[k];
-  const int M1 = W1 ? M1k[k] : 0, M2 = W2 ? M2k[k] : 0;
-  if (tid < BT) ss[tid] = tid < nbt ? tslot(tl, t, tid) : 0;
+  const int M1 = W1 ? min(M1k[k], M1max) : 0, M2 = W2 ? min(M2k[k], M2max) : 0;
+  if (tid < BPT) ss[tid] = tid < nbg ? tslot(tl, t, grp * BPT + tid) : 0;
   __syncthreads();
-  for (int i = tid; i < BT * MAXM; i += NT) {
-    const int b = i / MAXM, m = i % MAXM;
-    c1[b][m] = (b < nbt && m < M1) ? cscale<R>(C1[(size_t)ss[b] * c1s + m], alpha1) : mk<R>(0, 0);
-    c2[b][m] = (b < nbt && m < M2) ? cscale<R>(C2[(size_t)ss[b] * c2s + m], alpha2) : mk<R>(0, 0);
+  for (int i = tid; i < BPT * M1max; i += NT) {
+    const int b = i / M1max, m = i % M1max;
+    c1[i] = (b < nbg && m < M1) ? cscale<R>(C1[(size_t)ss[b] * c1s + m], alpha1) : mk<R>(0, 0);
+  }
+  for (int i = tid; i < BPT * M2max; i += NT) {
+    const int b = i / M2max, m = i % M2max;
+    c2[i] = (b < nbg && m < M2) ? cscale<R>(C2[(size_t)ss[b] * c2s + m], alpha2) : mk<R>(0, 0);
   }
   __syncthreads();
-  const int g = blockIdx.x * NT + tid;
-  cplx<R> acc[BT];
+  const int g = gb * NT + tid;
+  cplx<R> acc[BPT];
 #pragma unroll
-  for (int b = 0; b < BT; ++b) acc[b] = mk<R>(0, 0);
+  for (int b = 0; b < BPT; ++b) acc[b] = mk<R>(0, 0);
   if (g < n) {
     const cplx<R>* w1 = W1 ? W1 + (size_t)k * w1k + g : nullptr;
     for (int m = 0; m < M1; ++m) {
       const cplx<R> w = w1[(size_t)m * w1s];
 #pragma unroll
-      for (int b = 0; b < BT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c1[b][m]));
+      for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c1[b * M1max + m]));
     }
     const cplx<R>* w2 = W2 ? W2 + (size_t)k * w2k + g : nullptr;
     for (int m = 0; m < M2; ++m) {
       const cplx<R> w = w2[(size_t)m * w2s];
 #pragma unroll
-      for (int b = 0; b < BT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c2[b][m]));
+      for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c2[b * M2max + m]));
     }
   }
 #pragma unroll
-  for (int b = 0; b < BT; ++b) {
+  for (int b = 0; b < BPT; ++b) {
     const int slot = ss[b];
-    const bool on = b < nbt && (!active || active[slot]);
+    const bool on = b < nbg && (!active || active[slot]);
     R d = 0;
     if (on && g < n) {
       cplx<R>* yp = Y + (size_t)slot * y_stride + g;
@@ -164,15 +232,18 @@ __global__ __launch_bounds__(NT) void update_kernel(
         d = dd.x * y.x + dd.y * y.y;
       }
     }
-    if (dpart && b < nbt) {
-      red[tid] = d;
-      __syncthreads();
-      for (int w = NT / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] += red[tid + w];
-        __syncthreads();
-      }
-      if (tid == 0) dpart[(size_t)slot * gridDim.x + blockIdx.x] = red[0];
-      __syncthreads();
+    if (dpart) {
+      d = wave_sum(d);
+      if ((tid & 63) == 0) red[(tid >> 6) * BPT + b] = d;
+    }
+  }
+  if (dpart) {
+    __syncthreads();
+    if (tid < nbg) {
+      R v = red[tid];
+#pragma unroll
+      for (int w = 1; w < NT / 64; ++w) v += red[w * BPT + tid];
+      dpart[(size_t)ss[tid] * nparts + gb] = v;
     }
   }
 }
@@ -425,19 +496,25 @@ __global__ void cscale_kernel(size_t n, cplx<R>* __restrict__ x, R a) {
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-static int nsc_for(int nb_max, int& sc_len) {
-  int nch = (nb_max + CH - 1) / CH;
-  int nsc = nch < 96 ? nch : 96;
-  int per = (nch + nsc - 1) / nsc;
+// Super-chunks per tile: enough blocks to fill the chip (about
+// GRAM_BLOCKS over all tiles), each at least one chunk long.
+static int nsc_for(int nb_max, int ntiles, int& sc_len) {
+  const int nch = (nb_max + CH - 1) / CH;
+  const int want = (GRAM_BLOCKS + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
+  int nsc = std::max(1, std::min(nch, want));
+  const int per = (nch + nsc - 1) / nsc;
   sc_len = per * CH;
   nsc = (nb_max + sc_len - 1) / sc_len;
   return nsc;
 }
 
 size_t gram_part_elems(int ntiles, int nb_max, int Mmax) {
-  int sc_len;
-  const int nsc = nsc_for(nb_max, sc_len);
-  return (size_t)ntiles * nsc * Mmax * BT;
+  size_t most = 0;
+  for (int t = 1; t <= ntiles; ++t) {
+    int sc_len;
+    most = std::max(most, (size_t)t * nsc_for(nb_max, t, sc_len));
+  }
+  return most * Mmax * BT;
 }
 
 template <typename R>
@@ -448,10 +525,15 @@ void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
   IKR_CHECK(Mmax <= MAXM, 1, "too many projector rows");
   IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Mk && W && X && part && coef, 8,
             "gram: null device pointer");
+  if (tl.n <= 0) return;
   int sc_len;
-  const int nsc = nsc_for(nb_max, sc_len);
-  hipLaunchKernelGGL((gram_kernel<R>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, Mk,
-                     Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part, active);
+  const int nsc = nsc_for(nb_max, tl.n, sc_len);
+  if (Mmax <= 16)
+    hipLaunchKernelGGL((gram_kernel<R, 16>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, Mk,
+                       Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part, active);
+  else
+    hipLaunchKernelGGL((gram_kernel<R, 32>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, Mk,
+                       Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part, active);
   IKR_HIP(hipGetLastError());
   const int outs_per_block = NT / 64;
   hipLaunchKernelGGL((gram_reduce_kernel<R>),
@@ -460,7 +542,9 @@ void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
   IKR_HIP(hipGetLastError());
 }
 
-int update_nblocks(int nb_max) { return (nb_max + NT - 1) / NT; }
+// Partials per slot of the update's dot: NT-wide blocks of g, padded to a
+// multiple of 8 (the XCD interleave of the launch).
+int update_nblocks(int nb_max) { return ((nb_max + NT - 1) / NT + 7) / 8 * 8; }
 
 template <typename R>
 void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
@@ -469,10 +553,22 @@ void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
   IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Y, 8, "update: null device pointer");
   IKR_CHECK((!t1.W || (t1.Mk && t1.C)) && (!t2.W || (t2.Mk && t2.C)), 8,
             "update: null coefficient pointer");
-  hipLaunchKernelGGL((update_kernel<R>), dim3(update_nblocks(nb_max), tl.n), dim3(NT), 0,
-                     st, tl, nb, active, Y, y_stride, a, t1.W, t1.wk, t1.ws, t1.Mk,
-                     t1.C, t1.cs, t1.alpha, t2.W, t2.wk, t2.ws, t2.Mk, t2.C, t2.cs,
-                     t2.alpha, D, dpart);
+  const int M1max = t1.W ? t1.Mmax : 0, M2max = t2.W ? t2.Mmax : 0;
+  IKR_CHECK(M1max <= MAXM && M2max <= MAXM, 1, "update: too many projector rows");
+  if (tl.n <= 0) return;
+  const int ngb = update_nblocks(nb_max);
+  const int blocks = ngb * tl.n;
+  const int bpt = blocks >= UPD_BLOCKS ? 16 : (2 * blocks >= UPD_BLOCKS ? 8 : 4);
+  const size_t lds = (size_t)bpt * (M1max + M2max) * sizeof(cplx<R>);
+  const dim3 grid(ngb * (BT / bpt), tl.n);
+#define IKR_UPD(B)                                                                    \
+  hipLaunchKernelGGL((update_kernel<R, B>), grid, dim3(NT), lds, st, tl, nb, active, Y,  \
+                     y_stride, a, t1.W, t1.wk, t1.ws, t1.Mk, t1.C, t1.cs, t1.alpha, M1max, \
+                     t2.W, t2.wk, t2.ws, t2.Mk, t2.C, t2.cs, t2.alpha, M2max, D, dpart, ngb)
+  if (bpt == 16) IKR_UPD(16);
+  else if (bpt == 8) IKR_UPD(8);
+  else IKR_UPD(4);
+#undef IKR_UPD
   IKR_HIP(hipGetLastError());
 }
 

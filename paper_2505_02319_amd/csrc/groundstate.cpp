@@ -217,7 +217,7 @@ void compute_ground_state(System& s) {
       gram<double>(tl, s.d_nb.get(), nbm, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
                    (size_t)s.natoms * nbm, nbm, Y, nbm, part.get(), pcoef.get(), MAXM, st);
       UpdTerm<double> t{s.d_proj.get(), (size_t)s.natoms * nbm, nbm, s.d_natoms_k.get(),
-                        pcoef.get(), MAXM, s.dnl};
+                        pcoef.get(), MAXM, s.dnl, s.natoms};
       update<double>(tl, s.d_nb.get(), nbm, nullptr, Z, nbm, 1.0, t, UpdTerm<double>{}, nullptr,
                      nullptr, st);
     }

@@ -123,7 +123,7 @@ void apply_hamiltonian(System& s, int k, int nvec, const double2* x, double2* y)
                  (size_t)s.natoms * s.nb_max, s.nb_max, x, s.nb_max, part.get(), coef.get(),
                  MAXM, st);
     UpdTerm<double> t1{s.d_proj.get(), (size_t)s.natoms * s.nb_max, s.nb_max,
-                       s.d_natoms_k.get(), coef.get(), MAXM, s.dnl};
+                       s.d_natoms_k.get(), coef.get(), MAXM, s.dnl, s.natoms};
     update<double>(tl, s.d_nb.get(), s.nb_max, nullptr, y, s.nb_max, 1.0, t1, UpdTerm<double>{},
                    nullptr, nullptr, st);
   }
@@ -208,9 +208,9 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
                   s.d_iters.get(), s.d_counters.get(), s.d_counters.get() + 1,
                   min_iter, max_iter};
   const int nup = update_nblocks(nbm), nvb = vec_nblocks(nbm);
-  UpdTerm<R> phiA{phi, phik, nbm, dMq, w.coefA.get(), MAXM, R(-1)};
+  UpdTerm<R> phiA{phi, phik, nbm, dMq, w.coefA.get(), MAXM, R(-1), Mq_max};
   UpdTerm<R> projB{proj, (size_t)s.natoms * nbm, nbm, s.d_natoms_k.get(), w.coefB.get(), MAXM,
-                   R(s.dnl)};
+                   R(s.dnl), s.natoms};
 
   // Algorithmic bytes per band for the kernel timer: mean sphere and footprint.
   double nb_avg = 0, ncol_avg = 0;
@@ -403,7 +403,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     df[j] = s.docc[(size_t)s.slot_k[j] * nbn + s.slot_n[j]] * (de[j] - defermi);
 
   // b = -Q t   (r = -t + Phi M)
-  UpdTerm<double> phiM{s.d_phi.get(), phik, nbm, dMq, w.coefA.get(), MAXM, 1.0};
+  UpdTerm<double> phiM{s.d_phi.get(), phik, nbm, dMq, w.coefA.get(), MAXM, 1.0, Mq_max};
   update<double>(s.tiles, s.d_nb.get(), nbm, nullptr, w.r.get(), nbm, -1.0, phiM, none,
                  nullptr, nullptr, st);
 
@@ -436,7 +436,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     res.noconv += o32.noconv;
   }
   res.n_ham = res.n_ham64 + res.n_ham32;
-  UpdTerm<double> phiA{s.d_phi.get(), phik, nbm, dMq, w.coefA.get(), MAXM, -1.0};
+  UpdTerm<double> phiA{s.d_phi.get(), phik, nbm, dMq, w.coefA.get(), MAXM, -1.0, Mq_max};
   const double S16 = 16.0;
   double ncol_avg = 0;
   for (int j = 0; j < J; ++j) ncol_avg += s.kp[s.slot_k[j]].ncol;
@@ -448,7 +448,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
                nbm, w.x.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
   IKR_HIP(hipMemcpyAsync(w.coefB.get(), dp.data(), dp.size() * sizeof(double2),
                          hipMemcpyHostToDevice, st));
-  UpdTerm<double> phiB{s.d_phi.get(), phik, nbm, dMq, w.coefB.get(), MAXM, 1.0};
+  UpdTerm<double> phiB{s.d_phi.get(), phik, nbm, dMq, w.coefB.get(), MAXM, 1.0, Mq_max};
   update<double>(s.tiles, s.d_nb.get(), nbm, nullptr, w.x.get(), nbm, 1.0, phiA, phiB, nullptr,
                  nullptr, st);
 
