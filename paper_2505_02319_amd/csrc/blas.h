@@ -16,6 +16,7 @@ struct Tiles {
   const int* slot0;
   const int* nb;           // slots in the tile (<= BT)
   const int* idx = nullptr;
+  const int* dn = nullptr; // device count of live tiles (n is then an upper bound)
 };
 
 __device__ __forceinline__ int tslot(const Tiles& tl, int t, int b) {

@@ -21,6 +21,7 @@ constexpr int UPD_BLOCKS = 1024;    // update blocks below which tiles are split
 
 // True when some slot of tile t takes part (active == null: all do).
 __device__ __forceinline__ bool tile_live(const Tiles& tl, int t, const int* active) {
+  if (tl.dn && t >= *tl.dn) return false;
   if (!active) return true;
   const int nbt = tl.nb[t];
   bool any = false;
@@ -37,18 +38,22 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 // part[((t * nsc + sc) * Mmax + m) * BT + b] = sum_{g in super-chunk}
 //                                 conj(W[k][m][g]) X[slot0 + b][g]
 //
-// Chunks of CH coefficients of the tile's BT bands and of MT projector rows
-// are staged in LDS.  Each thread owns a 4 x 4 block of the MT x BT output
-// (rows 4mi.., bands 4bi..) over one of KS = NT / MT interleaved slices of
-// the chunk, so every LDS value it reads feeds four complex multiply-adds;
-// the slices are summed by shuffles inside a wavefront, then across waves.
-template <typename R, int MT>
+// Chunks of CH coefficients of the tile's BT bands and of MT = RB * SBM
+// projector rows are staged in LDS.  Each thread owns an RB x 4 block of the
+// MT x BT output (rows RB*mi.., bands 4bi..) over one of KS interleaved
+// slices of the chunk, so every LDS value it reads feeds four (or RB)
+// complex multiply-adds; the slices are summed by shuffles inside a
+// wavefront, then across the wavefronts.
+template <typename R, int RB, int SBM>
 __global__ __launch_bounds__(NT) void gram_kernel(
     Tiles tl, const int* __restrict__ nb, const int* __restrict__ Mk, int Mmax,
     const cplx<R>* __restrict__ W, size_t wk_stride, int w_stride,
     const cplx<R>* __restrict__ X, int x_stride, int nsc, int sc_len,
     cplx<R>* __restrict__ part, const int* __restrict__ active) {
-  constexpr int KS = NT / MT;             // slices per chunk
+  constexpr int MT = RB * SBM;            // rows per pass
+  constexpr int SB = SBM * (BT / 4);      // threads covering one slice
+  constexpr int KS = NT / SB;             // slices per chunk
+  static_assert(64 % SB == 0 && CH % KS == 0, "gram tiling");
   constexpr int LW = CH + 1;
   constexpr int NWAVE = NT / 64;
   constexpr int STAGE = (BT + MT) * LW, RED = NWAVE * MT * BT;
@@ -63,14 +68,14 @@ __global__ __launch_bounds__(NT) void gram_kernel(
   const int M = Mk[k], n = nb[k];
   if (tid < BT) ss[tid] = tid < nbt ? tslot(tl, t, tid) : 0;
   __syncthreads();
-  const int sb = tid % MT, mi = sb >> 2, bi = sb & 3, ks = tid / MT;
+  const int sb = tid % SB, mi = sb >> 2, bi = sb & 3, ks = tid / SB;
   const int wave = tid >> 6, lane = tid & 63;
   const cplx<R>* Wk = W + (size_t)k * wk_stride;
   const int gbeg = sc * sc_len, gend = min(n, gbeg + sc_len);
   for (int m0 = 0; m0 < M; m0 += MT) {
-    R ar[4][4], ai[4][4];
+    R ar[RB][4], ai[RB][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < RB; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = R(0);
     for (int g0 = gbeg; g0 < gend; g0 += CH) {
@@ -87,13 +92,13 @@ __global__ __launch_bounds__(NT) void gram_kernel(
 #pragma unroll
       for (int u = 0; u < CH / KS; ++u) {
         const int e = ks + KS * u;
-        cplx<R> w[4], x[4];
+        cplx<R> w[RB], x[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) w[i] = Ws[(4 * mi + i) * LW + e];
+        for (int i = 0; i < RB; ++i) w[i] = Ws[(RB * mi + i) * LW + e];
 #pragma unroll
         for (int j = 0; j < 4; ++j) x[j] = Xs[(4 * bi + j) * LW + e];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < RB; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             ar[i][j] += w[i].x * x[j].x + w[i].y * x[j].y;
@@ -102,22 +107,22 @@ __global__ __launch_bounds__(NT) void gram_kernel(
       }
       __syncthreads();
     }
-    // the slices held by one wavefront sit in lanes sb, sb + MT, ...
+    // the slices held by one wavefront sit in lanes sb, sb + SB, ...
 #pragma unroll
-    for (int o = MT; o < 64; o <<= 1)
+    for (int o = SB; o < 64; o <<= 1)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           ar[i][j] += __shfl_xor(ar[i][j], o, 64);
           ai[i][j] += __shfl_xor(ai[i][j], o, 64);
         }
-    if (lane < MT)
+    if (lane < SB)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-          red[wave * MT * BT + (4 * mi + i) * BT + 4 * bi + j] = mk<R>(ar[i][j], ai[i][j]);
+          red[wave * MT * BT + (RB * mi + i) * BT + 4 * bi + j] = mk<R>(ar[i][j], ai[i][j]);
     __syncthreads();
     for (int o = tid; o < MT * BT; o += NT) {
       const int m = o / BT, b = o % BT;
@@ -522,18 +527,21 @@ void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
           const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
           int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st,
           const int* active) {
-  IKR_CHECK(Mmax <= MAXM, 1, "too many projector rows");
   IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Mk && W && X && part && coef, 8,
             "gram: null device pointer");
+  IKR_CHECK(Mmax <= cstride, 1, "gram: coefficient stride below the row count");
   if (tl.n <= 0) return;
   int sc_len;
   const int nsc = nsc_for(nb_max, tl.n, sc_len);
-  if (Mmax <= 16)
-    hipLaunchKernelGGL((gram_kernel<R, 16>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, Mk,
-                       Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part, active);
-  else
-    hipLaunchKernelGGL((gram_kernel<R, 32>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, Mk,
-                       Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part, active);
+  // rows per pass: 16, 32 or 48 (the smallest that holds Mmax, else 48)
+#define IKR_GRAM(RB, SBM)                                                              \
+  hipLaunchKernelGGL((gram_kernel<R, RB, SBM>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, \
+                     Mk, Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part,   \
+                     active)
+  if (Mmax <= 16) IKR_GRAM(4, 4);
+  else if (Mmax <= 32) IKR_GRAM(4, 8);
+  else IKR_GRAM(6, 8);
+#undef IKR_GRAM
   IKR_HIP(hipGetLastError());
   const int outs_per_block = NT / 64;
   hipLaunchKernelGGL((gram_reduce_kernel<R>),
@@ -554,7 +562,8 @@ void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
   IKR_CHECK((!t1.W || (t1.Mk && t1.C)) && (!t2.W || (t2.Mk && t2.C)), 8,
             "update: null coefficient pointer");
   const int M1max = t1.W ? t1.Mmax : 0, M2max = t2.W ? t2.Mmax : 0;
-  IKR_CHECK(M1max <= MAXM && M2max <= MAXM, 1, "update: too many projector rows");
+  IKR_CHECK((size_t)BT * (M1max + M2max) * sizeof(cplx<R>) <= 65536, 1,
+            "update: too many projector rows");
   if (tl.n <= 0) return;
   const int ngb = update_nblocks(nb_max);
   const int blocks = ngb * tl.n;

@@ -1,0 +1,71 @@
+// Declarations of the fused Sternheimer CG kernels (cg.hip).
+//
+// One CG iteration on the projected operator Q (H - e_n) Q (paper: the
+// discretised Sternheimer equation, with the iterates kept in range Q as in
+// the remark on re-projection) needs one pass over p~ = z + beta p for all
+// projections: with W_k = [projectors | phi_1, H phi_1, phi_2, H phi_2, ...]
+// the gram coefficients q = P^H p~, a = Phi^H p~, h = (H Phi)^H p~ give
+//   p   = p~ - Phi a                                   (p in range Q)
+//   c   = Phi^H (H - e) p = h - e a - (G - e S) a,     G = Phi^H H Phi, S = Phi^H Phi
+//   A p = (H_loc - e) p~ + P D q - (H Phi) a + Phi (e a - c),
+// all from that one gram and one update.  With the preconditioned residual
+// z = M^-1 r and r in range Q, <r, Q z> = <r, z>, so no projection of z is
+// needed: the next p~ is projected by the next iteration's update.
+#pragma once
+
+#include "blas.h"
+#include "common.h"
+
+namespace ikr {
+
+// z = M^-1 r over the listed slots; partials |r|^2 -> rpart, <r, z> -> zpart
+// ([slot * nparts + block], nparts = vec_nblocks(nb_max)).
+template <typename R>
+void cg_start(const Slots& sl, const int* nb, const double* kin, int nb_max,
+              const R* pshift, const cplx<R>* r, cplx<R>* z, R* rpart, R* zpart,
+              hipStream_t st);
+
+// Per-slot update coefficients from the gram of p~ against W_k (rows: Na
+// projectors, then phi_m / H phi_m interleaved for m < Mq[k]):
+//   gam[r < Na]       = dnl q_r
+//   gam[Na + 2m]      = e a_m - c_m
+//   gam[Na + 2m + 1]  = -a_m
+// GT[k][j][m] = <phi_m, H phi_j>, ST[k][j][m] = <phi_m, phi_j> (row stride nbn).
+template <typename R>
+void cg_combine(const Slots& sl, int Na, const int* Mq, int Mq_max, const cplx<R>* craw,
+                int cstride, const R* shift, const cplx<R>* GT, const cplx<R>* ST, int nbn,
+                R dnl, cplx<R>* gam, hipStream_t st);
+
+// Ap = w~ + sum_r W[r] gam[r] (in place in Wv), p = p~ - sum_m phi_m a_m (in
+// place in P), partial <p, Ap> -> dpart[slot * update_nblocks(nb_max) + gb].
+template <typename R>
+void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, size_t wk,
+               int Na, const int* Mq, int Mq_max, const cplx<R>* gam, const cplx<R>* craw,
+               int cstride, cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st);
+
+// x += alpha p ; r -= alpha Ap ; z = M^-1 r (into w) ; partials |r|^2, <r, z>.
+template <typename R>
+void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, const R* alpha,
+              const R* pshift, cplx<R>* x, cplx<R>* r, const cplx<R>* p, cplx<R>* w,
+              R* rpart, R* zpart, hipStream_t st);
+
+// alpha = rz / <p, Ap> per listed slot (0 when <p, Ap> = 0).
+template <typename R>
+void cg_alpha(const Slots& sl, int nparts, const R* dpart, const R* rz, R* alpha,
+              hipStream_t st);
+
+// start: rz = <r, z>, beta = 0.  Otherwise: iteration count, |r|^2,
+// convergence (|r|^2 <= tol2 after at least min_iter iterations, or the
+// cap), and for slots still active beta = <r, z> / rz, rz = <r, z>.
+template <typename R>
+void cg_finish(const Slots& sl, int nparts, const R* rpart, const R* zpart,
+               const CgScalars<R>& cs, int* active, int start, hipStream_t st);
+
+// Active-set compaction on the device: list[] of active slots (k order),
+// tiles of up to BT of them per k (ctk, cto = offset into list, ctn),
+// cnt[0] = active slots, cnt[1] = tiles; hist[2 * it ..] the same (if not null).
+void cg_compact(int nk, const int* slot0_k, const int* nslot_k, const int* active,
+                int* list, int* ctk, int* cto, int* ctn, int* cnt, int* hist, int it,
+                hipStream_t st);
+
+}  // namespace ikr

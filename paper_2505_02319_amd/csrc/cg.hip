@@ -1,0 +1,412 @@
+// Fused Sternheimer CG kernels: one projection gram and one two-output
+// update per iteration, the vector step with both dots, per-slot scalars,
+// and the on-device active-set compaction (no host round trip per
+// iteration).  Reductions are two-stage with fixed orders, so results are
+// bitwise reproducible run to run.
+#include "cg.h"
+
+namespace ikr {
+namespace {
+
+constexpr int NT = 256;
+constexpr int NW = NT / 64;
+constexpr int CT = 1024;     // threads of the compaction block
+
+template <typename T> __device__ __forceinline__ T wsum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Block sums of two values (result in thread 0): shuffles, then the waves
+// in order.
+template <typename R> __device__ __forceinline__ void block_sum2(R& a, R& b, R* red) {
+  a = wsum(a);
+  b = wsum(b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = a;
+    red[NW + w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = red[0];
+    b = red[NW];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+      a += red[i];
+      b += red[NW + i];
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void cg_start_kernel(
+    Slots s, const int* __restrict__ nb, const double* __restrict__ kin, int nb_max,
+    const R* __restrict__ pshift, const cplx<R>* __restrict__ r, cplx<R>* __restrict__ z,
+    R* __restrict__ rpart, R* __restrict__ zpart) {
+  __shared__ R red[2 * NW];
+  if (!row_live(s, blockIdx.y)) return;
+  const int slot = slot_of(s, blockIdx.y);
+  const int k = s.k[slot];
+  const int g = blockIdx.x * NT + threadIdx.x;
+  R rr = 0, rz = 0;
+  if (g < nb[k]) {
+    const size_t o = (size_t)slot * nb_max + g;
+    const R m = R(1) / (R(kin[(size_t)k * nb_max + g]) + pshift[slot]);
+    const cplx<R> rv = r[o];
+    z[o] = cscale<R>(rv, m);
+    rr = rv.x * rv.x + rv.y * rv.y;
+    rz = m * rr;
+  }
+  block_sum2(rr, rz, red);
+  if (threadIdx.x == 0) {
+    rpart[(size_t)slot * gridDim.x + blockIdx.x] = rr;
+    zpart[(size_t)slot * gridDim.x + blockIdx.x] = rz;
+  }
+}
+
+// One wavefront per slot; lane m takes rows m, m + 64, ...
+template <typename R>
+__global__ __launch_bounds__(64) void cg_combine_kernel(
+    Slots s, int Na, const int* __restrict__ Mq, const cplx<R>* __restrict__ craw, int cstride,
+    const R* __restrict__ shift, const cplx<R>* __restrict__ GT, const cplx<R>* __restrict__ ST,
+    int nbn, R dnl, cplx<R>* __restrict__ gam) {
+  if (!row_live(s, blockIdx.x)) return;
+  const int slot = slot_of(s, blockIdx.x);
+  const int k = s.k[slot];
+  const int M = Mq[k];
+  const R e = shift[slot];
+  const cplx<R>* c = craw + (size_t)slot * cstride;
+  cplx<R>* o = gam + (size_t)slot * cstride;
+  const cplx<R>* G = GT + (size_t)k * nbn * nbn;
+  const cplx<R>* S = ST + (size_t)k * nbn * nbn;
+  for (int r = threadIdx.x; r < Na; r += 64) o[r] = cscale<R>(c[r], dnl);
+  for (int m = threadIdx.x; m < M; m += 64) {
+    const cplx<R> am = c[Na + 2 * m], hm = c[Na + 2 * m + 1];
+    R cx = hm.x - e * am.x, cy = hm.y - e * am.y;
+    for (int j = 0; j < M; ++j) {
+      const cplx<R> aj = c[Na + 2 * j];
+      const cplx<R> g = G[(size_t)j * nbn + m], sv = S[(size_t)j * nbn + m];
+      const R dx = g.x - e * sv.x, dy = g.y - e * sv.y;
+      cx -= dx * aj.x - dy * aj.y;
+      cy -= dx * aj.y + dy * aj.x;
+    }
+    o[Na + 2 * m] = mk<R>(e * am.x - cx, e * am.y - cy);
+    o[Na + 2 * m + 1] = mk<R>(-am.x, -am.y);
+  }
+}
+
+// Block layout as the generic update: NT coefficients g of BPT bands; band
+// groups split a tile when tiles are few; blocks sharing g are 8 apart (one
+// XCD).  LDS: gam [BPT][Mrows], neg a [BPT][Mq_max].
+template <typename R, int BPT>
+__global__ __launch_bounds__(NT) void cg_update_kernel(
+    Tiles tl, const int* __restrict__ nb, int nb_max, const cplx<R>* __restrict__ Wcg,
+    size_t wk, int Na, const int* __restrict__ Mq, int Mq_max,
+    const cplx<R>* __restrict__ gam, const cplx<R>* __restrict__ craw, int cstride,
+    cplx<R>* __restrict__ Wv, cplx<R>* __restrict__ P, R* __restrict__ dpart, int nparts) {
+  constexpr int G = BT / BPT;
+  extern __shared__ __align__(16) unsigned char cgu_smem[];
+  const int Mr = Na + 2 * Mq_max;
+  cplx<R>* cg = reinterpret_cast<cplx<R>*>(cgu_smem);   // [BPT][Mr]
+  cplx<R>* ca = cg + BPT * Mr;                             // [BPT][Mq_max]
+  __shared__ R red[NW * BPT];
+  __shared__ int ss[BPT];
+  const int t = blockIdx.y, tid = threadIdx.x;
+  const int grp = (blockIdx.x >> 3) % G;
+  const int gb = (blockIdx.x / (8 * G)) * 8 + (blockIdx.x & 7);
+  if (tl.dn && t >= *tl.dn) return;
+  const int k = tl.k[t];
+  const int nbg = min(BPT, tl.nb[t] - grp * BPT);
+  if (nbg <= 0) return;
+  const int n = nb[k];
+  const int M = min(Mq[k], Mq_max);
+  if (tid < BPT) ss[tid] = tid < nbg ? tslot(tl, t, grp * BPT + tid) : 0;
+  __syncthreads();
+  for (int i = tid; i < BPT * Mr; i += NT) {
+    const int b = i / Mr, r = i % Mr;
+    cg[i] = (b < nbg && r < Na + 2 * M) ? gam[(size_t)ss[b] * cstride + r] : mk<R>(0, 0);
+  }
+  for (int i = tid; i < BPT * Mq_max; i += NT) {
+    const int b = i / Mq_max, m = i % Mq_max;
+    const cplx<R> a = (b < nbg && m < M) ? craw[(size_t)ss[b] * cstride + Na + 2 * m]
+                                         : mk<R>(0, 0);
+    ca[i] = mk<R>(-a.x, -a.y);
+  }
+  __syncthreads();
+  const int g = gb * NT + tid;
+  cplx<R> a1[BPT], a2[BPT];
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) a1[b] = a2[b] = mk<R>(0, 0);
+  if (g < n) {
+    const cplx<R>* W = Wcg + (size_t)k * wk + g;
+    for (int r = 0; r < Na; ++r) {
+      const cplx<R> w = W[(size_t)r * nb_max];
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) a1[b] = cadd<R>(a1[b], cmul<R>(w, cg[b * Mr + r]));
+    }
+    for (int m = 0; m < M; ++m) {
+      const cplx<R> f = W[(size_t)(Na + 2 * m) * nb_max];
+      const cplx<R> h = W[(size_t)(Na + 2 * m + 1) * nb_max];
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) {
+        a1[b] = cadd<R>(a1[b], cadd<R>(cmul<R>(f, cg[b * Mr + Na + 2 * m]),
+                                       cmul<R>(h, cg[b * Mr + Na + 2 * m + 1])));
+        a2[b] = cadd<R>(a2[b], cmul<R>(f, ca[b * Mq_max + m]));
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    R d = 0;
+    if (b < nbg && g < n) {
+      const size_t o = (size_t)ss[b] * nb_max + g;
+      const cplx<R> ap = cadd<R>(Wv[o], a1[b]);
+      const cplx<R> pv = cadd<R>(P[o], a2[b]);
+      Wv[o] = ap;
+      P[o] = pv;
+      d = pv.x * ap.x + pv.y * ap.y;
+    }
+    d = wsum(d);
+    if ((tid & 63) == 0) red[(tid >> 6) * BPT + b] = d;
+  }
+  __syncthreads();
+  if (tid < nbg) {
+    R v = red[tid];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[w * BPT + tid];
+    dpart[(size_t)ss[tid] * nparts + gb] = v;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void cg_step2_kernel(
+    Slots s, const int* __restrict__ nb, const double* __restrict__ kin, int nb_max,
+    const R* __restrict__ alpha, const R* __restrict__ pshift, cplx<R>* __restrict__ x,
+    cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p, cplx<R>* __restrict__ w,
+    R* __restrict__ rpart, R* __restrict__ zpart) {
+  __shared__ R red[2 * NW];
+  if (!row_live(s, blockIdx.y)) return;
+  const int slot = slot_of(s, blockIdx.y);
+  const int k = s.k[slot];
+  const int g = blockIdx.x * NT + threadIdx.x;
+  R rr = 0, rz = 0;
+  if (g < nb[k]) {
+    const size_t o = (size_t)slot * nb_max + g;
+    const R a = alpha[slot];
+    cplx<R> xv = x[o], rv = r[o];
+    const cplx<R> pv = p[o], wv = w[o];
+    xv = mk<R>(xv.x + a * pv.x, xv.y + a * pv.y);
+    rv = mk<R>(rv.x - a * wv.x, rv.y - a * wv.y);
+    x[o] = xv;
+    r[o] = rv;
+    const R m = R(1) / (R(kin[(size_t)k * nb_max + g]) + pshift[slot]);
+    w[o] = cscale<R>(rv, m);
+    rr = rv.x * rv.x + rv.y * rv.y;
+    rz = m * rr;
+  }
+  block_sum2(rr, rz, red);
+  if (threadIdx.x == 0) {
+    rpart[(size_t)slot * gridDim.x + blockIdx.x] = rr;
+    zpart[(size_t)slot * gridDim.x + blockIdx.x] = rz;
+  }
+}
+
+// One wavefront per listed slot.
+template <typename R>
+__global__ __launch_bounds__(NT) void cg_alpha_kernel(Slots s, int nparts,
+                                                      const R* __restrict__ dpart,
+                                                      const R* __restrict__ rz,
+                                                      R* __restrict__ alpha) {
+  const int row = blockIdx.x * NW + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= s.n || !row_live(s, row)) return;
+  const int slot = slot_of(s, row);
+  R v = 0;
+  for (int i = lane; i < nparts; i += 64) v += dpart[(size_t)slot * nparts + i];
+  v = wsum(v);
+  if (lane == 0) alpha[slot] = v != R(0) ? rz[slot] / v : R(0);
+}
+
+template <typename R>
+__global__ __launch_bounds__(NT) void cg_finish_kernel(Slots s, int nparts,
+                                                       const R* __restrict__ rpart,
+                                                       const R* __restrict__ zpart,
+                                                       CgScalars<R> cs, int* __restrict__ active,
+                                                       int start) {
+  const int row = blockIdx.x * NW + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= s.n || !row_live(s, row)) return;
+  const int slot = slot_of(s, row);
+  R rr = 0, rz = 0;
+  for (int i = lane; i < nparts; i += 64) {
+    rr += rpart[(size_t)slot * nparts + i];
+    rz += zpart[(size_t)slot * nparts + i];
+  }
+  rr = wsum(rr);
+  rz = wsum(rz);
+  if (lane != 0) return;
+  if (start) {
+    cs.rz[slot] = rz;
+    cs.beta[slot] = 0;
+    return;
+  }
+  const int it = ++cs.iters[slot];
+  cs.rnorm2[slot] = rr;
+  const bool conv = it >= cs.min_iter && (double)rr <= cs.tol2[slot];
+  if (conv || it >= cs.max_iter) {
+    active[slot] = 0;
+    if (!conv) atomicAdd(cs.noconv, 1);
+    return;
+  }
+  cs.beta[slot] = cs.rz[slot] != R(0) ? rz / cs.rz[slot] : R(0);
+  cs.rz[slot] = rz;
+}
+
+// Thread k (< nk) counts and lists the active slots of k-point k; thread 0
+// turns the per-k counts into list and tile offsets (k order).
+__global__ __launch_bounds__(CT) void cg_compact_kernel(
+    int nk, const int* __restrict__ slot0_k, const int* __restrict__ nslot_k,
+    const int* __restrict__ active, int* __restrict__ list, int* __restrict__ ctk,
+    int* __restrict__ cto, int* __restrict__ ctn, int* __restrict__ cnt,
+    int* __restrict__ hist, int it) {
+  __shared__ int na[CT], lb[CT], tb[CT + 1];
+  const int tid = threadIdx.x;
+  if (tid < nk) {
+    int c = 0;
+    const int j0 = slot0_k[tid], m = nslot_k[tid];
+    for (int i = 0; i < m; ++i) c += active[j0 + i] != 0;
+    na[tid] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int a = 0, t = 0;
+    for (int k = 0; k < nk; ++k) {
+      lb[k] = a;
+      tb[k] = t;
+      a += na[k];
+      t += (na[k] + BT - 1) / BT;
+    }
+    tb[nk] = t;
+    cnt[0] = a;
+    cnt[1] = t;
+    if (hist) {
+      hist[2 * it] = a;
+      hist[2 * it + 1] = t;
+    }
+  }
+  __syncthreads();
+  if (tid < nk) {
+    const int j0 = slot0_k[tid], m = nslot_k[tid];
+    int pos = lb[tid];
+    for (int i = 0; i < m; ++i)
+      if (active[j0 + i]) list[pos++] = j0 + i;
+    for (int t = tb[tid]; t < tb[tid + 1]; ++t) {
+      const int o = (t - tb[tid]) * BT;
+      ctk[t] = tid;
+      cto[t] = lb[tid] + o;
+      ctn[t] = min(BT, na[tid] - o);
+    }
+  }
+}
+
+}  // namespace
+
+static int cg_vec_blocks(int nb_max) { return (nb_max + NT - 1) / NT; }
+
+template <typename R>
+void cg_start(const Slots& sl, const int* nb, const double* kin, int nb_max, const R* pshift,
+              const cplx<R>* r, cplx<R>* z, R* rpart, R* zpart, hipStream_t st) {
+  if (sl.n <= 0) return;
+  hipLaunchKernelGGL((cg_start_kernel<R>), dim3(cg_vec_blocks(nb_max), sl.n), dim3(NT), 0, st,
+                     sl, nb, kin, nb_max, pshift, r, z, rpart, zpart);
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
+void cg_combine(const Slots& sl, int Na, const int* Mq, int Mq_max, const cplx<R>* craw,
+                int cstride, const R* shift, const cplx<R>* GT, const cplx<R>* ST, int nbn,
+                R dnl, cplx<R>* gam, hipStream_t st) {
+  if (sl.n <= 0) return;
+  IKR_CHECK(Na + 2 * Mq_max <= cstride && Mq_max <= nbn, 1, "cg_combine: row count");
+  hipLaunchKernelGGL((cg_combine_kernel<R>), dim3(sl.n), dim3(64), 0, st, sl, Na, Mq, craw,
+                     cstride, shift, GT, ST, nbn, dnl, gam);
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
+void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, size_t wk,
+               int Na, const int* Mq, int Mq_max, const cplx<R>* gam, const cplx<R>* craw,
+               int cstride, cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st) {
+  if (tl.n <= 0) return;
+  IKR_CHECK(Na + 2 * Mq_max <= cstride, 1, "cg_update: row count");
+  const int ngb = update_nblocks(nb_max);
+  const int blocks = ngb * tl.n;
+  const int bpt = blocks >= 1024 ? 16 : (2 * blocks >= 1024 ? 8 : 4);
+  const size_t lds = (size_t)bpt * (Na + 3 * Mq_max) * sizeof(cplx<R>);
+  IKR_CHECK(lds <= 65536, 1, "cg_update: too many projection rows");
+  const dim3 grid(ngb * (BT / bpt), tl.n);
+#define IKR_CGU(B)                                                                         \
+  hipLaunchKernelGGL((cg_update_kernel<R, B>), grid, dim3(NT), lds, st, tl, nb, nb_max, Wcg, \
+                     wk, Na, Mq, Mq_max, gam, craw, cstride, Wv, P, dpart, ngb)
+  if (bpt == 16) IKR_CGU(16);
+  else if (bpt == 8) IKR_CGU(8);
+  else IKR_CGU(4);
+#undef IKR_CGU
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
+void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, const R* alpha,
+              const R* pshift, cplx<R>* x, cplx<R>* r, const cplx<R>* p, cplx<R>* w,
+              R* rpart, R* zpart, hipStream_t st) {
+  if (sl.n <= 0) return;
+  hipLaunchKernelGGL((cg_step2_kernel<R>), dim3(cg_vec_blocks(nb_max), sl.n), dim3(NT), 0, st,
+                     sl, nb, kin, nb_max, alpha, pshift, x, r, p, w, rpart, zpart);
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
+void cg_alpha(const Slots& sl, int nparts, const R* dpart, const R* rz, R* alpha,
+              hipStream_t st) {
+  if (sl.n <= 0) return;
+  hipLaunchKernelGGL((cg_alpha_kernel<R>), dim3((sl.n + NW - 1) / NW), dim3(NT), 0, st, sl,
+                     nparts, dpart, rz, alpha);
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
+void cg_finish(const Slots& sl, int nparts, const R* rpart, const R* zpart,
+               const CgScalars<R>& cs, int* active, int start, hipStream_t st) {
+  if (sl.n <= 0) return;
+  hipLaunchKernelGGL((cg_finish_kernel<R>), dim3((sl.n + NW - 1) / NW), dim3(NT), 0, st, sl,
+                     nparts, rpart, zpart, cs, active, start);
+  IKR_HIP(hipGetLastError());
+}
+
+void cg_compact(int nk, const int* slot0_k, const int* nslot_k, const int* active, int* list,
+                int* ctk, int* cto, int* ctn, int* cnt, int* hist, int it, hipStream_t st) {
+  IKR_CHECK(nk <= CT, 1, "cg_compact: too many k-points for one block");
+  hipLaunchKernelGGL(cg_compact_kernel, dim3(1), dim3(CT), 0, st, nk, slot0_k, nslot_k, active,
+                     list, ctk, cto, ctn, cnt, hist, it);
+  IKR_HIP(hipGetLastError());
+}
+
+#define IKR_INST(R)                                                                            \
+  template void cg_start<R>(const Slots&, const int*, const double*, int, const R*,            \
+                            const cplx<R>*, cplx<R>*, R*, R*, hipStream_t);                    \
+  template void cg_combine<R>(const Slots&, int, const int*, int, const cplx<R>*, int,         \
+                              const R*, const cplx<R>*, const cplx<R>*, int, R, cplx<R>*,      \
+                              hipStream_t);                                                    \
+  template void cg_update<R>(const Tiles&, const int*, int, const cplx<R>*, size_t, int,       \
+                             const int*, int, const cplx<R>*, const cplx<R>*, int, cplx<R>*,   \
+                             cplx<R>*, R*, hipStream_t);                                       \
+  template void cg_step2<R>(const Slots&, const int*, const double*, int, const R*, const R*,  \
+                            cplx<R>*, cplx<R>*, const cplx<R>*, cplx<R>*, R*, R*, hipStream_t); \
+  template void cg_alpha<R>(const Slots&, int, const R*, const R*, R*, hipStream_t);           \
+  template void cg_finish<R>(const Slots&, int, const R*, const R*, const CgScalars<R>&, int*,  \
+                             int, hipStream_t);
+IKR_INST(double)
+IKR_INST(float)
+#undef IKR_INST
+
+}  // namespace ikr

@@ -75,14 +75,20 @@ struct Geom {
 // Per-slot (band of the batch) metadata for batched kernels.  A launch
 // covers n grid rows; row y works on slot list[y] (list may be null: y).
 struct Slots {
-  int n;                 // number of grid rows
+  int n;                 // number of grid rows (an upper bound when dn is set)
   const int* k;          // [slots] k-point of the slot
   const int* active;     // [slots] nonzero when the slot takes part (may be null)
   const int* list = nullptr;   // [n] compact list of slots (may be null)
+  const int* dn = nullptr;     // device count of live rows (may be null: all n)
 };
 
 __device__ __forceinline__ int slot_of(const Slots& s, int row) {
   return s.list ? s.list[row] : row;
+}
+
+// False for grid rows past the device-side live count.
+__device__ __forceinline__ bool row_live(const Slots& s, int row) {
+  return !s.dn || row < *s.dn;
 }
 
 // ---------------------------------------------------------------- FFT API

@@ -52,6 +52,7 @@ __global__ __launch_bounds__(NT) void col_kernel(
   __shared__ int sstart[NCB + 1];
   __shared__ int sclo[NCB];
 
+  if (!row_live(s, blockIdx.y)) return;
   const int slot = slot_of(s, blockIdx.y);
   if (s.active && !s.active[slot]) return;
   const int k = (MODE == 2) ? 0 : s.k[slot];
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
     const R* __restrict__ V, int v_per_slot) {
   constexpr int LQ = Q + 1;
   __shared__ cplx<R> pl[P * LQ];
+  if (!row_live(s, blockIdx.y)) return;
   const int slot = slot_of(s, blockIdx.y);
   if (s.active && !s.active[slot]) return;
   const int c = blockIdx.x;

@@ -92,6 +92,13 @@ void KTimer::end(int id, hipStream_t st, double bytes) {
   if (s.pending.size() > 4096) resolve(s);
 }
 
+void KTimer::add_bytes(int id, double bytes) {
+  State& s = S();
+  if (id < 0 || id >= K_COUNT || !((s.mask >> id) & 1u)) return;
+  std::lock_guard<std::mutex> g(s.mu);
+  s.bytes[id] += bytes;
+}
+
 void KTimer::query(int id, long long* launches, double* ms, double* bytes) {
   State& s = S();
   std::lock_guard<std::mutex> g(s.mu);

@@ -25,6 +25,8 @@ struct KTimer {
   static bool enabled();
   static void begin(int id, hipStream_t st);
   static void end(int id, hipStream_t st, double bytes);
+  // algorithmic bytes of launches whose size is known only after they ran
+  static void add_bytes(int id, double bytes);
   // launches, total milliseconds and total algorithmic bytes since reset
   static void query(int id, long long* launches, double* ms, double* bytes);
   static void reset();

@@ -298,6 +298,13 @@ void ensure_fp32(System& s) {
   convert_array(s.d_proj.n, s.d_proj.get(), w.proj.get(), st);
   w.vloc.alloc(s.ng);
   convert_array(s.ng, s.d_vloc.get(), w.vloc.get(), st);
+  w.wcg.alloc(d.wcg.n);
+  convert_array(d.wcg.n, d.wcg.get(), w.wcg.get(), st);
+  w.gT.alloc(d.gT.n);
+  convert_array(d.gT.n, d.gT.get(), w.gT.get(), st);
+  w.sT.alloc(d.sT.n);
+  convert_array(d.sT.n, d.sT.get(), w.sT.get(), st);
+  w.craw.alloc(d.craw.n); w.gam.alloc(d.gam.n); w.zpart.alloc(d.zpart.n);
   IKR_HIP(hipStreamSynchronize(st));
 }
 
@@ -325,6 +332,8 @@ void import_ground_state(System& s, const double* eps, const double* coeffs) {
 // kernel and the grt orbital norms.
 void finish_setup(System& s) {
   const int nk = s.nk, nbn = s.nbands;
+  s.w32.x.alloc(0);   // FP32 copies are rebuilt from this ground state on demand
+  s.mcg = s.natoms + 2 * nbn;
   s.occ.assign((size_t)nk * nbn, 0.0);
   s.docc.assign((size_t)nk * nbn, 0.0);
   if (s.temperature <= 0) {
@@ -409,7 +418,10 @@ void finish_setup(System& s) {
   const int mrows = std::max(s.nocc_max, s.natoms) + 1;
   w.coefA.alloc((size_t)s.J * MAXM);
   w.coefB.alloc((size_t)s.J * MAXM);
-  w.part.alloc(gram_part_elems(s.tiles.n, s.nb_max, std::max(mrows, s.nbands)));
+  w.part.alloc(gram_part_elems(s.tiles.n, s.nb_max, std::max({mrows, s.nbands, s.mcg})));
+  w.craw.alloc((size_t)s.J * s.mcg);
+  w.gam.alloc((size_t)s.J * s.mcg);
+  w.zpart.alloc((size_t)s.J * vec_nblocks(s.nb_max));
   w.rz.alloc(s.J); w.alpha.alloc(s.J); w.beta.alloc(s.J); w.rnorm2.alloc(s.J);
   w.dpart.alloc((size_t)s.J * std::max(update_nblocks(s.nb_max), vec_nblocks(s.nb_max)));
   w.pshift.alloc(s.J); w.shift.alloc(s.J);
@@ -420,6 +432,15 @@ void finish_setup(System& s) {
   s.d_ctn.alloc(s.tiles.n);
   s.d_iters.alloc(s.J);
   s.d_counters.alloc(4);
+  s.d_slot0_k.upload(s.slot0_k, st);
+  {
+    std::vector<int> mo(nk), ma(nk, s.mcg);
+    for (int k = 0; k < nk; ++k) mo[k] = s.natoms + 2 * s.nocc_k[k];
+    s.d_mcg_occ.upload(mo, st);
+    s.d_mcg_all.upload(ma, st);
+  }
+  s.d_cnt.alloc(2);
+  s.h_cnt.alloc(4);
   s.d_tol2.alloc(s.J);
   s.d_wa.alloc(s.J);
   s.d_wb.alloc(s.J);
@@ -454,6 +475,48 @@ void finish_setup(System& s) {
     }
     s.w64.pshift.upload(ps, st);
     s.w64.shift.upload(sh, st);
+  }
+
+  // -- fused CG projections: W_k = [projectors | phi_1, H phi_1, phi_2, H phi_2, ...],
+  //    G^T[k][j][m] = <phi_m, H phi_j> and S^T[k][j][m] = <phi_m, phi_j>
+  {
+    const int Na = s.natoms;
+    const size_t kb = (size_t)nbn * s.nb_max, rowb = s.nb_max * sizeof(double2);
+    DBuf<double2> hphi;
+    hphi.alloc((size_t)nk * kb);
+    IKR_HIP(hipMemsetAsync(hphi.get(), 0, hphi.n * sizeof(double2), st));
+    for (int k = 0; k < nk; ++k)
+      apply_hamiltonian(s, k, nbn, s.d_phi.get() + k * kb, hphi.get() + k * kb);
+    w.wcg.alloc((size_t)nk * s.mcg * s.nb_max);
+    for (int k = 0; k < nk; ++k) {
+      double2* dst = w.wcg.get() + (size_t)k * s.mcg * s.nb_max;
+      if (Na > 0)
+        IKR_HIP(hipMemcpyAsync(dst, s.d_proj.get() + (size_t)k * Na * s.nb_max, Na * rowb,
+                               hipMemcpyDeviceToDevice, st));
+      IKR_HIP(hipMemcpy2DAsync(dst + (size_t)Na * s.nb_max, 2 * rowb, s.d_phi.get() + k * kb,
+                               rowb, rowb, nbn, hipMemcpyDeviceToDevice, st));
+      IKR_HIP(hipMemcpy2DAsync(dst + (size_t)(Na + 1) * s.nb_max, 2 * rowb, hphi.get() + k * kb,
+                               rowb, rowb, nbn, hipMemcpyDeviceToDevice, st));
+    }
+    std::vector<int> tk, ts, tn;
+    for (int k = 0; k < nk; ++k)
+      for (int n0 = 0; n0 < nbn; n0 += BT) {
+        tk.push_back(k);
+        ts.push_back(k * nbn + n0);
+        tn.push_back(std::min(BT, nbn - n0));
+      }
+    DBuf<int> dtk, dts, dtn;
+    dtk.upload(tk, st); dts.upload(ts, st); dtn.upload(tn, st);
+    Tiles tl{(int)tk.size(), dtk.get(), dts.get(), dtn.get()};
+    DBuf<double2> part;
+    part.alloc(gram_part_elems(tl.n, s.nb_max, nbn));
+    w.gT.alloc((size_t)nk * nbn * nbn);
+    w.sT.alloc((size_t)nk * nbn * nbn);
+    gram<double>(tl, s.d_nb.get(), s.nb_max, s.d_nbands_k.get(), nbn, s.d_phi.get(), kb,
+                 s.nb_max, hphi.get(), s.nb_max, part.get(), w.gT.get(), nbn, st);
+    gram<double>(tl, s.d_nb.get(), s.nb_max, s.d_nbands_k.get(), nbn, s.d_phi.get(), kb,
+                 s.nb_max, s.d_phi.get(), s.nb_max, part.get(), w.sT.get(), nbn, st);
+    IKR_HIP(hipStreamSynchronize(st));
   }
 
   // -- density rho = sum_k w_k sum_n f |psi|^2 (grid values)

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 
+#include "cg.h"
 #include "ktimer.h"
 #include "system.h"
 
@@ -176,23 +177,33 @@ std::vector<double> slot_norms(System& s, const double2* r) {
   return out;
 }
 
-// Preconditioned CG on Q (H - e_n) Q x = r for the member slots, all at once,
-// with per-band convergence masks and a compact active set rebuilt after
-// every iteration (Remark after Lemma cgtol_E: Ap and z re-projected onto
-// range Q; zero initial guess; at least min_iter iterations).
+template <typename R> const cplx<R>* wcg_of(const System& s);
+template <> const double2* wcg_of<double>(const System& s) { return s.w64.wcg.get(); }
+template <> const float2* wcg_of<float>(const System& s) { return s.w32.wcg.get(); }
+
+// Preconditioned CG on Q (H - e_n) Q x = r for the member slots, all at once
+// (discretised Sternheimer equation; zero initial guess; at least min_iter
+// iterations; absolute stopping test on |r|).  The iterates stay in range Q
+// (remark after Lemma cgtol_E) through the exact projection of p and Ap that
+// one gram of p~ = z + beta p against [projectors | phi, H phi] provides.
+// The active set is compacted on the device after every iteration; the
+// host reads its size one iteration late (an upper bound, since bands only
+// leave the set), so the stream never drains between iterations.
 template <typename R>
 CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>& member,
              const std::vector<double>& tol_slot, int min_iter, int max_iter,
-             const int* dMq, int Mq_max) {
+             const int* dMq, int Mq_max, const int* dMcg) {
   const hipStream_t st = s.stream;
-  const int J = s.J, nbm = s.nb_max, nbn = s.nbands;
+  const int J = s.J, nbm = s.nb_max, nbn = s.nbands, Na = s.natoms;
   const R inv_ng = R(1.0 / s.ng);
-  const size_t phik = (size_t)nbn * nbm;
-  const cplx<R>* phi = phi_of<R>(s);
-  const cplx<R>* proj = proj_of<R>(s);
   const R* vloc = vloc_of<R>(s);
-  UpdTerm<R> none{};
+  const cplx<R>* wcg = wcg_of<R>(s);
+  const size_t wk = (size_t)s.mcg * nbm;
+  const int Mrows = Na + 2 * Mq_max;
   CgOut out;
+  int nmem = 0;
+  for (int v : member) nmem += v != 0;
+  if (nmem == 0 || max_iter <= 0) return out;
   if (w.r.get() != rhs)
     IKR_HIP(hipMemcpyAsync(w.r.get(), rhs, (size_t)J * nbm * sizeof(cplx<R>),
                            hipMemcpyDeviceToDevice, st));
@@ -204,133 +215,129 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   IKR_HIP(hipMemcpyAsync(s.d_active.get(), member.data(), J * sizeof(int), hipMemcpyHostToDevice, st));
   IKR_HIP(hipMemsetAsync(s.d_iters.get(), 0, J * sizeof(int), st));
   IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, 4 * sizeof(int), st));
+  if (s.d_hist.n < (size_t)2 * (max_iter + 1)) s.d_hist.alloc((size_t)2 * (max_iter + 1));
   CgScalars<R> cs{w.rz.get(), w.alpha.get(), w.beta.get(), w.rnorm2.get(), s.d_tol2.get(),
                   s.d_iters.get(), s.d_counters.get(), s.d_counters.get() + 1,
                   min_iter, max_iter};
   const int nup = update_nblocks(nbm), nvb = vec_nblocks(nbm);
-  UpdTerm<R> phiA{phi, phik, nbm, dMq, w.coefA.get(), MAXM, R(-1), Mq_max};
-  UpdTerm<R> projB{proj, (size_t)s.natoms * nbm, nbm, s.d_natoms_k.get(), w.coefB.get(), MAXM,
-                   R(s.dnl), s.natoms};
-
-  // Algorithmic bytes per band for the kernel timer: mean sphere and footprint.
-  double nb_avg = 0, ncol_avg = 0;
-  for (int j = 0; j < J; ++j) {
-    nb_avg += s.kp[s.slot_k[j]].nb;
-    ncol_avg += s.kp[s.slot_k[j]].ncol;
-  }
-  nb_avg /= J;
-  ncol_avg /= J;
-  const double SZ = sizeof(cplx<R>), colC = ncol_avg * s.L.C;
-  // Compact active set: the slots still iterating and per-k tiles of them.
-  std::vector<int> hflag(member), hlist(J), htk, hto, htn;
+  int* cnt = s.d_cnt.get();
+  auto compact = [&](int it) {
+    cg_compact(s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_active.get(), s.d_list.get(),
+               s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), cnt,
+               it >= 0 ? s.d_hist.get() : nullptr, it, st);
+  };
+  // host bound on the tiles of the member set
   int nct = 0;
-  auto rebuild = [&]() {
-    int na = 0;
-    htk.clear(); hto.clear(); htn.clear();
-    for (int k = 0; k < s.nk; ++k) {
-      const int j0 = s.slot0_k[k], j1 = j0 + s.nocc_k[k];
-      int cnt = 0;
-      for (int j = j0; j < j1; ++j) {
-        if (!hflag[j]) continue;
-        if (cnt % BT == 0) {
-          htk.push_back(k);
-          hto.push_back(na);
-          htn.push_back(0);
-        }
-        hlist[na++] = j;
-        ++htn.back();
-        ++cnt;
+  for (int k = 0; k < s.nk; ++k) {
+    int c = 0;
+    for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) c += member[j] != 0;
+    nct += (c + BT - 1) / BT;
+  }
+  int nact = nmem;
+  compact(-1);
+  {
+    // z = M^-1 r, rz = <r, z>, beta = 0
+    Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
+    cg_start<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.pshift.get(), w.r.get(), w.w.get(),
+                w.dpart.get(), w.zpart.get(), st);
+    cg_finish<R>(sl, nvb, w.dpart.get(), w.zpart.get(), cs, s.d_active.get(), 1, st);
+  }
+  hipEvent_t ev[2];
+  IKR_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+  IKR_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  int iters = 0;
+  const bool timing = KTimer::enabled();
+  try {
+    for (int it = 0; it < max_iter; ++it) {
+      Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
+      Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(), cnt + 1};
+      // p~ = z + beta p ; w~ = (H_loc - e) p~ through the pruned FFT
+      KTimer::begin(K_COL_INV, st);
+      launch_col_inv<R>(s.geom, s.fft, sl, w.p.get(), nbm, w.T1.get(), w.w.get(), w.beta.get(),
+                        w.p.get(), st);
+      KTimer::end(K_COL_INV, st, 0.0);
+      KTimer::begin(K_PLANE_HV, st);
+      launch_plane_hv<R>(s.geom, s.fft, sl, w.T1.get(), w.T2.get(), vloc, 0, st);
+      KTimer::end(K_PLANE_HV, st, 0.0);
+      KTimer::begin(K_COL_FWD, st);
+      launch_col_fwd<R>(s.geom, s.fft, sl, w.T2.get(), w.w.get(), nbm, w.p.get(), w.shift.get(),
+                        inv_ng, st);
+      KTimer::end(K_COL_FWD, st, 0.0);
+      // q, a, h = W_k^H p~ ; update coefficients ; Ap and p = Q p~ ; <p, Ap>
+      KTimer::begin(K_GRAM, st);
+      gram<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm, w.p.get(), nbm, w.part.get(),
+              w.craw.get(), s.mcg, st);
+      KTimer::end(K_GRAM, st, 0.0);
+      cg_combine<R>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
+                    w.sT.get(), nbn, R(s.dnl), w.gam.get(), st);
+      KTimer::begin(K_UPDATE, st);
+      cg_update<R>(ctl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), w.craw.get(),
+                   s.mcg, w.w.get(), w.p.get(), w.dpart.get(), st);
+      KTimer::end(K_UPDATE, st, 0.0);
+      cg_alpha<R>(sl, nup, w.dpart.get(), w.rz.get(), w.alpha.get(), st);
+      // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, <r, z>
+      KTimer::begin(K_CG_STEP, st);
+      cg_step2<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.alpha.get(), w.pshift.get(),
+                  w.x.get(), w.r.get(), w.p.get(), w.w.get(), w.dpart.get(), w.zpart.get(), st);
+      KTimer::end(K_CG_STEP, st, 0.0);
+      cg_finish<R>(sl, nvb, w.dpart.get(), w.zpart.get(), cs, s.d_active.get(), 0, st);
+      compact(it);
+      iters = it + 1;
+      IKR_HIP(hipMemcpyAsync(s.h_cnt.p + 2 * (it & 1), cnt, 2 * sizeof(int),
+                             hipMemcpyDeviceToHost, st));
+      IKR_HIP(hipEventRecord(ev[it & 1], st));
+      if (it >= 1) {
+        IKR_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
+        nact = s.h_cnt.p[2 * ((it - 1) & 1)];
+        nct = s.h_cnt.p[2 * ((it - 1) & 1) + 1];
+        if (nact == 0) break;
       }
     }
-    nct = (int)htk.size();
-    if (na > 0) {
-      IKR_HIP(hipMemcpyAsync(s.d_list.get(), hlist.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
-      IKR_HIP(hipMemcpyAsync(s.d_ctk.get(), htk.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
-      IKR_HIP(hipMemcpyAsync(s.d_cto.get(), hto.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
-      IKR_HIP(hipMemcpyAsync(s.d_ctn.get(), htn.data(), nct * sizeof(int), hipMemcpyHostToDevice, st));
-    }
     IKR_HIP(hipStreamSynchronize(st));
-    return na;
-  };
-  int nact = rebuild();
-  if (nact == 0) return out;
-  {
-    // z = Q M^-1 r, rz = <r, z>, beta = 0
-    Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get()};
-    precond<R>(J, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, w.pshift.get(),
-               w.r.get(), w.w.get(), st);
-    gram<R>(ctl, s.d_nb.get(), nbm, dMq, Mq_max, phi, phik, nbm, w.w.get(),
-            nbm, w.part.get(), w.coefA.get(), MAXM, st);
-    update<R>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, R(1), phiA, none, w.r.get(),
-              w.dpart.get(), st);
-    cg_scalars<R>(nact, nup, w.dpart.get(), 2, s.d_active.get(), cs, 1, st, s.d_list.get());
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    throw;
   }
-  for (int it = 0; it < max_iter && nact > 0; ++it) {
-    Slots act{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get()};
-    Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get()};
-    auto tile_bytes = [&](double M, bool upd, bool dot) {
-      // W read once per tile, X read (gram) or Y read+write (+ D read) per slot
-      return nct * M * nb_avg * SZ + nact * nb_avg * SZ * (upd ? (dot ? 3.0 : 2.0) : 1.0);
-    };
-    // p = z + beta p ; w = (H - e) p  (local part through the pruned FFT)
-    KTimer::begin(K_COL_INV, st);
-    launch_col_inv<R>(s.geom, s.fft, act, w.p.get(), nbm, w.T1.get(), w.w.get(), w.beta.get(),
-                      w.p.get(), st);
-    KTimer::end(K_COL_INV, st, nact * (3.0 * nb_avg + colC) * SZ);
-    KTimer::begin(K_PLANE_HV, st);
-    launch_plane_hv<R>(s.geom, s.fft, act, w.T1.get(), w.T2.get(), vloc, 0, st);
-    KTimer::end(K_PLANE_HV, st, nact * 2.0 * colC * SZ + sizeof(R) * (double)s.ng);
-    KTimer::begin(K_COL_FWD, st);
-    launch_col_fwd<R>(s.geom, s.fft, act, w.T2.get(), w.w.get(), nbm, w.p.get(), w.shift.get(),
-                      inv_ng, st);
-    KTimer::end(K_COL_FWD, st, nact * (colC * SZ + nb_avg * (2.0 * SZ + 8.0)));
-    if (s.natoms > 0) {
-      KTimer::begin(K_GRAM, st);
-      gram<R>(ctl, s.d_nb.get(), nbm, s.d_natoms_k.get(), s.natoms, proj, (size_t)s.natoms * nbm,
-              nbm, w.p.get(), nbm, w.part.get(), w.coefB.get(), MAXM, st);
-      KTimer::end(K_GRAM, st, tile_bytes(s.natoms, false, false));
-      KTimer::begin(K_UPDATE, st);
-      update<R>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, R(1), projB, none, nullptr,
-                nullptr, st);
-      KTimer::end(K_UPDATE, st, tile_bytes(s.natoms, true, false));
+  IKR_HIP(hipEventDestroy(ev[0]));
+  IKR_HIP(hipEventDestroy(ev[1]));
+  const std::vector<int> hits = download(s.d_iters.get(), J, st);
+  for (int j = 0; j < J; ++j) out.n_ham += hits[j];
+  const std::vector<int> ctr = download(s.d_counters.get(), 4, st);
+  const std::vector<int> last = download(cnt, 2, st);
+  out.noconv = ctr[1] + last[0];
+  if (timing) {
+    // algorithmic bytes of the launches, from the live counts of each iteration
+    double nb_avg = 0, ncol_avg = 0;
+    for (int j = 0; j < J; ++j) {
+      nb_avg += s.kp[s.slot_k[j]].nb;
+      ncol_avg += s.kp[s.slot_k[j]].ncol;
     }
-    // Ap = Q w ; pAp
-    KTimer::begin(K_GRAM, st);
-    gram<R>(ctl, s.d_nb.get(), nbm, dMq, Mq_max, phi, phik, nbm, w.w.get(), nbm,
-            w.part.get(), w.coefA.get(), MAXM, st);
-    KTimer::end(K_GRAM, st, tile_bytes(Mq_max, false, false));
-    KTimer::begin(K_UPDATE, st);
-    update<R>(ctl, s.d_nb.get(), nbm, nullptr, w.w.get(), nbm, R(1), phiA, none, w.p.get(),
-              w.dpart.get(), st);
-    KTimer::end(K_UPDATE, st, tile_bytes(Mq_max, true, true));
-    cg_scalars<R>(nact, nup, w.dpart.get(), 0, s.d_active.get(), cs, 0, st, s.d_list.get());
-    // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, convergence
-    KTimer::begin(K_CG_STEP, st);
-    cg_step<R>(nact, s.d_slot_k.get(), s.d_nb.get(), s.d_kin.get(), nbm, nullptr, w.alpha.get(),
-               w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(), w.dpart.get(), st,
-               s.d_list.get());
-    KTimer::end(K_CG_STEP, st, nact * nb_avg * (7.0 * SZ + 8.0));
-    cg_scalars<R>(nact, nvb, w.dpart.get(), 1, s.d_active.get(), cs, 0, st, s.d_list.get());
-    // z = Q M^-1 r, rz = <r, z>, beta (bands that just converged are skipped)
-    KTimer::begin(K_GRAM, st);
-    gram<R>(ctl, s.d_nb.get(), nbm, dMq, Mq_max, phi, phik, nbm, w.w.get(), nbm,
-            w.part.get(), w.coefA.get(), MAXM, st, s.d_active.get());
-    KTimer::end(K_GRAM, st, tile_bytes(Mq_max, false, false));
-    KTimer::begin(K_UPDATE, st);
-    update<R>(ctl, s.d_nb.get(), nbm, s.d_active.get(), w.w.get(), nbm, R(1), phiA, none,
-              w.r.get(), w.dpart.get(), st);
-    KTimer::end(K_UPDATE, st, tile_bytes(Mq_max, true, true));
-    cg_scalars<R>(nact, nup, w.dpart.get(), 2, s.d_active.get(), cs, 0, st, s.d_list.get());
-    out.n_ham += nact;
-    IKR_HIP(hipMemcpyAsync(hflag.data(), s.d_active.get(), J * sizeof(int),
-                           hipMemcpyDeviceToHost, st));
-    IKR_HIP(hipStreamSynchronize(st));
-    nact = rebuild();
+    nb_avg /= J;
+    ncol_avg /= J;
+    const double SZ = sizeof(cplx<R>), colC = ncol_avg * s.L.C;
+    const std::vector<int> hist = download(s.d_hist.get(), (size_t)2 * iters, st);
+    double b[K_COUNT] = {};
+    int na = nmem, nt = 0;
+    for (int k = 0; k < s.nk; ++k) {
+      int c = 0;
+      for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) c += member[j] != 0;
+      nt += (c + BT - 1) / BT;
+    }
+    for (int it = 0; it < iters; ++it) {
+      b[K_COL_INV] += na * (3.0 * nb_avg + colC) * SZ;
+      b[K_PLANE_HV] += na * 2.0 * colC * SZ + (na > 0 ? sizeof(R) * (double)s.ng : 0.0);
+      b[K_COL_FWD] += na * (colC * SZ + nb_avg * (2.0 * SZ + 8.0));
+      b[K_GRAM] += nt * Mrows * nb_avg * SZ + na * nb_avg * SZ;
+      b[K_UPDATE] += nt * Mrows * nb_avg * SZ + na * 4.0 * nb_avg * SZ;
+      b[K_CG_STEP] += na * nb_avg * (7.0 * SZ + 8.0);
+      na = hist[2 * it];
+      nt = hist[2 * it + 1];
+    }
+    for (int id = 0; id < K_COUNT; ++id)
+      if (b[id] > 0) KTimer::add_bytes(id, b[id]);
   }
-  int noconv = 0;
-  IKR_HIP(hipMemcpyAsync(&noconv, s.d_counters.get() + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-  IKR_HIP(hipStreamSynchronize(st));
-  out.noconv = noconv + nact;
   return out;
 }
 
@@ -353,6 +360,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   // extra bands are treated by sum over states.
   const bool use_schur = schur && s.nbands > s.nocc_max;
   const int* dMq = use_schur ? s.d_nbands_k.get() : s.d_nocc_k.get();
+  const int* dMcg = use_schur ? s.d_mcg_all.get() : s.d_mcg_occ.get();
   const int Mq_max = use_schur ? s.nbands : s.nocc_max;
 
   // right-hand sides t_j = F(u F^-1 phi_j) into r
@@ -418,7 +426,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
       if (tol_slot[j] >= theta * bn[j]) { m32[j] = 1; m64[j] = 0; ++n32; }
   }
   const CgOut o64 = run_cg<double>(s, s.w64, w.r.get(), m64, tol_slot, min_iter, max_iter,
-                                   dMq, Mq_max);
+                                   dMq, Mq_max, dMcg);
   res.n_ham64 = o64.n_ham;
   res.noconv = o64.noconv;
   if (n32 > 0) {
@@ -430,7 +438,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     dl32.upload(l32, st);
     convert_slots(n32, dl32.get(), s.d_slot_k.get(), s.d_nb.get(), nbm, w.r.get(), s.w32.r.get(), st);
     const CgOut o32 = run_cg<float>(s, s.w32, s.w32.r.get(), m32, tol_slot, min_iter,
-                                      max_iter, dMq, Mq_max);
+                                      max_iter, dMq, Mq_max, dMcg);
     convert_slots(n32, dl32.get(), s.d_slot_k.get(), s.d_nb.get(), nbm, s.w32.x.get(), w.x.get(), st);
     res.n_ham32 = o32.n_ham;
     res.noconv += o32.noconv;

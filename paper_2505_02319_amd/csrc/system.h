@@ -52,6 +52,24 @@ template <typename R> struct CgWork {
   DBuf<R> rz, alpha, beta, rnorm2, dpart, pshift, shift;
   DBuf<cplx<R>> phi, proj;     // copies of Phi / projectors in this precision
   DBuf<R> vloc;
+  // fused CG projections: W_k = [projectors | phi_1, H phi_1, phi_2, ...]
+  // ([nk][mcg][nb_max]), G^T and S^T ([nk][nbands][nbands]), raw gram
+  // coefficients and update coefficients ([J][mcg]), <r, z> partials
+  DBuf<cplx<R>> wcg, gT, sT, craw, gam;
+  DBuf<R> zpart;
+};
+
+// Page-locked host memory (for asynchronous device-to-host copies).
+template <typename T> struct HBuf {
+  T* p = nullptr;
+  HBuf() = default;
+  HBuf(const HBuf&) = delete;
+  HBuf& operator=(const HBuf&) = delete;
+  ~HBuf() { if (p) (void)hipHostFree(p); }
+  void alloc(size_t count) {
+    if (p) { (void)hipHostFree(p); p = nullptr; }
+    if (count) IKR_HIP(hipHostMalloc((void**)&p, count * sizeof(T), hipHostMallocDefault));
+  }
 };
 
 struct System {
@@ -113,6 +131,11 @@ struct System {
   DBuf<double2> d_kw1, d_kw2;
   DBuf<int> d_active, d_iters, d_counters;
   DBuf<int> d_list, d_ctk, d_cto, d_ctn;   // compact active slots and their tiles
+  DBuf<int> d_slot0_k;             // first slot of each k
+  int mcg = 0;                     // rows of W_k: natoms + 2 nbands
+  DBuf<int> d_mcg_occ, d_mcg_all;  // rows used per k: natoms + 2 nocc_k / + 2 nbands
+  DBuf<int> d_cnt, d_hist;         // live counts of the compaction, per-iteration history
+  HBuf<int> h_cnt;                 // [2][2] lagged copies of d_cnt
   DBuf<double> d_tol2;
   std::vector<double> knorm_hist;
 
