@@ -72,23 +72,44 @@ __global__ __launch_bounds__(NT) void gram_kernel(
   const int wave = tid >> 6, lane = tid & 63;
   const cplx<R>* Wk = W + (size_t)k * wk_stride;
   const int gbeg = sc * sc_len, gend = min(n, gbeg + sc_len);
+  // chunks are fetched into registers one chunk ahead of their use
+  constexpr int XL = BT * CH / NT;
+  constexpr int WL = (MT * CH + NT - 1) / NT;
+  static_assert(BT * CH % NT == 0, "gram staging");
+  cplx<R> xr[XL], wr[WL];
+  auto fetch = [&](int g0, int m0) {
+#pragma unroll
+    for (int l = 0; l < XL; ++l) {
+      const int i = tid + l * NT, b = i / CH, e = i % CH, gg = g0 + e;
+      xr[l] = (b < nbt && gg < gend) ? X[(size_t)ss[b] * x_stride + gg] : mk<R>(0, 0);
+    }
+#pragma unroll
+    for (int l = 0; l < WL; ++l) {
+      const int i = tid + l * NT, m = i / CH, e = i % CH, gg = g0 + e;
+      wr[l] = (i < MT * CH && m0 + m < M && gg < gend) ? Wk[(size_t)(m0 + m) * w_stride + gg]
+                                                        : mk<R>(0, 0);
+    }
+  };
   for (int m0 = 0; m0 < M; m0 += MT) {
     R ar[RB][4], ai[RB][4];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) ar[i][j] = ai[i][j] = R(0);
+    if (gbeg < gend) fetch(gbeg, m0);
     for (int g0 = gbeg; g0 < gend; g0 += CH) {
-      for (int i = tid; i < BT * CH; i += NT) {
-        const int b = i / CH, e = i % CH, gg = g0 + e;
-        Xs[b * LW + e] = (b < nbt && gg < gend) ? X[(size_t)ss[b] * x_stride + gg] : mk<R>(0, 0);
+#pragma unroll
+      for (int l = 0; l < XL; ++l) {
+        const int i = tid + l * NT;
+        Xs[(i / CH) * LW + i % CH] = xr[l];
       }
-      for (int i = tid; i < MT * CH; i += NT) {
-        const int m = i / CH, e = i % CH, gg = g0 + e;
-        Ws[m * LW + e] = (m0 + m < M && gg < gend) ? Wk[(size_t)(m0 + m) * w_stride + gg]
-                                                   : mk<R>(0, 0);
+#pragma unroll
+      for (int l = 0; l < WL; ++l) {
+        const int i = tid + l * NT;
+        if (i < MT * CH) Ws[(i / CH) * LW + i % CH] = wr[l];
       }
       __syncthreads();
+      if (g0 + CH < gend) fetch(g0 + CH, m0);
 #pragma unroll
       for (int u = 0; u < CH / KS; ++u) {
         const int e = ks + KS * u;
@@ -208,38 +229,56 @@ __global__ __launch_bounds__(NT) void update_kernel(
   cplx<R> acc[BPT];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) acc[b] = mk<R>(0, 0);
+  // rows are loaded U at a time before use, so that their latencies overlap
+  constexpr int U = 4;
+  auto term = [&](const cplx<R>* Wt, int ws, int M, const cplx<R>* c, int Mmax) {
+    int m = 0;
+    for (; m + U <= M; m += U) {
+      cplx<R> w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) w[u] = Wt[(size_t)(m + u) * ws];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w[u], c[b * Mmax + m + u]));
+    }
+    for (; m < M; ++m) {
+      const cplx<R> w = Wt[(size_t)m * ws];
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c[b * Mmax + m]));
+    }
+  };
   if (g < n) {
-    const cplx<R>* w1 = W1 ? W1 + (size_t)k * w1k + g : nullptr;
-    for (int m = 0; m < M1; ++m) {
-      const cplx<R> w = w1[(size_t)m * w1s];
-#pragma unroll
-      for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c1[b * M1max + m]));
-    }
-    const cplx<R>* w2 = W2 ? W2 + (size_t)k * w2k + g : nullptr;
-    for (int m = 0; m < M2; ++m) {
-      const cplx<R> w = w2[(size_t)m * w2s];
-#pragma unroll
-      for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c2[b * M2max + m]));
-    }
+    if (W1) term(W1 + (size_t)k * w1k + g, w1s, M1, c1, M1max);
+    if (W2) term(W2 + (size_t)k * w2k + g, w2s, M2, c2, M2max);
   }
+  // outputs U bands at a time: loads first, then the stores
 #pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int slot = ss[b];
-    const bool on = b < nbg && (!active || active[slot]);
-    R d = 0;
-    if (on && g < n) {
-      cplx<R>* yp = Y + (size_t)slot * y_stride + g;
-      cplx<R> y = a != R(0) ? *yp : mk<R>(0, 0);     // a = 0: Y is write-only
-      y = mk<R>(a * y.x + acc[b].x, a * y.y + acc[b].y);
-      *yp = y;
-      if (D) {
-        const cplx<R> dd = D[(size_t)slot * y_stride + g];
-        d = dd.x * y.x + dd.y * y.y;
+  for (int b0 = 0; b0 < BPT; b0 += U) {
+    cplx<R> yv[U], dv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      yv[u] = dv[u] = mk<R>(0, 0);
+      const int slot = ss[b0 + u];
+      if (b0 + u < nbg && (!active || active[slot]) && g < n) {
+        if (a != R(0)) yv[u] = Y[(size_t)slot * y_stride + g];   // a = 0: Y is write-only
+        if (D) dv[u] = D[(size_t)slot * y_stride + g];
       }
     }
-    if (dpart) {
-      d = wave_sum(d);
-      if ((tid & 63) == 0) red[(tid >> 6) * BPT + b] = d;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u;
+      const int slot = ss[b];
+      R d = 0;
+      if (b < nbg && (!active || active[slot]) && g < n) {
+        const cplx<R> y = mk<R>(a * yv[u].x + acc[b].x, a * yv[u].y + acc[b].y);
+        Y[(size_t)slot * y_stride + g] = y;
+        d = dv[u].x * y.x + dv[u].y * y.y;
+      }
+      if (dpart) {
+        d = wave_sum(d);
+        if ((tid & 63) == 0) red[(tid >> 6) * BPT + b] = d;
+      }
     }
   }
   if (dpart) {

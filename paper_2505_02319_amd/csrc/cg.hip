@@ -139,14 +139,43 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(
   cplx<R> a1[BPT], a2[BPT];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) a1[b] = a2[b] = mk<R>(0, 0);
+  // rows are loaded U at a time before use, so that their latencies overlap
+  constexpr int U = 4;
   if (g < n) {
     const cplx<R>* W = Wcg + (size_t)k * wk + g;
-    for (int r = 0; r < Na; ++r) {
+    int r = 0;
+    for (; r + U <= Na; r += U) {
+      cplx<R> w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) w[u] = W[(size_t)(r + u) * nb_max];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) a1[b] = cadd<R>(a1[b], cmul<R>(w[u], cg[b * Mr + r + u]));
+    }
+    for (; r < Na; ++r) {
       const cplx<R> w = W[(size_t)r * nb_max];
 #pragma unroll
       for (int b = 0; b < BPT; ++b) a1[b] = cadd<R>(a1[b], cmul<R>(w, cg[b * Mr + r]));
     }
-    for (int m = 0; m < M; ++m) {
+    int m = 0;
+    for (; m + U <= M; m += U) {
+      cplx<R> f[U], h[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        f[u] = W[(size_t)(Na + 2 * (m + u)) * nb_max];
+        h[u] = W[(size_t)(Na + 2 * (m + u) + 1) * nb_max];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int b = 0; b < BPT; ++b) {
+          const int c0 = b * Mr + Na + 2 * (m + u);
+          a1[b] = cadd<R>(a1[b], cadd<R>(cmul<R>(f[u], cg[c0]), cmul<R>(h[u], cg[c0 + 1])));
+          a2[b] = cadd<R>(a2[b], cmul<R>(f[u], ca[b * Mq_max + m + u]));
+        }
+    }
+    for (; m < M; ++m) {
       const cplx<R> f = W[(size_t)(Na + 2 * m) * nb_max];
       const cplx<R> h = W[(size_t)(Na + 2 * m + 1) * nb_max];
 #pragma unroll
@@ -157,19 +186,34 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(
       }
     }
   }
+  // outputs U bands at a time: loads first, then the stores
 #pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    R d = 0;
-    if (b < nbg && g < n) {
-      const size_t o = (size_t)ss[b] * nb_max + g;
-      const cplx<R> ap = cadd<R>(Wv[o], a1[b]);
-      const cplx<R> pv = cadd<R>(P[o], a2[b]);
-      Wv[o] = ap;
-      P[o] = pv;
-      d = pv.x * ap.x + pv.y * ap.y;
+  for (int b0 = 0; b0 < BPT; b0 += U) {
+    cplx<R> wv[U], pv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      wv[u] = pv[u] = mk<R>(0, 0);
+      if (b0 + u < nbg && g < n) {
+        const size_t o = (size_t)ss[b0 + u] * nb_max + g;
+        wv[u] = Wv[o];
+        pv[u] = P[o];
+      }
     }
-    d = wsum(d);
-    if ((tid & 63) == 0) red[(tid >> 6) * BPT + b] = d;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u;
+      R d = 0;
+      if (b < nbg && g < n) {
+        const size_t o = (size_t)ss[b] * nb_max + g;
+        const cplx<R> ap = cadd<R>(wv[u], a1[b]);
+        const cplx<R> pn = cadd<R>(pv[u], a2[b]);
+        Wv[o] = ap;
+        P[o] = pn;
+        d = pn.x * ap.x + pn.y * ap.y;
+      }
+      d = wsum(d);
+      if ((tid & 63) == 0) red[(tid >> 6) * BPT + b] = d;
+    }
   }
   __syncthreads();
   if (tid < nbg) {
@@ -341,7 +385,9 @@ void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, s
   IKR_CHECK(Na + 2 * Mq_max <= cstride, 1, "cg_update: row count");
   const int ngb = update_nblocks(nb_max);
   const int blocks = ngb * tl.n;
-  const int bpt = blocks >= 1024 ? 16 : (2 * blocks >= 1024 ? 8 : 4);
+  // FP64 caps the band group at 8 (16 would leave one wavefront per SIMD)
+  int bpt = blocks >= 1024 ? 16 : (2 * blocks >= 1024 ? 8 : 4);
+  if (sizeof(R) == 8 && bpt > 8) bpt = 8;
   const size_t lds = (size_t)bpt * (Na + 3 * Mq_max) * sizeof(cplx<R>);
   IKR_CHECK(lds <= 65536, 1, "cg_update: too many projection rows");
   const dim3 grid(ngb * (BT / bpt), tl.n);

@@ -29,6 +29,12 @@ __device__ __forceinline__ int find_col(const int* s, int ncb, int e) {
   return lo;
 }
 
+// Twiddle table of length N copied into LDS (read by every butterfly stage).
+template <typename R, int N>
+__device__ __forceinline__ void load_tw(cplx<R>* dst, const cplx<R>* __restrict__ src) {
+  for (int i = threadIdx.x; i < N; i += NT) dst[i] = src[i];
+}
+
 template <int C> constexpr int ncb_for() { return C <= 24 ? 32 : (C <= 64 ? 32 : 16); }
 
 // ---------------------------------------------------------------- columns
@@ -51,6 +57,7 @@ __global__ __launch_bounds__(NT) void col_kernel(
   __shared__ cplx<R> buf[NCB * LS];
   __shared__ int sstart[NCB + 1];
   __shared__ int sclo[NCB];
+  __shared__ cplx<R> stw[C];
 
   if (!row_live(s, blockIdx.y)) return;
   const int slot = slot_of(s, blockIdx.y);
@@ -62,6 +69,7 @@ __global__ __launch_bounds__(NT) void col_kernel(
   const int ncb = min(NCB, ncol - col0);
   const int tid = threadIdx.x;
   const size_t tbase = (size_t)slot * C * g.ncol_max;
+  load_tw<R, C>(stw, tw);
 
   if (MODE == 0) {
     for (int i = tid; i < NCB * LS; i += NT) buf[i] = mk<R>(0, 0);
@@ -72,28 +80,46 @@ __global__ __launch_bounds__(NT) void col_kernel(
     __syncthreads();
     const int e0 = sstart[0], e1 = sstart[ncb];
     const cplx<R>* xs = xin + (size_t)slot * x_stride;
-    for (int e = e0 + tid; e < e1; e += NT) {
-      const int l = find_col(sstart, ncb, e);
-      const int c = fold(sclo[l] + (e - sstart[l]), C);
-      cplx<R> v = xs[e];
-      if (z) {
-        const R b = beta[slot];
-        const cplx<R> zz = z[(size_t)slot * x_stride + e];
-        v = mk<R>(zz.x + b * v.x, zz.y + b * v.y);
-        pout[(size_t)slot * x_stride + e] = v;
+    const R b = z ? beta[slot] : R(0);
+    // U elements per thread and round: loads first, so their latencies overlap
+    constexpr int U = 4;
+    for (int e00 = e0 + tid; e00 < e1; e00 += U * NT) {
+      cplx<R> v[U], zz[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e00 + u * NT;
+        if (e < e1) {
+          v[u] = xs[e];
+          if (z) zz[u] = z[(size_t)slot * x_stride + e];
+        }
       }
-      buf[l * LS + c] = v;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e00 + u * NT;
+        if (e < e1) {
+          const int l = find_col(sstart, ncb, e);
+          const int c = fold(sclo[l] + (e - sstart[l]), C);
+          cplx<R> w = v[u];
+          if (z) {
+            w = mk<R>(zz[u].x + b * w.x, zz[u].y + b * w.y);
+            pout[(size_t)slot * x_stride + e] = w;
+          }
+          buf[l * LS + c] = w;
+        }
+      }
     }
     __syncthreads();
-    lds_fft<R, C, TPL, NT, MAXV, true>(buf, ncb, LS, 1, tw);
+    lds_fft<R, C, TPL, NT, MAXV, true>(buf, ncb, LS, 1, stw);
     for (int i = tid; i < C * NCB; i += NT) {
       const int c = i / NCB, l = i % NCB;
       if (l < ncb) T[tbase + (size_t)c * g.ncol_max + col0 + l] = buf[l * LS + c];
     }
   } else {
-    for (int i = tid; i < C * NCB; i += NT) {
+#pragma unroll
+    for (int u = 0; u < (C * NCB + NT - 1) / NT; ++u) {
+      const int i = tid + u * NT;
       const int c = i / NCB, l = i % NCB;
-      if (l < ncb) buf[l * LS + c] = T[tbase + (size_t)c * g.ncol_max + col0 + l];
+      if (i < C * NCB && l < ncb) buf[l * LS + c] = T[tbase + (size_t)c * g.ncol_max + col0 + l];
     }
     if (MODE == 1) {
       const int* cs = g.col_start + (size_t)k * (g.ncol_max + 1) + col0;
@@ -102,21 +128,37 @@ __global__ __launch_bounds__(NT) void col_kernel(
       for (int i = tid; i < ncb; i += NT) sclo[i] = cl[i];
     }
     __syncthreads();
-    lds_fft<R, C, TPL, NT, MAXV, false>(buf, ncb, LS, 1, tw);
+    lds_fft<R, C, TPL, NT, MAXV, false>(buf, ncb, LS, 1, stw);
     if (MODE == 1) {
       const int e0 = sstart[0], e1 = sstart[ncb];
       const double* kin = g.kin + (size_t)k * g.nb_max;
       const R sh = shift ? shift[slot] : R(0);
-      for (int e = e0 + tid; e < e1; e += NT) {
-        const int l = find_col(sstart, ncb, e);
-        const int c = fold(sclo[l] + (e - sstart[l]), C);
-        cplx<R> v = cscale<R>(buf[l * LS + c], scale);
-        if (xin) {
-          const cplx<R> xx = xin[(size_t)slot * x_stride + e];
-          const R d = R(kin[e]) - sh;
-          v = mk<R>(v.x + d * xx.x, v.y + d * xx.y);
+      constexpr int U = 4;
+      for (int e00 = e0 + tid; e00 < e1; e00 += U * NT) {
+        cplx<R> xx[U];
+        R kv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = e00 + u * NT;
+          if (xin && e < e1) {
+            xx[u] = xin[(size_t)slot * x_stride + e];
+            kv[u] = R(kin[e]);
+          }
         }
-        yout[(size_t)slot * y_stride + e] = v;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int e = e00 + u * NT;
+          if (e < e1) {
+            const int l = find_col(sstart, ncb, e);
+            const int c = fold(sclo[l] + (e - sstart[l]), C);
+            cplx<R> v = cscale<R>(buf[l * LS + c], scale);
+            if (xin) {
+              const R d = kv[u] - sh;
+              v = mk<R>(v.x + d * xx[u].x, v.y + d * xx[u].y);
+            }
+            yout[(size_t)slot * y_stride + e] = v;
+          }
+        }
       }
     } else {
       // MODE 2: multiply by khat (internal layout [c][pq]) and transform back
@@ -128,7 +170,7 @@ __global__ __launch_bounds__(NT) void col_kernel(
         }
       }
       __syncthreads();
-      lds_fft<R, C, TPL, NT, MAXV, true>(buf, ncb, LS, 1, tw);
+      lds_fft<R, C, TPL, NT, MAXV, true>(buf, ncb, LS, 1, stw);
       for (int i = tid; i < C * NCB; i += NT) {
         const int c = i / NCB, l = i % NCB;
         if (l < ncb) T[tbase + (size_t)c * g.ncol_max + col0 + l] = buf[l * LS + c];
@@ -166,6 +208,9 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
     const R* __restrict__ V, int v_per_slot) {
   constexpr int LQ = Q + 1;
   __shared__ cplx<R> pl[P * LQ];
+  __shared__ cplx<R> sP[P], sQ[Q];
+  load_tw<R, P>(sP, twP);
+  load_tw<R, Q>(sQ, twQ);
   if (!row_live(s, blockIdx.y)) return;
   const int slot = slot_of(s, blockIdx.y);
   if (s.active && !s.active[slot]) return;
@@ -177,19 +222,42 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
   __syncthreads();
   const int* pq = g.col_pq + (size_t)k * g.ncol_max;
   const size_t tb = ((size_t)slot * g.C + c) * g.ncol_max;
-  for (int col = tid; col < ncol; col += NT) {
-    const int v = pq[col];
-    pl[(v / Q) * LQ + (v % Q)] = Tin[tb + col];
+  constexpr int U = 4;   // columns per thread and round, loads first
+  for (int c00 = tid; c00 < ncol; c00 += U * NT) {
+    cplx<R> tv[U];
+    int pv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int col = c00 + u * NT;
+      if (col < ncol) {
+        pv[u] = pq[col];
+        tv[u] = Tin[tb + col];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (c00 + u * NT < ncol) pl[(pv[u] / Q) * LQ + (pv[u] % Q)] = tv[u];
   }
   __syncthreads();
-  fft2d<R, P, Q, true>(pl, twP, twQ);
+  fft2d<R, P, Q, true>(pl, sP, sQ);
   const R* vp = V + (v_per_slot ? (size_t)slot * g.C * P * Q : 0) + (size_t)c * P * Q;
-  for (int i = tid; i < P * Q; i += NT) {
-    const int p = i / Q, q = i % Q;
-    pl[p * LQ + q] = cscale<R>(pl[p * LQ + q], vp[i]);
+  constexpr int NV = (P * Q + NT - 1) / NT;
+  R vv[NV];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int i = tid + u * NT;
+    if (i < P * Q) vv[u] = vp[i];
+  }
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int i = tid + u * NT;
+    if (i < P * Q) {
+      const int p = i / Q, q = i % Q;
+      pl[p * LQ + q] = cscale<R>(pl[p * LQ + q], vv[u]);
+    }
   }
   __syncthreads();
-  fft2d<R, P, Q, false>(pl, twP, twQ);
+  fft2d<R, P, Q, false>(pl, sP, sQ);
   for (int col = tid; col < ncol; col += NT) {
     const int v = pq[col];
     Tout[tb + col] = pl[(v / Q) * LQ + (v % Q)];
@@ -207,6 +275,9 @@ __global__ __launch_bounds__(NT) void plane_rho_kernel(
   constexpr int LQ = Q + 1;
   constexpr int OWN = (P * Q + NT - 1) / NT;
   __shared__ double2 pl[P * LQ];
+  __shared__ double2 sP[P], sQ[Q];
+  load_tw<double, P>(sP, twP);
+  load_tw<double, Q>(sQ, twQ);
   const int c = blockIdx.x;
   const int grp = blockIdx.y;
   const int tid = threadIdx.x;
@@ -224,12 +295,24 @@ __global__ __launch_bounds__(NT) void plane_rho_kernel(
       const double2* T = pass == 0 ? Ta : Tb;
       for (int i = tid; i < P * LQ; i += NT) pl[i] = mk<double>(0, 0);
       __syncthreads();
-      for (int col = tid; col < ncol; col += NT) {
-        const int v = pq[col];
-        pl[(v / Q) * LQ + (v % Q)] = T[tb + col];
+      constexpr int U = 4;   // columns per thread and round, loads first
+      for (int c00 = tid; c00 < ncol; c00 += U * NT) {
+        double2 tv[U];
+        int pv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int col = c00 + u * NT;
+          if (col < ncol) {
+            pv[u] = pq[col];
+            tv[u] = T[tb + col];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if (c00 + u * NT < ncol) pl[(pv[u] / Q) * LQ + (pv[u] % Q)] = tv[u];
       }
       __syncthreads();
-      fft2d<double, P, Q, true>(pl, twP, twQ);
+      fft2d<double, P, Q, true>(pl, sP, sQ);
       const double ka = wa[slot], kb = wb[slot];
 #pragma unroll
       for (int o = 0; o < OWN; ++o) {
@@ -263,6 +346,9 @@ __global__ __launch_bounds__(NT) void plane_grid_kernel(
     double2* __restrict__ grid) {
   constexpr int LQ = Q + 1;
   __shared__ double2 pl[P * LQ];
+  __shared__ double2 sP[P], sQ[Q];
+  load_tw<double, P>(sP, twP);
+  load_tw<double, Q>(sQ, twQ);
   const int c = blockIdx.x, slot = blockIdx.y, tid = threadIdx.x;
   const int k = slot_k[slot];
   const int ncol = g.ncol[k];
@@ -275,7 +361,7 @@ __global__ __launch_bounds__(NT) void plane_grid_kernel(
     pl[(v / Q) * LQ + (v % Q)] = T[tb + col];
   }
   __syncthreads();
-  fft2d<double, P, Q, true>(pl, twP, twQ);
+  fft2d<double, P, Q, true>(pl, sP, sQ);
   double2* out = grid + ((size_t)slot * g.C + c) * P * Q;
   for (int i = tid; i < P * Q; i += NT) out[i] = pl[(i / Q) * LQ + (i % Q)];
 }
@@ -287,11 +373,14 @@ __global__ __launch_bounds__(NT) void plane_fwd_kernel(
     const double* __restrict__ v, double2* __restrict__ T) {
   constexpr int LQ = Q + 1;
   __shared__ double2 pl[P * LQ];
+  __shared__ double2 sP[P], sQ[Q];
+  load_tw<double, P>(sP, twP);
+  load_tw<double, Q>(sQ, twQ);
   const int c = blockIdx.x, tid = threadIdx.x;
   const double* vp = v + (size_t)c * P * Q;
   for (int i = tid; i < P * Q; i += NT) pl[(i / Q) * LQ + (i % Q)] = mk<double>(vp[i], 0.0);
   __syncthreads();
-  fft2d<double, P, Q, false>(pl, twP, twQ);
+  fft2d<double, P, Q, false>(pl, sP, sQ);
   double2* out = T + (size_t)c * P * Q;
   for (int i = tid; i < P * Q; i += NT) out[i] = pl[(i / Q) * LQ + (i % Q)];
 }
@@ -305,12 +394,15 @@ __global__ __launch_bounds__(NT) void plane_inv_kernel(
     double* __restrict__ partial) {
   constexpr int LQ = Q + 1;
   __shared__ double2 pl[P * LQ];
+  __shared__ double2 sP[P], sQ[Q];
+  load_tw<double, P>(sP, twP);
+  load_tw<double, Q>(sQ, twQ);
   __shared__ double red[NT];
   const int c = blockIdx.x, tid = threadIdx.x;
   const double2* tp = T + (size_t)c * P * Q;
   for (int i = tid; i < P * Q; i += NT) pl[(i / Q) * LQ + (i % Q)] = tp[i];
   __syncthreads();
-  fft2d<double, P, Q, true>(pl, twP, twQ);
+  fft2d<double, P, Q, true>(pl, sP, sQ);
   const double inv_ng = 1.0 / ((double)g.C * P * Q);
   const size_t base = (size_t)c * P * Q;
   double ss = 0.0;
