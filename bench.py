@@ -76,7 +76,11 @@ def main():
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--schur", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-checks", action="store_true",
+                    help="skip the untimed accuracy and FP64 comparison solves")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the response path here is single-GPU "
@@ -84,6 +88,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_probe:
+        copy_probe(torch, args.copy_probe)
+        return
 
     from paper_2505_02319_amd import (ResponseSystem, default_opts, profile_enable,
                                       profile_query, profile_reset)
@@ -133,7 +141,58 @@ def main():
     profile_enable(False)
     prof = profile_query()
 
-    # accuracy of the returned solution (untimed): true residual with tight CG
+    bnorm = float(torch.linalg.norm(b))
+    true_rel, fp64, n32 = None, None, None
+    if not args.no_checks:
+        true_rel, fp64, n32 = accuracy_checks(rs, b, bnorm, args, default_opts)
+
+    launches, ms, by = prof[dom]
+    achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
+                   "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+               for k, v in allk.items()}
+    bytes_per_launch = by / max(launches, 1)
+    value = args.steps / elapsed
+    out = {
+        "metric": "drho solves/s at rel. res 1e-8",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == 0 else "f32/f64",
+        "fp64_cg_solve": fp64,
+        "n_ham_fp32_per_solve": n32,
+        "data": "synthetic",
+        "config": {"workload": describe(spec, args), "global_batch": 1,
+                   "parallelism": "single-gpu"},
+        "hpsi_band_applies_per_s": n_ham / elapsed,
+        "n_ham_per_solve": n_ham / args.steps,
+        "gmres_iters_per_solve": gm / args.steps,
+        "true_rel_residual": true_rel,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(spec.name, dom),
+                     "avg_launch_us": 1e3 * ms / max(launches, 1),
+                     "bytes_per_launch": bytes_per_launch},
+        "kernels_warmup_step": kernels,
+        "setup_seconds": t_setup,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(spec, n_ham / args.steps, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    rs.close()
+
+
+def accuracy_checks(rs, b, bnorm, args, default_opts):
+    """Untimed: the true residual of the benchmarked solve (tight CG), and the
+    same solve with the Sternheimer CG in FP64 throughout."""
+    import torch
     vopts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
                          precision=args.precision, schur=args.schur, want_true_residual=1)
     xv, vst = rs.solve(b, vopts)
@@ -149,52 +208,69 @@ def main():
             "true_rel_residual": pst["true_res"] / bnorm,
             "rel_diff_vs_mixed": float(torch.linalg.norm(xv - xp) / torch.linalg.norm(xp))}
     log(f"fp64 CG: {pst['seconds']:.3f} s, true rel. residual {fp64['true_rel_residual']:.2e}")
+    return true_rel, fp64, vst["n_ham_fp32"]
 
-    launches, ms, by = prof[dom]
-    achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    kernels = {k: {"launches": v[0], "ms": round(v[1], 3),
-                   "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
-               for k, v in allk.items()}
-    value = args.steps / elapsed
-    out = {
-        "metric": "drho solves/s at rel. res 1e-8",
-        "value": value,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == 0 else "f32/f64",
-        "fp64_cg_solve": fp64,
-        "n_ham_fp32_per_solve": vst["n_ham_fp32"],
-        "data": "synthetic",
-        "config": {"workload": f"{spec.name}: 8-atom cubic cell a=20.52 bohr, Ecut 15 Ha, "
-                               f"FFT 48^3, 2x2x2 k, 16+4 bands, K_H + Slater, "
-                               f"strategy {args.strategy}, extra bands by sum over states "
-                               f"{'on' if args.schur else 'off'}, "
-                               f"CG precision {'mixed' if args.precision else 'fp64'}, "
-                               f"m 20, tau 1e-8||b||",
-                   "global_batch": 1, "parallelism": "single-gpu"},
-        "hpsi_band_applies_per_s": n_ham / elapsed,
-        "n_ham_per_solve": n_ham / args.steps,
-        "gmres_iters_per_solve": gm / args.steps,
-        "true_rel_residual": true_rel,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None,
-                     "avg_launch_us": 1e3 * ms / max(launches, 1),
-                     "bytes_per_launch": by / max(launches, 1)},
-        "kernels_warmup_step": kernels,
-        "setup_seconds": t_setup,
-    }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(spec, n_ham / args.steps, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
-    rs.close()
+
+def describe(spec, args):
+    L = spec.lattice
+    return (f"{spec.name}: {len(spec.frac_pos)}-atom cell {L[0]:g}x{L[1]:g}x{L[2]:g} bohr, "
+            f"Ecut {spec.ecut:g} Ha, FFT {spec.fft[0]}x{spec.fft[1]}x{spec.fft[2]}, "
+            f"{spec.kgrid[0]}x{spec.kgrid[1]}x{spec.kgrid[2]} k, {spec.nocc}+{spec.nextra} bands, "
+            f"T {spec.temperature:g}, K_H{' + Slater' if spec.xc else ''}, "
+            f"strategy {args.strategy}, extra bands by sum over states "
+            f"{'on' if args.schur else 'off'}, CG precision "
+            f"{'mixed' if args.precision else 'fp64'}, m 20, tau 1e-8||b||")
+
+
+def copy_probe(torch, mib):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(5):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "copies": 5}), flush=True)
+
+
+KERNEL_SOURCES = {   # sources whose change invalidates a kernel's counter readings
+    "plane_hv": ["fft.hip", "fft_core.h", "common.h"],
+    "col_inv": ["fft.hip", "fft_core.h", "common.h"],
+    "col_fwd": ["fft.hip", "fft_core.h", "common.h"],
+    "gram": ["blas.hip", "blas.h", "common.h"],
+    "update": ["cg.hip", "cg.h", "blas.h", "common.h"],
+    "cg_step": ["cg.hip", "cg.h", "common.h"],
+}
+
+
+def source_digest(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel.replace("_fp32", ""), []):
+        with open(os.path.join(ROOT, "paper_2505_02319_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of the kernel from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, each scaled by the same counter's reading
+    for a plain copy of known size); None when there is none for this kernel
+    and workload, or when the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if not line.startswith("traffic:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if kv.get("kernel") != kernel or kv.get("source") != source_digest(kernel):
+                continue
+            return (float(kv["fetch_kib"]) * 1024 / float(kv["fetch_factor"]) +
+                    float(kv["write_kib"]) * 1024 / float(kv["write_factor"]))
+    return None
 
 
 if __name__ == "__main__":

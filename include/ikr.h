@@ -212,7 +212,8 @@ ikr_status ikr_solve_response(ikr_handle h, const double* b_dev,
  * stream (0 disables, -1 times all); each launch carries its algorithmic
  * byte count (bytes the kernel must move to or from HBM by its definition,
  * not by measurement).  kernel_id indexes ikr_profile_kernel_name
- * (0 .. ikr_profile_kernel_count()-1). */
+ * (0 .. ikr_profile_kernel_count()-1); the FP32 launches of the mixed-
+ * precision CG are timed under their own ids (names ending in "_fp32"). */
 ikr_status ikr_profile_enable(int kernel_mask);
 ikr_status ikr_profile_reset(void);
 int ikr_profile_kernel_count(void);

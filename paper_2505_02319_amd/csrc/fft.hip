@@ -51,9 +51,6 @@ __global__ __launch_bounds__(NT) void col_kernel(
     const R* __restrict__ shift, R scale, const R* __restrict__ khat) {
   constexpr int NCB = ncb_for<C>();
   constexpr int LS = C + 1;                      // padded line stride
-  constexpr int TPL = tpl_for<C>();
-  constexpr int G = NT / TPL;
-  constexpr int MAXV = (NCB + G - 1) / G;
   __shared__ cplx<R> buf[NCB * LS];
   __shared__ int sstart[NCB + 1];
   __shared__ int sclo[NCB];
@@ -109,7 +106,7 @@ __global__ __launch_bounds__(NT) void col_kernel(
       }
     }
     __syncthreads();
-    lds_fft<R, C, TPL, NT, MAXV, true>(buf, ncb, LS, 1, stw);
+    lds_fft<R, C, NT, NCB, true>(buf, ncb, LS, 1, stw);
     for (int i = tid; i < C * NCB; i += NT) {
       const int c = i / NCB, l = i % NCB;
       if (l < ncb) T[tbase + (size_t)c * g.ncol_max + col0 + l] = buf[l * LS + c];
@@ -128,7 +125,7 @@ __global__ __launch_bounds__(NT) void col_kernel(
       for (int i = tid; i < ncb; i += NT) sclo[i] = cl[i];
     }
     __syncthreads();
-    lds_fft<R, C, TPL, NT, MAXV, false>(buf, ncb, LS, 1, stw);
+    lds_fft<R, C, NT, NCB, false>(buf, ncb, LS, 1, stw);
     if (MODE == 1) {
       const int e0 = sstart[0], e1 = sstart[ncb];
       const double* kin = g.kin + (size_t)k * g.nb_max;
@@ -170,7 +167,7 @@ __global__ __launch_bounds__(NT) void col_kernel(
         }
       }
       __syncthreads();
-      lds_fft<R, C, TPL, NT, MAXV, true>(buf, ncb, LS, 1, stw);
+      lds_fft<R, C, NT, NCB, true>(buf, ncb, LS, 1, stw);
       for (int i = tid; i < C * NCB; i += NT) {
         const int c = i / NCB, l = i % NCB;
         if (l < ncb) T[tbase + (size_t)c * g.ncol_max + col0 + l] = buf[l * LS + c];
@@ -180,23 +177,16 @@ __global__ __launch_bounds__(NT) void col_kernel(
 }
 
 // ---------------------------------------------------------------- planes
-template <int P, int Q> constexpr int plane_maxv_rows() {
-  return (P + (NT / tpl_for<Q>()) - 1) / (NT / tpl_for<Q>());
-}
-template <int P, int Q> constexpr int plane_maxv_cols() {
-  return (Q + (NT / tpl_for<P>()) - 1) / (NT / tpl_for<P>());
-}
-
 template <typename R, int P, int Q, bool INV>
 __device__ __forceinline__ void fft2d(cplx<R>* pl, const cplx<R>* twP,
                                       const cplx<R>* twQ) {
   constexpr int LQ = Q + 1;
   if (INV) {
-    lds_fft<R, Q, tpl_for<Q>(), NT, plane_maxv_rows<P, Q>(), true>(pl, P, LQ, 1, twQ);
-    lds_fft<R, P, tpl_for<P>(), NT, plane_maxv_cols<P, Q>(), true>(pl, Q, 1, LQ, twP);
+    lds_fft<R, Q, NT, P, true>(pl, P, LQ, 1, twQ);
+    lds_fft<R, P, NT, Q, true>(pl, Q, 1, LQ, twP);
   } else {
-    lds_fft<R, P, tpl_for<P>(), NT, plane_maxv_cols<P, Q>(), false>(pl, Q, 1, LQ, twP);
-    lds_fft<R, Q, tpl_for<Q>(), NT, plane_maxv_rows<P, Q>(), false>(pl, P, LQ, 1, twQ);
+    lds_fft<R, P, NT, Q, false>(pl, Q, 1, LQ, twP);
+    lds_fft<R, Q, NT, P, false>(pl, P, LQ, 1, twQ);
   }
 }
 

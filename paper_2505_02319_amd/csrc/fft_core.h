@@ -107,74 +107,66 @@ template <typename R, bool INV> struct Dft<R, 5, INV> {
 };
 
 // ------------------------------------------------------------ stage driver
-// Lines live in LDS at buf[l * lstride + e * estride], l < nlines.
-// NT threads, TPL threads per line, MAXV = max lines per thread group.
-template <typename R, int N, int TPL, int NT, int MAXV, bool INV, int STAGE, int NS>
+// Lines live in LDS at buf[l * lstride + e * estride], l < nlines <= MAXL.
+// The (line, butterfly) pairs of a stage are dealt out flat over the NT
+// threads (pair i -> line i / NB, butterfly i % NB), so every thread has at
+// most ceil(MAXL * NB / NT) butterflies whatever the line count, and the
+// lanes of a wavefront touch consecutive butterflies (distinct LDS banks
+// along a line, and for strided lines too since the line pitch is odd).
+template <typename R, int N, int NT, int MAXL, bool INV, int STAGE, int NS>
 struct Stages {
   __device__ __forceinline__ static void run(cplx<R>* buf, int nlines,
                                              int lstride, int estride,
                                              const cplx<R>* __restrict__ tw) {
     constexpr int RAD = Rad<N>::r[STAGE];
     constexpr int NB = N / RAD;                   // butterflies per line
-    constexpr int BPT = (NB + TPL - 1) / TPL;     // butterflies per thread
-    constexpr int G = NT / TPL;                   // thread groups
+    constexpr int NV = (MAXL * NB + NT - 1) / NT; // butterflies per thread
+    const int tot = nlines * NB;
     const int tid = threadIdx.x;
-    const int grp = tid / TPL, lane = tid % TPL;
-    cplx<R> v[MAXV][BPT][RAD];
+    cplx<R> v[NV][RAD];
 #pragma unroll
-    for (int vl = 0; vl < MAXV; ++vl) {
-      const int l = grp + G * vl;
+    for (int vi = 0; vi < NV; ++vi) {
+      const int i = tid + NT * vi;
+      if (i < tot) {
+        const int l = i / NB, b = i % NB;
+        cplx<R>* line = buf + l * lstride;
 #pragma unroll
-      for (int u = 0; u < BPT; ++u) {
-        const int b = lane + TPL * u;
-        if (grp < G && l < nlines && b < NB) {
-          cplx<R>* line = buf + l * lstride;
-#pragma unroll
-          for (int r = 0; r < RAD; ++r) {
-            cplx<R> x = line[(b + r * NB) * estride];
-            if (NS > 1 && r > 0) {
-              cplx<R> w = tw[(r * (b % NS)) * (N / (NS * RAD))];
-              if (INV) w.y = -w.y;
-              x = cmul<R>(x, w);
-            }
-            v[vl][u][r] = x;
+        for (int r = 0; r < RAD; ++r) {
+          cplx<R> x = line[(b + r * NB) * estride];
+          if (NS > 1 && r > 0) {
+            cplx<R> w = tw[(r * (b % NS)) * (N / (NS * RAD))];
+            if (INV) w.y = -w.y;
+            x = cmul<R>(x, w);
           }
-          Dft<R, RAD, INV>::run(v[vl][u]);
+          v[vi][r] = x;
         }
+        Dft<R, RAD, INV>::run(v[vi]);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int vl = 0; vl < MAXV; ++vl) {
-      const int l = grp + G * vl;
+    for (int vi = 0; vi < NV; ++vi) {
+      const int i = tid + NT * vi;
+      if (i < tot) {
+        const int l = i / NB, b = i % NB;
+        cplx<R>* line = buf + l * lstride;
+        const int d = (b / NS) * NS * RAD + (b % NS);
 #pragma unroll
-      for (int u = 0; u < BPT; ++u) {
-        const int b = lane + TPL * u;
-        if (grp < G && l < nlines && b < NB) {
-          cplx<R>* line = buf + l * lstride;
-          const int d = (b / NS) * NS * RAD + (b % NS);
-#pragma unroll
-          for (int r = 0; r < RAD; ++r) line[(d + r * NS) * estride] = v[vl][u][r];
-        }
+        for (int r = 0; r < RAD; ++r) line[(d + r * NS) * estride] = v[vi][r];
       }
     }
     __syncthreads();
     if constexpr (STAGE + 1 < Rad<N>::S)
-      Stages<R, N, TPL, NT, MAXV, INV, STAGE + 1, NS * RAD>::run(buf, nlines, lstride, estride, tw);
+      Stages<R, N, NT, MAXL, INV, STAGE + 1, NS * RAD>::run(buf, nlines, lstride, estride, tw);
   }
 };
 
 // Entry point: all lines transformed; caller must __syncthreads() before
 // (data written) -- the first stage's reads happen without a barrier.
-template <typename R, int N, int TPL, int NT, int MAXV, bool INV>
+template <typename R, int N, int NT, int MAXL, bool INV>
 __device__ __forceinline__ void lds_fft(cplx<R>* buf, int nlines, int lstride,
                                         int estride, const cplx<R>* tw) {
-  Stages<R, N, TPL, NT, MAXV, INV, 0, 1>::run(buf, nlines, lstride, estride, tw);
-}
-
-// Threads per line: enough to keep per-thread register arrays small.
-template <int N> constexpr int tpl_for() {
-  return N <= 16 ? 4 : (N <= 40 ? 4 : (N <= 72 ? 6 : 9));
+  Stages<R, N, NT, MAXL, INV, 0, 1>::run(buf, nlines, lstride, estride, tw);
 }
 
 }  // namespace ikr

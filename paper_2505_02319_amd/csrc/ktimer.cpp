@@ -59,8 +59,10 @@ void resolve(State& s) {
 }  // namespace
 
 const char* kernel_name(int id) {
-  static const char* names[K_COUNT] = {"col_inv", "plane_hv", "col_fwd", "gram",
-                                       "update", "cg_step", "plane_rho"};
+  static const char* names[K_COUNT] = {
+      "col_inv", "plane_hv", "col_fwd", "gram", "update", "cg_step", "plane_rho",
+      "col_inv_fp32", "plane_hv_fp32", "col_fwd_fp32", "gram_fp32", "update_fp32",
+      "cg_step_fp32"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 

@@ -15,8 +15,12 @@ enum KernelId : int {
   K_UPDATE = 4,     // projection updates X + W C (with dot partials)
   K_CG_STEP = 5,    // fused CG vector update
   K_PLANE_RHO = 6,  // density accumulation
-  K_COUNT = 7
+  K_FP32 = 7,       // FP32 variants of ids 0..5 follow: K_FP32 + id
+  K_COUNT = 13
 };
+
+// Id of a CG kernel for the precision R (FP32 launches are timed apart).
+template <typename R> constexpr int kid(int id) { return sizeof(R) == 4 ? K_FP32 + id : id; }
 
 const char* kernel_name(int id);
 

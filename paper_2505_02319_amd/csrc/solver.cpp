@@ -252,34 +252,34 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
       Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
       Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(), cnt + 1};
       // p~ = z + beta p ; w~ = (H_loc - e) p~ through the pruned FFT
-      KTimer::begin(K_COL_INV, st);
+      KTimer::begin(kid<R>(K_COL_INV), st);
       launch_col_inv<R>(s.geom, s.fft, sl, w.p.get(), nbm, w.T1.get(), w.w.get(), w.beta.get(),
                         w.p.get(), st);
-      KTimer::end(K_COL_INV, st, 0.0);
-      KTimer::begin(K_PLANE_HV, st);
+      KTimer::end(kid<R>(K_COL_INV), st, 0.0);
+      KTimer::begin(kid<R>(K_PLANE_HV), st);
       launch_plane_hv<R>(s.geom, s.fft, sl, w.T1.get(), w.T2.get(), vloc, 0, st);
-      KTimer::end(K_PLANE_HV, st, 0.0);
-      KTimer::begin(K_COL_FWD, st);
+      KTimer::end(kid<R>(K_PLANE_HV), st, 0.0);
+      KTimer::begin(kid<R>(K_COL_FWD), st);
       launch_col_fwd<R>(s.geom, s.fft, sl, w.T2.get(), w.w.get(), nbm, w.p.get(), w.shift.get(),
                         inv_ng, st);
-      KTimer::end(K_COL_FWD, st, 0.0);
+      KTimer::end(kid<R>(K_COL_FWD), st, 0.0);
       // q, a, h = W_k^H p~ ; update coefficients ; Ap and p = Q p~ ; <p, Ap>
-      KTimer::begin(K_GRAM, st);
+      KTimer::begin(kid<R>(K_GRAM), st);
       gram<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm, w.p.get(), nbm, w.part.get(),
               w.craw.get(), s.mcg, st);
-      KTimer::end(K_GRAM, st, 0.0);
+      KTimer::end(kid<R>(K_GRAM), st, 0.0);
       cg_combine<R>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
                     w.sT.get(), nbn, R(s.dnl), w.gam.get(), st);
-      KTimer::begin(K_UPDATE, st);
+      KTimer::begin(kid<R>(K_UPDATE), st);
       cg_update<R>(ctl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), w.craw.get(),
                    s.mcg, w.w.get(), w.p.get(), w.dpart.get(), st);
-      KTimer::end(K_UPDATE, st, 0.0);
+      KTimer::end(kid<R>(K_UPDATE), st, 0.0);
       cg_alpha<R>(sl, nup, w.dpart.get(), w.rz.get(), w.alpha.get(), st);
       // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, <r, z>
-      KTimer::begin(K_CG_STEP, st);
+      KTimer::begin(kid<R>(K_CG_STEP), st);
       cg_step2<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.alpha.get(), w.pshift.get(),
                   w.x.get(), w.r.get(), w.p.get(), w.w.get(), w.dpart.get(), w.zpart.get(), st);
-      KTimer::end(K_CG_STEP, st, 0.0);
+      KTimer::end(kid<R>(K_CG_STEP), st, 0.0);
       cg_finish<R>(sl, nvb, w.dpart.get(), w.zpart.get(), cs, s.d_active.get(), 0, st);
       compact(it);
       iters = it + 1;
@@ -335,8 +335,8 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
       na = hist[2 * it];
       nt = hist[2 * it + 1];
     }
-    for (int id = 0; id < K_COUNT; ++id)
-      if (b[id] > 0) KTimer::add_bytes(id, b[id]);
+    for (int id = 0; id < K_PLANE_RHO; ++id)
+      if (b[id] > 0) KTimer::add_bytes(kid<R>(id), b[id]);
   }
   return out;
 }
