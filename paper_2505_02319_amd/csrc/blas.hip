@@ -182,6 +182,28 @@ __global__ __launch_bounds__(NT) void gram_reduce_kernel(
   if (lane == 0) coef[(size_t)tslot(tl, t, b) * cstride + m] = mk<R>(sx, sy);
 }
 
+// acc[b] += sum_{m < M} Wt[m * ws] c[b * Mmax + m]; rows are loaded U at a
+// time before use, so that their latencies overlap.
+template <typename R, int BPT, int U>
+__device__ __forceinline__ void add_term(cplx<R> (&acc)[BPT], const cplx<R>* __restrict__ Wt,
+                                         int ws, int M, const cplx<R>* c, int Mmax) {
+  int m = 0;
+  for (; m + U <= M; m += U) {
+    cplx<R> w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) w[u] = Wt[(size_t)(m + u) * ws];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w[u], c[b * Mmax + m + u]));
+  }
+  for (; m < M; ++m) {
+    const cplx<R> w = Wt[(size_t)m * ws];
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c[b * Mmax + m]));
+  }
+}
+
 // Y[slot][g] = a * Y[slot][g] + sum_j alpha_j sum_m W_j[k][m][g] coef_j[slot][m]
 // for up to two (W, coef) sets; optional per-slot mask; optional partial
 // dot <D, Y_new> (real part) per (slot, block) into dpart[slot * nparts + gb].
@@ -229,28 +251,10 @@ __global__ __launch_bounds__(NT) void update_kernel(
   cplx<R> acc[BPT];
 #pragma unroll
   for (int b = 0; b < BPT; ++b) acc[b] = mk<R>(0, 0);
-  // rows are loaded U at a time before use, so that their latencies overlap
   constexpr int U = 4;
-  auto term = [&](const cplx<R>* Wt, int ws, int M, const cplx<R>* c, int Mmax) {
-    int m = 0;
-    for (; m + U <= M; m += U) {
-      cplx<R> w[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) w[u] = Wt[(size_t)(m + u) * ws];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-#pragma unroll
-        for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w[u], c[b * Mmax + m + u]));
-    }
-    for (; m < M; ++m) {
-      const cplx<R> w = Wt[(size_t)m * ws];
-#pragma unroll
-      for (int b = 0; b < BPT; ++b) acc[b] = cadd<R>(acc[b], cmul<R>(w, c[b * Mmax + m]));
-    }
-  };
   if (g < n) {
-    if (W1) term(W1 + (size_t)k * w1k + g, w1s, M1, c1, M1max);
-    if (W2) term(W2 + (size_t)k * w2k + g, w2s, M2, c2, M2max);
+    if (W1) add_term<R, BPT, U>(acc, W1 + (size_t)k * w1k + g, w1s, M1, c1, M1max);
+    if (W2) add_term<R, BPT, U>(acc, W2 + (size_t)k * w2k + g, w2s, M2, c2, M2max);
   }
   // outputs U bands at a time: loads first, then the stores
 #pragma unroll

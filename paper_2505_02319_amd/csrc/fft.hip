@@ -219,14 +219,13 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int col = c00 + u * NT;
-      if (col < ncol) {
-        pv[u] = pq[col];
-        tv[u] = Tin[tb + col];
-      }
+      const bool in = col < ncol;
+      pv[u] = in ? pq[col] : -1;
+      tv[u] = in ? Tin[tb + col] : mk<R>(0, 0);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
-      if (c00 + u * NT < ncol) pl[(pv[u] / Q) * LQ + (pv[u] % Q)] = tv[u];
+      if (pv[u] >= 0) pl[(pv[u] / Q) * LQ + (pv[u] % Q)] = tv[u];
   }
   __syncthreads();
   fft2d<R, P, Q, true>(pl, sP, sQ);
@@ -292,14 +291,13 @@ __global__ __launch_bounds__(NT) void plane_rho_kernel(
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int col = c00 + u * NT;
-          if (col < ncol) {
-            pv[u] = pq[col];
-            tv[u] = T[tb + col];
-          }
+          const bool in = col < ncol;
+          pv[u] = in ? pq[col] : -1;
+          tv[u] = in ? T[tb + col] : mk<double>(0, 0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-          if (c00 + u * NT < ncol) pl[(pv[u] / Q) * LQ + (pv[u] % Q)] = tv[u];
+          if (pv[u] >= 0) pl[(pv[u] / Q) * LQ + (pv[u] % Q)] = tv[u];
       }
       __syncthreads();
       fft2d<double, P, Q, true>(pl, sP, sQ);
