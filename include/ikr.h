@@ -207,6 +207,28 @@ ikr_status ikr_solve_response(ikr_handle h, const double* b_dev,
                               double* drho_dev, const ikr_solver_opts* opts,
                               ikr_stats* stats);
 
+/* ev = E~^T v = v - ||v|| K chi0~(v / ||v||), the transpose of eq.
+ * op_discretised's operator (E^T = 1 - K chi0, K and chi0 being symmetric in
+ * the grid inner product; the transpose is not in the paper).  The per-band
+ * CG tolerances are prefactor(strategy) * common as in ikr_apply_dielectric,
+ * with ||K v|| replaced by ||K||_2 ||v|| (the CG error now passes through K).
+ * Same arguments, layout, ownership and errors as ikr_apply_dielectric. */
+ikr_status ikr_apply_dielectric_adjoint(ikr_handle h, const double* v_dev,
+                                        double* ev_dev, double common,
+                                        const ikr_solver_opts* opts,
+                                        ikr_stats* stats);
+
+/* lambda solving E^T lambda = g by the inexact GMRES(m) of Alg. 1 applied to
+ * the transposed operator: lambda = dL/db for a loss L(drho) with
+ * g = dL/d(drho) and drho = E^-1 b.  g_dev, lambda_dev: device, FP64, N_g
+ * grid values in C order; caller-owned; must not alias.  Errors as
+ * ikr_solve_response (IKR_E_NOCONV when the restart cap is hit, lambda then
+ * holding the last iterate). */
+ikr_status ikr_solve_response_adjoint(ikr_handle h, const double* g_dev,
+                                      double* lambda_dev,
+                                      const ikr_solver_opts* opts,
+                                      ikr_stats* stats);
+
 /* Opt-in kernel timing (process-wide).  Bit i of kernel_mask brackets every
  * launch of hot kernel i of the Sternheimer CG by HIP events on the launching
  * stream (0 disables, -1 times all); each launch carries its algorithmic

@@ -26,7 +26,7 @@ import numpy as np
 
 from .groundstate import GroundState
 from .response import (Chi0Stats, HxcKernel, apply_dielectric,
-                       orbital_row_norm)
+                       apply_dielectric_adjoint, orbital_row_norm)
 from .system import System
 
 STRATEGIES = ("agr", "bal", "grt", "D10", "D100", "D10n", "thm2")
@@ -97,8 +97,9 @@ def inexact_gmres(sys: System, gs: GroundState, kern: HxcKernel,
                   b: np.ndarray, tau: float, strategy: str = "bal",
                   m: int = 20, s0: float = 1.0,
                   x0: Optional[np.ndarray] = None,
-                  max_restarts: int = 50) -> GmresResult:
-    """Algorithm 1 (inexact GMRES(m)) applied to E drho = b."""
+                  max_restarts: int = 50, adjoint: bool = False) -> GmresResult:
+    """Algorithm 1 (inexact GMRES(m)) applied to E drho = b, or with
+    ``adjoint`` to E^T lambda = b (same algorithm, transposed operator)."""
     shape = sys.n
     bvec = b.reshape(-1).astype(float)
     bnorm = float(np.linalg.norm(bvec))
@@ -110,15 +111,15 @@ def inexact_gmres(sys: System, gs: GroundState, kern: HxcKernel,
                 for ik in range(len(sys.bases))] if strategy == "thm2" else None
     stats = Chi0Stats()
     history = []
-    adaptive = strategy in ("agr", "bal", "grt")
+    adaptive = strategy in ("agr", "bal", "grt", "thm2")
     total_iters = 0
 
     def eop(v, common):
         def tol_fn(knorm):
             pref = strategy_prefactors(sys, gs, strategy, knorm, bnorm, orb, orb_full)
             return [p * common for p in pref]
-        ev, _ = apply_dielectric(sys, gs, kern, v.reshape(shape), tol_fn,
-                                 stats=stats)
+        op = apply_dielectric_adjoint if adjoint else apply_dielectric
+        ev, _ = op(sys, gs, kern, v.reshape(shape), tol_fn, stats=stats)
         return ev.reshape(-1)
 
     restarts = 0

@@ -352,6 +352,24 @@ def apply_dielectric(sys: System, gs: GroundState, kern: HxcKernel,
     return v.reshape(sys.n) - nu * chi, nu
 
 
+def apply_dielectric_adjoint(sys: System, gs: GroundState, kern: HxcKernel,
+                             v: np.ndarray, tol_fn, stats: Optional[Chi0Stats] = None):
+    """E^T v = v - ||v|| K chi0(v / ||v||).
+
+    The transpose of eq. op_discretised's operator: K and chi0 are symmetric
+    in the Euclidean grid inner product, so (1 - chi0 K)^T = 1 - K chi0.  Not
+    in the paper; used for dL/db = E^-T dL/d(drho).  ``tol_fn`` receives
+    ||K||_2 ||v|| (the CG error reaches the result through K).
+    Returns (E^T v, ||v||).
+    """
+    v = v.reshape(sys.n)
+    nu = float(np.linalg.norm(v))
+    if nu == 0.0:
+        return v.copy(), 0.0
+    chi = chi0_sternheimer(sys, gs, v / nu, tol_fn(kern.norm2_bound() * nu), stats=stats)
+    return v - nu * kern.apply(chi), nu
+
+
 def orbital_row_norm(sys: System, gs: GroundState, ik: int, real_part: bool = True) -> float:
     """||F_k^-1 Phi_k||_{2,inf} (max over grid points of the row norm), or of
     its real part (Sec. 3.4.1, used by the grt strategy)."""

@@ -86,6 +86,10 @@ SIGNATURES = {
     "ikr_apply_dielectric": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(SolverOpts),
                                        C.POINTER(Stats)]),
     "ikr_solve_response": (C.c_int, [_VP, _VP, _VP, C.POINTER(SolverOpts), C.POINTER(Stats)]),
+    "ikr_apply_dielectric_adjoint": (C.c_int, [_VP, _VP, _VP, C.c_double,
+                                               C.POINTER(SolverOpts), C.POINTER(Stats)]),
+    "ikr_solve_response_adjoint": (C.c_int, [_VP, _VP, _VP, C.POINTER(SolverOpts),
+                                             C.POINTER(Stats)]),
     "ikr_profile_enable": (C.c_int, [C.c_int]),
     "ikr_profile_reset": (C.c_int, []),
     "ikr_profile_kernel_count": (C.c_int, []),
@@ -315,16 +319,32 @@ class ResponseSystem:
                                           C.byref(o), C.byref(st)))
         return out, st.as_dict()
 
-    def solve(self, b, opts: Optional[SolverOpts] = None):
+    def apply_dielectric_adjoint(self, v, common: float, opts: Optional[SolverOpts] = None):
+        out = self._torch.empty_like(self._grid(v))
+        st = Stats()
+        o = opts or default_opts()
+        _check(lib().ikr_apply_dielectric_adjoint(self.h, _ptr(v), _ptr(out), float(common),
+                                                  C.byref(o), C.byref(st)))
+        return out, st.as_dict()
+
+    def _solve(self, fn, b, opts):
         out = self._torch.empty_like(self._grid(b))
         st = Stats()
         o = opts or default_opts()
-        code = lib().ikr_solve_response(self.h, _ptr(b), _ptr(out), C.byref(o), C.byref(st))
+        code = fn(self.h, _ptr(b), _ptr(out), C.byref(o), C.byref(st))
         if code != 0:
             err = IkrError(code, lib().ikr_last_error().decode())
             err.stats = st.as_dict()
             raise err
         return out, st.as_dict()
+
+    def solve(self, b, opts: Optional[SolverOpts] = None):
+        """drho = E^-1 b (Alg. 1)."""
+        return self._solve(lib().ikr_solve_response, b, opts)
+
+    def solve_adjoint(self, g, opts: Optional[SolverOpts] = None):
+        """lambda = E^-T g (the same inexact GMRES on the transposed operator)."""
+        return self._solve(lib().ikr_solve_response_adjoint, g, opts)
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
@@ -336,3 +356,39 @@ class ResponseSystem:
             self.close()
         except Exception:
             pass
+
+
+def _autograd_function():
+    import torch
+
+    class DysonSolve(torch.autograd.Function):
+        """drho = E^-1 b with its gradient dL/db = E^-T dL/d(drho): the backward
+        pass is the inexact GMRES solve of the transposed dielectric operator
+        (same Sternheimer kernels, nothing stored from the forward solve)."""
+
+        @staticmethod
+        def forward(ctx, b, rs, opts, adj_opts):
+            x, st = rs.solve(b.contiguous(), opts)
+            ctx.rs, ctx.adj_opts = rs, adj_opts if adj_opts is not None else opts
+            ctx.stats = st
+            return x
+
+        @staticmethod
+        def backward(ctx, g):
+            lam, st = ctx.rs.solve_adjoint(g.contiguous(), ctx.adj_opts)
+            ctx.adjoint_stats = st
+            return lam, None, None, None
+
+    return DysonSolve
+
+
+def dyson_solve(b, rs: "ResponseSystem", opts: Optional[SolverOpts] = None,
+                adj_opts: Optional[SolverOpts] = None):
+    """Differentiable solve of E drho = b (b a CUDA float64 grid tensor)."""
+    global _DYSON
+    if _DYSON is None:
+        _DYSON = _autograd_function()
+    return _DYSON.apply(b, rs, opts or default_opts(), adj_opts)
+
+
+_DYSON = None

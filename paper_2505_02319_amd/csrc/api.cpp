@@ -252,6 +252,41 @@ ikr_status ikr_solve_response(ikr_handle h, const double* b_dev, double* drho_de
   });
 }
 
+ikr_status ikr_apply_dielectric_adjoint(ikr_handle h, const double* v_dev, double* ev_dev,
+                                        double common, const ikr_solver_opts* opts,
+                                        ikr_stats* stats) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    check_opts(opts);
+    IKR_CHECK(v_dev && ev_dev && v_dev != ev_dev, IKR_E_ARG, "bad vector pointers");
+    IKR_CHECK(common > 0, IKR_E_ARG, "common tolerance factor must be positive");
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    ikr_stats local{};
+    ikr::apply_dielectric_adjoint_ext(*s, v_dev, ev_dev, common, *opts, opts->b_norm, &local);
+    local.true_res = -1;
+    if (stats) *stats = local;
+  });
+}
+
+ikr_status ikr_solve_response_adjoint(ikr_handle h, const double* g_dev, double* lambda_dev,
+                                      const ikr_solver_opts* opts, ikr_stats* stats) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    check_opts(opts);
+    IKR_CHECK(g_dev && lambda_dev && g_dev != lambda_dev, IKR_E_ARG, "bad vector pointers");
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    ikr_stats local{};
+    local.true_res = -1;
+    try {
+      ikr::solve_response(*s, g_dev, lambda_dev, *opts, &local, true);
+    } catch (...) {
+      if (stats) *stats = local;
+      throw;
+    }
+    if (stats) *stats = local;
+  });
+}
+
 ikr_status ikr_profile_enable(int kernel_mask) {
   return guarded([&] { ikr::KTimer::enable((unsigned)kernel_mask); });
 }

@@ -544,6 +544,12 @@ void finish_setup(System& s) {
       for (int i = 0; i < s.ng; ++i)
         fx[i] = -(1.0 / 3.0) * std::cbrt(3.0 / PI) * std::pow(std::max(rho[i], 1e-10), -2.0 / 3.0);
     s.d_fx.upload(fx, st);
+    // ||K||_2 bound: largest Hartree eigenvalue (smallest nonzero |G| = min b_i on
+    // an orthorhombic grid) plus the largest |f_x|
+    double fxmax = 0;
+    for (double v : fx) fxmax = std::max(fxmax, std::fabs(v));
+    const double bmin = std::min({s.b[0], s.b[1], s.b[2]});
+    s.knorm_bound = 4.0 * PI / (bmin * bmin) + fxmax;
   }
   // -- ||Re F_k^-1 Phi_k||_{2,inf} per k (grt strategy)
   {

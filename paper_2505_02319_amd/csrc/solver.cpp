@@ -552,14 +552,63 @@ void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext, double
   IKR_HIP(hipStreamSynchronize(st));
 }
 
+// Euclidean norm of a grid vector (fixed-order reduction).
+static double grid_norm(System& s, const double* v) {
+  const int nbl = multidot_nblocks(s.ng);
+  multidot(s.ng, 1, v, s.ng, v, s.d_multi.get(), s.stream);
+  const std::vector<double> h = download(s.d_multi.get(), nbl, s.stream);
+  double a = 0;
+  for (double x : h) a += x;
+  return std::sqrt(a);
+}
+
+// ev = E~^T v = v - ||v|| K chi0~(v / ||v||).  K and chi0 are symmetric in
+// the grid inner product, so the transpose of E = 1 - chi0 K is 1 - K chi0.
+// The CG error enters through K, bounded by ||K||_2 ||v|| ||(chi0 - chi0~) v^||,
+// so the strategies that use ||K v_i|| take ||K||_2 ||v_i|| instead.
+void apply_dielectric_adjoint_ext(System& s, const double* v_ext, double* ev_ext,
+                                  double common, const ikr_solver_opts& o, double bnorm,
+                                  ikr_stats* stt) {
+  const hipStream_t st = s.stream;
+  const double nu = grid_norm(s, v_ext);
+  if (stt) stt->knorm_last = nu;
+  if (nu == 0.0) {
+    IKR_HIP(hipMemcpyAsync(ev_ext, v_ext, s.ng * sizeof(double), hipMemcpyDeviceToDevice, st));
+    IKR_HIP(hipStreamSynchronize(st));
+    return;
+  }
+  to_internal(s.L, v_ext, s.d_tmpg.get(), st);
+  scale_copy(s.ng, s.d_tmpg.get(), 1.0 / nu, s.d_u.get(), st);
+  std::vector<double> tol = prefactors(s, o.strategy, s.knorm_bound * nu, bnorm,
+                                       o.schur && s.nbands > s.nocc_max);
+  for (double& t : tol) t *= common;
+  Chi0Result r = apply_chi0_internal(s, s.d_u.get(), s.d_drho.get(), tol, o.cg_min_iter,
+                                     o.cg_max_iter, o.precision, o.fp32_theta, o.schur);
+  if (stt) {
+    stt->n_ham += r.n_ham;
+    stt->n_ham_fp64 += r.n_ham64;
+    stt->n_ham_fp32 += r.n_ham32;
+    stt->cg_unconverged += r.noconv;
+  }
+  apply_kernel(s, s.d_drho.get(), s.d_u.get());
+  to_external(s.L, s.d_u.get(), ev_ext, -nu, v_ext, 1.0, st);
+  IKR_HIP(hipStreamSynchronize(st));
+}
+
 // ---------------------------------------------------------------- Alg. 1
+// Inexact GMRES(m) on E (adjoint = false) or on E^T (adjoint = true).
 void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_solver_opts& o,
-                    ikr_stats* stt) {
+                    ikr_stats* stt, bool adjoint) {
+  auto apply_op = [&](const double* v, double* ev, double common, double bn, ikr_stats* sp) {
+    if (adjoint) apply_dielectric_adjoint_ext(s, v, ev, common, o, bn, sp);
+    else apply_dielectric_ext(s, v, ev, common, o, bn, sp);
+  };
   const auto t0 = std::chrono::steady_clock::now();
   const hipStream_t st = s.stream;
   const int n = s.ng, m = o.restart_m;
   IKR_CHECK(m >= 1 && m <= 60, 1, "restart size out of range");
-  const bool adaptive = o.strategy == IKR_AGR || o.strategy == IKR_BAL || o.strategy == IKR_GRT;
+  const bool adaptive = o.strategy == IKR_AGR || o.strategy == IKR_BAL ||
+                        o.strategy == IKR_GRT || o.strategy == IKR_THM2;
   DBuf<double> V, coef, part, tmp;
   V.alloc((size_t)(m + 1) * n);
   coef.alloc(64);
@@ -597,7 +646,7 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
     if (x0_zero) {
       IKR_HIP(hipMemcpyAsync(v0, b_ext, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
-      apply_dielectric_ext(s, x_ext, v0, adaptive ? tau / 3.0 : tau, o, bnorm, stt);
+      apply_op(x_ext, v0, adaptive ? tau / 3.0 : tau, bnorm, stt);
       axpy(1, b_ext, {1.0}, -1.0, v0);
     }
     const double beta = std::sqrt(dots(1, v0, v0)[0]);
@@ -611,7 +660,7 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
     for (int i = 1; i <= m; ++i) {
       const double common = adaptive ? (s_est / (3.0 * m)) * tau / resid : tau;
       double* vi = V.get() + (size_t)i * n;
-      apply_dielectric_ext(s, V.get() + (size_t)(i - 1) * n, vi, common, o, bnorm, stt);
+      apply_op(V.get() + (size_t)(i - 1) * n, vi, common, bnorm, stt);
       ++iters;
       // classical Gram-Schmidt, twice
       std::vector<double> h = dots(i, V.get(), vi);
@@ -669,7 +718,8 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
     ikr_solver_opts ot = o;
     ot.strategy = IKR_FIXED;
     ikr_stats dummy{};
-    apply_dielectric_ext(s, x_ext, tmp.get(), o.true_res_cg_tol, ot, bnorm, &dummy);
+    if (adjoint) apply_dielectric_adjoint_ext(s, x_ext, tmp.get(), o.true_res_cg_tol, ot, bnorm, &dummy);
+    else apply_dielectric_ext(s, x_ext, tmp.get(), o.true_res_cg_tol, ot, bnorm, &dummy);
     axpy(1, b_ext, {1.0}, -1.0, tmp.get());
     stt->true_res = std::sqrt(dots(1, tmp.get(), tmp.get())[0]);
   }

@@ -123,6 +123,7 @@ struct System {
   DBuf<double> d_rho, d_fx, d_khat;   // internal layout
   std::vector<double> orbnorm_k;   // ||Re F_k^-1 Phi_k||_{2,inf}
   std::vector<double> orbnorm_full_k;  // ||F_k^-1 Phi_k||_{2,inf}
+  double knorm_bound = 0;          // ||K||_2 <= max 4 pi / |G|^2 + max |f_x|
 
   // work
   CgWork<double> w64;
@@ -165,7 +166,10 @@ void ensure_fp32(System& s);   // FP32 work space and operator copies (lazy)
 void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext,
                           double common, const ikr_solver_opts& o, double bnorm,
                           ikr_stats* st);
+void apply_dielectric_adjoint_ext(System& s, const double* v_ext, double* ev_ext,
+                                  double common, const ikr_solver_opts& o, double bnorm,
+                                  ikr_stats* st);
 void solve_response(System& s, const double* b_ext, double* x_ext,
-                    const ikr_solver_opts& o, ikr_stats* st);
+                    const ikr_solver_opts& o, ikr_stats* st, bool adjoint = false);
 
 }  // namespace ikr

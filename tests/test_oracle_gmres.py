@@ -110,3 +110,43 @@ def test_static_tolerance_loses_accuracy(tiny_dense):
     true_r = np.linalg.norm(b.ravel() - emat @ res_small.x.ravel())
     assert res_small.est_res <= tau / 3
     assert true_r > res_small.est_res
+
+
+def test_dielectric_adjoint_is_the_transpose(tiny_dense):
+    """E^T v from the Sternheimer route equals the dense transpose, and
+    <u, E v> = <E^T u, v> for the two Sternheimer-applied operators."""
+    from oracle.response import apply_dielectric_adjoint
+    sys, gs, kern, kmat, emat = tiny_dense
+    u = random_field(sys.spec, 5)
+    v = random_field(sys.spec, 6)
+    etu, nu = apply_dielectric_adjoint(sys, gs, kern, u, lambda knorm: 1e-13)
+    assert abs(nu - np.linalg.norm(u)) < 1e-14
+    assert np.linalg.norm(etu.ravel() - emat.T @ u.ravel()) < 1e-10 * np.linalg.norm(u)
+    ev, _ = apply_dielectric(sys, gs, kern, v, lambda knorm: 1e-13)
+    lhs = float(np.dot(u.ravel(), ev.ravel()))
+    rhs = float(np.dot(etu.ravel(), v.ravel()))
+    assert abs(lhs - rhs) < 1e-10 * np.linalg.norm(u) * np.linalg.norm(v)
+    # E^T differs from E: the pin is not vacuous
+    assert np.linalg.norm(emat - emat.T) > 1e-3 * np.linalg.norm(emat)
+
+
+def test_kernel_norm_bound(tiny_dense):
+    sys, gs, kern, kmat, emat = tiny_dense
+    assert np.linalg.norm(kmat, 2) <= kern.norm2_bound() * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("strategy", ["bal", "grt", "thm2"])
+def test_adjoint_gmres_matches_dense_transpose_solve(tiny_dense, strategy):
+    """lambda = E^-T g by Alg. 1 on the transposed operator; with ||K v||
+    replaced by ||K||_2 ||v|| the Theorem 2 strategies keep their guarantee."""
+    sys, gs, kern, kmat, emat = tiny_dense
+    g = random_field(sys.spec, 4)
+    tau = 1e-8 * np.linalg.norm(g)
+    res = inexact_gmres(sys, gs, kern, g, tau, strategy=strategy, m=20, adjoint=True)
+    lam = res.x.ravel()
+    true_r = np.linalg.norm(g.ravel() - emat.T @ lam)
+    if strategy in ("grt", "thm2"):
+        assert true_r <= tau
+    assert true_r <= 3 * tau
+    ref = np.linalg.solve(emat.T, g.ravel())
+    assert np.linalg.norm(lam - ref) <= np.linalg.cond(emat) * 10 * true_r + 1e-14
