@@ -229,6 +229,25 @@ ikr_status ikr_solve_response_adjoint(ikr_handle h, const double* g_dev,
                                       const ikr_solver_opts* opts,
                                       ikr_stats* stats);
 
+/* dL/dA_a for every atom a, the A_a being the local-potential amplitudes
+ * (V_loc = sum_a A_a a_a(r)), given drho = E^-1 b and lambda = E^-T dL/d(drho)
+ * (ikr_solve_response / ikr_solve_response_adjoint).  With u = K drho:
+ *   dL/dA_a = lambda^T (d chi0/dA_a) u + lambda^T chi0 (dK/dA_a) drho,
+ * the first term by the third-order (2n+1) form of the band energy with the
+ * first-order orbitals psi^u, psi^lambda and one adjoint Sternheimer solve per
+ * band, the second through two chi0 applications (dK/dA_a = f_x' chi0 a_a,
+ * the potential being fixed, not self-consistent).  Not in the paper; built
+ * on its Sternheimer route (eq. sternheimer_equation, eq. kchi0).
+ * drho_dev, lambda_dev: device FP64 grid values (C order), caller-owned.
+ * dlda_host: host array of natoms doubles, written on success.  cg_tol: CG
+ * tolerance relative to each right-hand side, in (0, 1) (1e-12 for
+ * gradients good to ~1e-8).  Errors: IKR_E_ARG for null pointers, a bad
+ * tolerance or smeared occupations (only fixed occupations are supported),
+ * IKR_E_STATE without a ground state, IKR_E_NAN for a non-finite result. */
+ikr_status ikr_grad_amplitudes(ikr_handle h, const double* drho_dev,
+                               const double* lambda_dev, double cg_tol,
+                               double* dlda_host, ikr_stats* stats);
+
 /* Opt-in kernel timing (process-wide).  Bit i of kernel_mask brackets every
  * launch of hot kernel i of the Sternheimer CG by HIP events on the launching
  * stream (0 disables, -1 times all); each launch carries its algorithmic

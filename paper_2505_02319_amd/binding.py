@@ -90,6 +90,8 @@ SIGNATURES = {
                                                C.POINTER(SolverOpts), C.POINTER(Stats)]),
     "ikr_solve_response_adjoint": (C.c_int, [_VP, _VP, _VP, C.POINTER(SolverOpts),
                                              C.POINTER(Stats)]),
+    "ikr_grad_amplitudes": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(C.c_double),
+                                      C.POINTER(Stats)]),
     "ikr_profile_enable": (C.c_int, [C.c_int]),
     "ikr_profile_reset": (C.c_int, []),
     "ikr_profile_kernel_count": (C.c_int, []),
@@ -346,6 +348,14 @@ class ResponseSystem:
         """lambda = E^-T g (the same inexact GMRES on the transposed operator)."""
         return self._solve(lib().ikr_solve_response_adjoint, g, opts)
 
+    def grad_amplitudes(self, drho, lam, cg_tol: float = 1e-12):
+        """dL/dA (numpy, one per atom) from drho = E^-1 b and lam = E^-T dL/d(drho)."""
+        out = np.zeros(self.spec.natoms)
+        st = Stats()
+        _check(lib().ikr_grad_amplitudes(self.h, _ptr(self._grid(drho)), _ptr(self._grid(lam)),
+                                         float(cg_tol), _dptr(out), C.byref(st)))
+        return out, st.as_dict()
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             lib().ikr_destroy(self.h)
@@ -367,28 +377,45 @@ def _autograd_function():
         (same Sternheimer kernels, nothing stored from the forward solve)."""
 
         @staticmethod
-        def forward(ctx, b, rs, opts, adj_opts):
+        def forward(ctx, b, amplitudes, rs, opts, adj_opts, grad_tol):
             x, st = rs.solve(b.contiguous(), opts)
             ctx.rs, ctx.adj_opts = rs, adj_opts if adj_opts is not None else opts
+            ctx.grad_tol = grad_tol
             ctx.stats = st
+            ctx.save_for_backward(x)
             return x
 
         @staticmethod
         def backward(ctx, g):
+            (x,) = ctx.saved_tensors
             lam, st = ctx.rs.solve_adjoint(g.contiguous(), ctx.adj_opts)
             ctx.adjoint_stats = st
-            return lam, None, None, None
+            gamp = None
+            if ctx.needs_input_grad[1]:
+                ga, _ = ctx.rs.grad_amplitudes(x, lam, ctx.grad_tol)
+                gamp = torch.from_numpy(ga)
+            return lam, gamp, None, None, None, None
 
     return DysonSolve
 
 
 def dyson_solve(b, rs: "ResponseSystem", opts: Optional[SolverOpts] = None,
-                adj_opts: Optional[SolverOpts] = None):
-    """Differentiable solve of E drho = b (b a CUDA float64 grid tensor)."""
+                adj_opts: Optional[SolverOpts] = None, amplitudes=None,
+                grad_tol: float = 1e-12):
+    """Differentiable solve of E drho = b (b a CUDA float64 grid tensor).
+
+    ``amplitudes``: optional CPU float64 tensor equal to the system's
+    local-potential amplitudes; when it requires grad, backward also returns
+    dL/dA (the system itself is not changed: the derivative is taken at the
+    amplitudes it was set up with)."""
     global _DYSON
     if _DYSON is None:
         _DYSON = _autograd_function()
-    return _DYSON.apply(b, rs, opts or default_opts(), adj_opts)
+    if amplitudes is not None:
+        got = np.asarray(amplitudes.detach().cpu(), float)
+        if got.shape != (rs.spec.natoms,) or not np.allclose(got, rs.spec.amp, rtol=0, atol=0):
+            raise ValueError("amplitudes must equal the system's local-potential amplitudes")
+    return _DYSON.apply(b, amplitudes, rs, opts or default_opts(), adj_opts, grad_tol)
 
 
 _DYSON = None

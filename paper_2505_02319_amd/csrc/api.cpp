@@ -6,6 +6,9 @@
 #include <string>
 
 #include "ktimer.h"
+#include <algorithm>
+#include <cmath>
+
 #include "system.h"
 
 using ikr::Error;
@@ -283,6 +286,21 @@ ikr_status ikr_solve_response_adjoint(ikr_handle h, const double* g_dev, double*
       if (stats) *stats = local;
       throw;
     }
+    if (stats) *stats = local;
+  });
+}
+
+ikr_status ikr_grad_amplitudes(ikr_handle h, const double* drho_dev, const double* lambda_dev,
+                               double cg_tol, double* dlda_host, ikr_stats* stats) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(drho_dev && lambda_dev && dlda_host, IKR_E_ARG, "null pointer");
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    ikr_stats local{};
+    local.true_res = -1;
+    const std::vector<double> g = ikr::grad_amplitudes(*s, drho_dev, lambda_dev, cg_tol, &local);
+    for (double v : g) IKR_CHECK(std::isfinite(v), IKR_E_NAN, "non-finite gradient");
+    std::copy(g.begin(), g.end(), dlda_host);
     if (stats) *stats = local;
   });
 }

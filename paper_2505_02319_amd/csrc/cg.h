@@ -49,9 +49,10 @@ void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, con
               const R* pshift, cplx<R>* x, cplx<R>* r, const cplx<R>* p, cplx<R>* w,
               R* rpart, R* zpart, hipStream_t st);
 
-// alpha = rz / <p, Ap> per listed slot (0 when <p, Ap> = 0).
+// alpha = rz / <p, Ap> per listed slot; on a breakdown (<p, Ap> <= 0 or a
+// non-finite alpha) alpha = 0 and the slot leaves the active set.
 template <typename R>
-void cg_alpha(const Slots& sl, int nparts, const R* dpart, const R* rz, R* alpha,
+void cg_alpha(const Slots& sl, int nparts, const R* dpart, const R* rz, R* alpha, int* active,
               hipStream_t st);
 
 // start: rz = <r, z>, beta = 0.  Otherwise: iteration count, |r|^2,

@@ -257,19 +257,30 @@ __global__ __launch_bounds__(NT) void cg_step2_kernel(
   }
 }
 
-// One wavefront per listed slot.
+// One wavefront per listed slot.  A breakdown (<p, Ap> not positive or not
+// finite: the operator is positive definite on range Q, so this only comes
+// from round-off once the residual is at the precision floor) leaves x and r
+// as they are (alpha = 0) and takes the slot out of the active set.
 template <typename R>
 __global__ __launch_bounds__(NT) void cg_alpha_kernel(Slots s, int nparts,
                                                       const R* __restrict__ dpart,
                                                       const R* __restrict__ rz,
-                                                      R* __restrict__ alpha) {
+                                                      R* __restrict__ alpha,
+                                                      int* __restrict__ active) {
   const int row = blockIdx.x * NW + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= s.n || !row_live(s, row)) return;
   const int slot = slot_of(s, row);
   R v = 0;
   for (int i = lane; i < nparts; i += 64) v += dpart[(size_t)slot * nparts + i];
   v = wsum(v);
-  if (lane == 0) alpha[slot] = v != R(0) ? rz[slot] / v : R(0);
+  if (lane != 0) return;
+  const R a = rz[slot] / v;
+  if (v > R(0) && a == a && a - a == R(0)) {
+    alpha[slot] = a;
+  } else {
+    alpha[slot] = R(0);
+    active[slot] = 0;
+  }
 }
 
 template <typename R>
@@ -297,6 +308,10 @@ __global__ __launch_bounds__(NT) void cg_finish_kernel(Slots s, int nparts,
   const int it = ++cs.iters[slot];
   cs.rnorm2[slot] = rr;
   const bool conv = it >= cs.min_iter && (double)rr <= cs.tol2[slot];
+  if (!active[slot]) {            // stopped by a breakdown in this iteration
+    if (!conv) atomicAdd(cs.noconv, 1);
+    return;
+  }
   if (conv || it >= cs.max_iter) {
     active[slot] = 0;
     if (!conv) atomicAdd(cs.noconv, 1);
@@ -412,11 +427,11 @@ void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, con
 }
 
 template <typename R>
-void cg_alpha(const Slots& sl, int nparts, const R* dpart, const R* rz, R* alpha,
+void cg_alpha(const Slots& sl, int nparts, const R* dpart, const R* rz, R* alpha, int* active,
               hipStream_t st) {
   if (sl.n <= 0) return;
   hipLaunchKernelGGL((cg_alpha_kernel<R>), dim3((sl.n + NW - 1) / NW), dim3(NT), 0, st, sl,
-                     nparts, dpart, rz, alpha);
+                     nparts, dpart, rz, alpha, active);
   IKR_HIP(hipGetLastError());
 }
 
@@ -448,7 +463,7 @@ void cg_compact(int nk, const int* slot0_k, const int* nslot_k, const int* activ
                              cplx<R>*, R*, hipStream_t);                                       \
   template void cg_step2<R>(const Slots&, const int*, const double*, int, const R*, const R*,  \
                             cplx<R>*, cplx<R>*, const cplx<R>*, cplx<R>*, R*, R*, hipStream_t); \
-  template void cg_alpha<R>(const Slots&, int, const R*, const R*, R*, hipStream_t);           \
+  template void cg_alpha<R>(const Slots&, int, const R*, const R*, R*, int*, hipStream_t);     \
   template void cg_finish<R>(const Slots&, int, const R*, const R*, const CgScalars<R>&, int*,  \
                              int, hipStream_t);
 IKR_INST(double)

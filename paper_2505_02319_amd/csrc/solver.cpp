@@ -16,6 +16,7 @@ namespace ikr {
 namespace {
 
 constexpr double DEGEN_TOL = 1e-8;
+constexpr double TOL_FLOOR = 1e-14;   // CG tolerances never below this times ||b_j||
 
 double focc_dx(double x) {
   const double e = std::exp(-std::fabs(x));
@@ -274,7 +275,7 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
       cg_update<R>(ctl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), w.craw.get(),
                    s.mcg, w.w.get(), w.p.get(), w.dpart.get(), st);
       KTimer::end(kid<R>(K_UPDATE), st, 0.0);
-      cg_alpha<R>(sl, nup, w.dpart.get(), w.rz.get(), w.alpha.get(), st);
+      cg_alpha<R>(sl, nup, w.dpart.get(), w.rz.get(), w.alpha.get(), s.d_active.get(), st);
       // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, <r, z>
       KTimer::begin(kid<R>(K_CG_STEP), st);
       cg_step2<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.alpha.get(), w.pshift.get(),
@@ -345,8 +346,9 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
 
 // ---------------------------------------------------------------- chi0
 Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
-                               const std::vector<double>& tol_slot, int min_iter,
-                               int max_iter, int precision, double theta, int schur) {
+                               const std::vector<double>& tol_in, int min_iter,
+                               int max_iter, int precision, double theta, int schur,
+                               const Chi0Extra* ex) {
   IKR_CHECK(s.have_gs, 2, "ground state not set up");
   const hipStream_t st = s.stream;
   CgWork<double>& w = s.w64;
@@ -363,14 +365,20 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   const int* dMcg = use_schur ? s.d_mcg_all.get() : s.d_mcg_occ.get();
   const int Mq_max = use_schur ? s.nbands : s.nocc_max;
 
-  // right-hand sides t_j = F(u F^-1 phi_j) into r
-  launch_plane_hv<double>(s.geom, s.fft, all, s.d_Tphi.get(), w.T2.get(), u_int, 0, st);
-  launch_col_fwd<double>(s.geom, s.fft, all, w.T2.get(), w.r.get(), nbm, nullptr, nullptr,
-                         inv_ng, st);
+  // right-hand sides t_j = F(u F^-1 phi_j) into r (or given ones)
+  if (ex && ex->rhs_pw) {
+    IKR_HIP(hipMemcpyAsync(w.r.get(), ex->rhs_pw, (size_t)J * nbm * sizeof(double2),
+                           hipMemcpyDeviceToDevice, st));
+  } else {
+    launch_plane_hv<double>(s.geom, s.fft, all, s.d_Tphi.get(), w.T2.get(), u_int, 0, st);
+    launch_col_fwd<double>(s.geom, s.fft, all, w.T2.get(), w.r.get(), nbm, nullptr, nullptr,
+                           inv_ng, st);
+  }
   // M[j][m] = <phi_m, t_j>
   gram<double>(s.tiles, s.d_nb.get(), nbm, dMq, Mq_max, s.d_phi.get(), phik,
                nbm, w.r.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
   const std::vector<double2> M = download(w.coefA.get(), (size_t)J * MAXM, st);
+  if (ex && ex->m_out) *ex->m_out = M;
 
   // occupation response and occupied-space part (minimal gauge)
   std::vector<double> de(J), df(J, 0.0);
@@ -418,12 +426,20 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   // Per-band precision: bands whose tolerance is loose relative to their
   // right-hand side run the CG in FP32 (FP32 FFTs and projections); the
   // others, and everything after the CG, stay in FP64.
+  // Tolerances are floored at TOL_FLOOR ||b_j||: below that the FP64
+  // recursion has nothing left to resolve (round-off level).
+  std::vector<double> tol_slot(tol_in);
   std::vector<int> m64(J, 1), m32(J, 0);
   int n32 = 0;
-  if (precision == 1) {
+  {
     const std::vector<double> bn = slot_norms(s, w.r.get());
-    for (int j = 0; j < J; ++j)
-      if (tol_slot[j] >= theta * bn[j]) { m32[j] = 1; m64[j] = 0; ++n32; }
+    for (int j = 0; j < J; ++j) {
+      if (ex && ex->tol_relative) tol_slot[j] *= bn[j];
+      tol_slot[j] = std::max(tol_slot[j], TOL_FLOOR * bn[j]);
+    }
+    if (precision == 1)
+      for (int j = 0; j < J; ++j)
+        if (tol_slot[j] >= theta * bn[j]) { m32[j] = 1; m64[j] = 0; ++n32; }
   }
   const CgOut o64 = run_cg<double>(s, s.w64, w.r.get(), m64, tol_slot, min_iter, max_iter,
                                    dMq, Mq_max, dMcg);
@@ -459,6 +475,13 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   UpdTerm<double> phiB{s.d_phi.get(), phik, nbm, dMq, w.coefB.get(), MAXM, 1.0, Mq_max};
   update<double>(s.tiles, s.d_nb.get(), nbm, nullptr, w.x.get(), nbm, 1.0, phiA, phiB, nullptr,
                  nullptr, st);
+  if (ex && ex->dphi_out)
+    IKR_HIP(hipMemcpyAsync(ex->dphi_out, w.x.get(), (size_t)J * nbm * sizeof(double2),
+                           hipMemcpyDeviceToDevice, st));
+  if (!drho_int) {
+    IKR_HIP(hipStreamSynchronize(st));
+    return res;
+  }
 
   // drho = sum_k w_k sum_n 2 f Re(conj psi dpsi) + df |psi|^2
   launch_col_inv<double>(s.geom, s.fft, all, w.x.get(), nbm, w.T1.get(), nullptr, nullptr,
@@ -671,6 +694,7 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
       for (int j = 0; j < i; ++j) { neg[j] = -h2[j]; h[j] += h2[j]; }
       axpy(i, V.get(), neg, 1.0, vi);
       const double hn = std::sqrt(dots(1, vi, vi)[0]);
+      IKR_CHECK(std::isfinite(hn), 5, "non-finite Krylov vector");
       for (int j = 0; j < i; ++j) H[(size_t)j * m + (i - 1)] = h[j];
       H[(size_t)i * m + (i - 1)] = hn;
       if (hn > 0) scale_copy(n, vi, 1.0 / hn, vi, st);

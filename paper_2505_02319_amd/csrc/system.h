@@ -137,6 +137,7 @@ struct System {
   DBuf<int> d_mcg_occ, d_mcg_all;  // rows used per k: natoms + 2 nocc_k / + 2 nbands
   DBuf<int> d_cnt, d_hist;         // live counts of the compaction, per-iteration history
   HBuf<int> h_cnt;                 // [2][2] lagged copies of d_cnt
+  std::vector<double> dvloc;       // [natoms][ng] dV_loc/dA_a, internal layout (lazy)
   DBuf<double> d_tol2;
   std::vector<double> knorm_hist;
 
@@ -158,10 +159,21 @@ struct Chi0Result {
   long long n_ham = 0, n_ham32 = 0, n_ham64 = 0;
   int noconv = 0;
 };
+// Optional inputs/outputs of the chi0 path beyond the density.
+struct Chi0Extra {
+  const double2* rhs_pw = nullptr;     // t_j [J][nb_max] instead of F(u psi_j)
+  double2* dphi_out = nullptr;         // delta phi_j [J][nb_max] (device copy)
+  std::vector<double2>* m_out = nullptr;   // M[j][m] = <phi_m, t_j> (host, stride MAXM)
+  bool tol_relative = false;           // tolerances scale with ||b_j||
+};
 Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
                                const std::vector<double>& tol_slot, int min_iter,
                                int max_iter, int precision = 0, double theta = 1e-5,
-                               int schur = 0);
+                               int schur = 0, const Chi0Extra* ex = nullptr);
+// dL/dA for every atom from drho = E^-1 b and lambda = E^-T dL/d(drho)
+// (fixed occupations only), CG tolerances relative to each right-hand side.
+std::vector<double> grad_amplitudes(System& s, const double* drho_ext, const double* lam_ext,
+                                    double cg_tol, ikr_stats* st);
 void ensure_fp32(System& s);   // FP32 work space and operator copies (lazy)
 void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext,
                           double common, const ikr_solver_opts& o, double bnorm,

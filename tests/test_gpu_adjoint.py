@@ -104,3 +104,81 @@ def test_solve_adjoint_cfg1_against_oracle_gmres():
     lam, st = rs.solve_adjoint(to_dev(g), default_opts(strategy="grt", tol=1e-10))
     assert rel(to_host(lam), ref.x) < 1e-8
     assert st["gmres_iters"] > 0
+
+
+def _gpu_system_for(spec):
+    """Library system for an arbitrary spec with the oracle's ground state."""
+    from gpu_common import reorder_map
+    from oracle.groundstate import ground_state
+    from oracle.system import System
+    from paper_2505_02319_amd import ResponseSystem
+    osys = System(spec)
+    ogs = ground_state(osys)
+    rs = ResponseSystem(spec, ground_state=None)
+    inf = rs.info()
+    perms = [reorder_map(rs.basis(k), osys.bases[k].miller) for k in range(inf.nk)]
+    eps = np.array([ogs.eps[k] for k in range(inf.nk)])
+    cf = np.zeros((inf.nk, inf.nbands, inf.nb_max), np.complex128)
+    for k in range(inf.nk):
+        cf[k, :, :len(perms[k])] = ogs.phi[k][:, perms[k]]
+    rs.import_ground_state(eps, cf)
+    return rs, osys, ogs
+
+
+@pytest.mark.parametrize("name", ["tiny", "tiny_k"])
+def test_grad_amplitudes_matches_oracle(name):
+    """The library's dL/dA (third-order form + f_x' term) against the oracle's,
+    both from the same drho and lambda (dense solves)."""
+    from oracle.gradient import amplitude_gradient
+    from oracle.response import HxcKernel
+    rs, osys, emat = _dense(name)
+    from gpu_common import oracle_state
+    _, ogs = oracle_state(name)
+    b = random_field(osys.spec, 2)
+    t = random_field(osys.spec, 3)
+    x = np.linalg.solve(emat, b.ravel())
+    lam = np.linalg.solve(emat.T, 2 * (x - t.ravel()))
+    got, st = rs.grad_amplitudes(to_dev(x.reshape(osys.n)), to_dev(lam.reshape(osys.n)), 1e-13)
+    kern = HxcKernel(osys, ogs.rho, xc=osys.spec.xc)
+    ref = amplitude_gradient(osys, ogs, kern, x, lam, tol=1e-13)
+    assert rel(got, ref) < 1e-8, (got, ref)
+    assert st["n_ham"] > 0
+
+
+def test_autograd_amplitude_gradient_matches_fd():
+    """dL/dA through the autograd Function (adjoint GMRES + amplitude
+    gradient) against central differences of the library's own loss with the
+    ground state recomputed at A +- h (L = ||drho - t||^2)."""
+    import torch
+    from paper_2505_02319_amd import default_opts, dyson_solve
+    from workloads import config
+    spec = config("tiny")
+    rs, osys, ogs = _gpu_system_for(spec)
+    b = to_dev(random_field(spec, 2))
+    t = to_dev(random_field(spec, 3))
+    opts = default_opts(strategy="grt", tol=1e-12)
+    amp = torch.tensor(np.asarray(spec.amp, float), requires_grad=True)
+    x = dyson_solve(b, rs, opts, amplitudes=amp)
+    loss = torch.sum((x - t) ** 2)
+    loss.backward()
+    grad = amp.grad.numpy()
+    h = 1e-4
+    for atom in range(spec.natoms):
+        vals = []
+        for sgn in (1, -1):
+            a2 = np.array(spec.amp, float)
+            a2[atom] += sgn * h
+            rs2, _, _ = _gpu_system_for(spec.with_(amp=a2))
+            x2, _ = rs2.solve(b, opts)
+            vals.append(float(torch.sum((x2 - t) ** 2)))
+            rs2.close()
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(grad[atom] - fd) < 1e-5 * abs(fd), (atom, grad[atom], fd)
+
+
+def test_grad_amplitudes_rejects_smeared_occupations():
+    from paper_2505_02319_amd import IkrError
+    rs, osys, ogs, perms = gpu_system("tiny_metal")
+    v = to_dev(random_field(osys.spec, 2))
+    with pytest.raises(IkrError):
+        rs.grad_amplitudes(v, v, 1e-12)
