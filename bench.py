@@ -87,6 +87,8 @@ def main():
               "(k-point sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    # setup and eigensolver progress on stderr (large cells take minutes)
+    os.environ.setdefault("IKR_VERBOSE", "1")
     import torch
 
     if args.copy_probe:

@@ -123,13 +123,16 @@ typedef struct {
   long long n_ham_fp64;
   int gmres_iters;
   int restarts;
-  int cg_unconverged;       /* Sternheimer solves that hit the iteration cap */
+  int cg_unconverged;       /* Sternheimer solves that hit the iteration cap or
+                               broke down (after any FP64 fallback) */
   double est_res;           /* final estimated GMRES residual */
   double true_res;          /* ||b - E x|| if requested, else -1 */
   double s_final;
   double sigma_min;
   double knorm_last;        /* ||K v|| of the last dielectric application */
   double seconds;
+  long long fp64_fallback;  /* FP32 Sternheimer solves that did not converge and
+                               were solved again in FP64 (mixed precision) */
 } ikr_stats;
 
 /* Fill opts with the defaults above (strategy bal, tol 1e-8 relative). */

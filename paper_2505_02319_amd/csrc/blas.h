@@ -103,6 +103,9 @@ void multidot(int n, int nv, const double* V, size_t vstride, const double* w,
 void multiaxpy(int n, int nv, const double* V, size_t vstride, const double* c, double a,
                double* y, hipStream_t st);
 void scale_copy(size_t n, const double* x, double a, double* y, hipStream_t st);
+// full[i] = sum_n |G[n][i]|^2, re[i] = sum_n (Re G[n][i])^2 for n < nv (grid rows)
+void grid_row_norms(size_t ng, int nv, const double2* G, double* full, double* re,
+                    hipStream_t st);
 template <typename R>
 void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st);
 

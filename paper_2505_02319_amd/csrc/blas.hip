@@ -503,6 +503,21 @@ __global__ __launch_bounds__(NT) void resid_kernel(
   if (tid == 0) part[(size_t)slot * gridDim.x + blockIdx.x] = red[0];
 }
 
+// full[i] = sum_n |G[n][i]|^2 and re[i] = sum_n (Re G[n][i])^2 over the nv rows
+__global__ void grid_row_norms_kernel(size_t ng, int nv, const double2* __restrict__ G,
+                                      double* __restrict__ full, double* __restrict__ re) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ng) return;
+  double f = 0, r = 0;
+  for (int n = 0; n < nv; ++n) {
+    const double2 v = G[(size_t)n * ng + i];
+    f += v.x * v.x + v.y * v.y;
+    r += v.x * v.x;
+  }
+  full[i] = f;
+  re[i] = r;
+}
+
 // out[slot] = in[slot] over the sphere of the listed slots (precision change)
 template <typename A, typename B>
 __global__ __launch_bounds__(NT) void cvt_slots_kernel(
@@ -694,6 +709,13 @@ void multiaxpy(int n, int nv, const double* V, size_t vstride, const double* c, 
   IKR_CHECK(nv <= 64, 1, "too many vectors in multiaxpy");
   hipLaunchKernelGGL(multiaxpy_kernel, dim3((n + NT - 1) / NT), dim3(NT), 0, st, n, nv, V,
                      vstride, c, a, y);
+  IKR_HIP(hipGetLastError());
+}
+
+void grid_row_norms(size_t ng, int nv, const double2* G, double* full, double* re,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(grid_row_norms_kernel, dim3((ng + 255) / 256), dim3(256), 0, st, ng, nv, G,
+                     full, re);
   IKR_HIP(hipGetLastError());
 }
 

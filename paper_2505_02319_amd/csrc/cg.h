@@ -49,6 +49,10 @@ void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, con
               const R* pshift, cplx<R>* x, cplx<R>* r, const cplx<R>* p, cplx<R>* w,
               R* rpart, R* zpart, hipStream_t st);
 
+// x = p = 0 on the whole rows of the listed slots (the CG's start).
+template <typename R>
+void cg_zero(const Slots& sl, int nb_max, cplx<R>* x, cplx<R>* p, hipStream_t st);
+
 // alpha = rz / <p, Ap> per listed slot; on a breakdown (<p, Ap> <= 0 or a
 // non-finite alpha) alpha = 0 and the slot leaves the active set.
 template <typename R>

@@ -257,6 +257,19 @@ __global__ __launch_bounds__(NT) void cg_step2_kernel(
   }
 }
 
+// x = p = 0 over the whole row of every listed slot.
+template <typename R>
+__global__ __launch_bounds__(NT) void cg_zero_kernel(Slots s, int nb_max, cplx<R>* __restrict__ x,
+                                                     cplx<R>* __restrict__ p) {
+  if (!row_live(s, blockIdx.y)) return;
+  const int slot = slot_of(s, blockIdx.y);
+  const int g = blockIdx.x * NT + threadIdx.x;
+  if (g >= nb_max) return;
+  const size_t o = (size_t)slot * nb_max + g;
+  x[o] = mk<R>(0, 0);
+  p[o] = mk<R>(0, 0);
+}
+
 // One wavefront per listed slot.  A breakdown (<p, Ap> not positive or not
 // finite: the operator is positive definite on range Q, so this only comes
 // from round-off once the residual is at the precision floor) leaves x and r
@@ -317,7 +330,13 @@ __global__ __launch_bounds__(NT) void cg_finish_kernel(Slots s, int nparts,
     if (!conv) atomicAdd(cs.noconv, 1);
     return;
   }
-  cs.beta[slot] = cs.rz[slot] != R(0) ? rz / cs.rz[slot] : R(0);
+  const R beta = cs.rz[slot] != R(0) ? rz / cs.rz[slot] : R(0);
+  if (!(beta == beta && beta - beta == R(0))) {   // overflow: a breakdown
+    active[slot] = 0;
+    atomicAdd(cs.noconv, 1);
+    return;
+  }
+  cs.beta[slot] = beta;
   cs.rz[slot] = rz;
 }
 
@@ -427,6 +446,14 @@ void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, con
 }
 
 template <typename R>
+void cg_zero(const Slots& sl, int nb_max, cplx<R>* x, cplx<R>* p, hipStream_t st) {
+  if (sl.n <= 0) return;
+  hipLaunchKernelGGL((cg_zero_kernel<R>), dim3(cg_vec_blocks(nb_max), sl.n), dim3(NT), 0, st, sl,
+                     nb_max, x, p);
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
 void cg_alpha(const Slots& sl, int nparts, const R* dpart, const R* rz, R* alpha, int* active,
               hipStream_t st) {
   if (sl.n <= 0) return;
@@ -464,6 +491,7 @@ void cg_compact(int nk, const int* slot0_k, const int* nslot_k, const int* activ
   template void cg_step2<R>(const Slots&, const int*, const double*, int, const R*, const R*,  \
                             cplx<R>*, cplx<R>*, const cplx<R>*, cplx<R>*, R*, R*, hipStream_t); \
   template void cg_alpha<R>(const Slots&, int, const R*, const R*, R*, int*, hipStream_t);     \
+  template void cg_zero<R>(const Slots&, int, cplx<R>*, cplx<R>*, hipStream_t);               \
   template void cg_finish<R>(const Slots&, int, const R*, const R*, const CgScalars<R>&, int*,  \
                              int, hipStream_t);
 IKR_INST(double)

@@ -12,6 +12,9 @@
 #include <cstdlib>
 #include <random>
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include "system.h"
 
 namespace ikr {
@@ -25,95 +28,56 @@ namespace {
 
 using cd = double2;
 
-// Real symmetric Jacobi eigensolver (cyclic), eigenvalues ascending.
-void jacobi_sym(int n, std::vector<double>& A, std::vector<double>& w,
-                std::vector<double>& V) {
-  V.assign((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0, scale = 0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        const double a = A[(size_t)i * n + j];
-        if (i != j) off += a * a; else scale += a * a;
-      }
-    if (off <= 1e-30 * (scale + off) || off == 0.0) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[(size_t)p * n + q];
-        if (apq == 0.0) continue;
-        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-        const double theta = (aqq - app) / (2 * apq);
-        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
-        const double c = 1 / std::sqrt(t * t + 1), s = t * c;
-        for (int k = 0; k < n; ++k) {
-          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-          A[(size_t)k * n + p] = c * akp - s * akq;
-          A[(size_t)k * n + q] = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-          A[(size_t)p * n + k] = c * apk - s * aqk;
-          A[(size_t)q * n + k] = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-          V[(size_t)k * n + p] = c * vkp - s * vkq;
-          V[(size_t)k * n + q] = s * vkp + c * vkq;
-        }
-      }
-  }
-  std::vector<int> idx(n);
-  for (int i = 0; i < n; ++i) idx[i] = i;
-  std::sort(idx.begin(), idx.end(), [&](int a, int b) {
-    return A[(size_t)a * n + a] < A[(size_t)b * n + b];
-  });
-  std::vector<double> V2((size_t)n * n);
-  w.resize(n);
-  for (int j = 0; j < n; ++j) {
-    w[j] = A[(size_t)idx[j] * n + idx[j]];
-    for (int i = 0; i < n; ++i) V2[(size_t)i * n + j] = V[(size_t)i * n + idx[j]];
-  }
-  V.swap(V2);
-}
-
-// Hermitian eigenproblem A U = U diag(lam) through the real symmetric
-// embedding [[Re, -Im], [Im, Re]]; complex eigenvectors are picked from the
-// doubled real spectrum by Gram-Schmidt in ascending order.
-void herm_eig(int n, const std::vector<cd>& A, std::vector<double>& lam, std::vector<cd>& U) {
-  const int m = 2 * n;
-  std::vector<double> M((size_t)m * m), w, V;
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      const cd a = A[(size_t)i * n + j];
-      M[(size_t)i * m + j] = a.x;
-      M[(size_t)(i + n) * m + (j + n)] = a.x;
-      M[(size_t)i * m + (j + n)] = -a.y;
-      M[(size_t)(i + n) * m + j] = a.y;
+// Batched Hermitian eigenproblems A_k U_k = U_k diag(lam_k) on the device
+// (rocSOLVER zheevd, eigenvalues ascending); A_k row-major on the host, U_k
+// returned row-major (U[i * n + c] = component i of eigenvector c).
+struct BatchEig {
+  rocblas_handle h = nullptr;
+  DBuf<cd> A;
+  DBuf<double> D, E;
+  DBuf<int> info;
+  BatchEig() = default;
+  BatchEig(const BatchEig&) = delete;
+  BatchEig& operator=(const BatchEig&) = delete;
+  ~BatchEig() { if (h) (void)rocblas_destroy_handle(h); }
+  void run(hipStream_t st, int n, const std::vector<std::vector<cd>>& mats,
+           std::vector<double>& lam, std::vector<std::vector<cd>>& U) {
+    const int nb = (int)mats.size();
+    const size_t nn = (size_t)n * n;
+    if (!h) {
+      IKR_CHECK(rocblas_create_handle(&h) == rocblas_status_success, 7, "rocblas handle");
+      A.alloc(nn * nb);
+      D.alloc((size_t)n * nb);
+      E.alloc((size_t)n * nb);
+      info.alloc(nb);
     }
-  jacobi_sym(m, M, w, V);
-  lam.clear();
-  U.assign((size_t)n * n, mk<double>(0, 0));
-  int got = 0;
-  for (int c = 0; c < m && got < n; ++c) {
-    std::vector<cd> z(n);
-    for (int i = 0; i < n; ++i) z[i] = mk<double>(V[(size_t)i * m + c], V[(size_t)(i + n) * m + c]);
-    for (int pass = 0; pass < 2; ++pass)
-      for (int b = 0; b < got; ++b) {
-        cd d = mk<double>(0, 0);
-        for (int i = 0; i < n; ++i) d = cadd<double>(d, cmulc<double>(U[(size_t)i * n + b], z[i]));
-        for (int i = 0; i < n; ++i) z[i] = csub<double>(z[i], cmul<double>(U[(size_t)i * n + b], d));
+    IKR_CHECK(rocblas_set_stream(h, st) == rocblas_status_success, 7, "rocblas stream");
+    std::vector<cd> cm(nn * nb);
+    for (int k = 0; k < nb; ++k)
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) cm[k * nn + (size_t)j * n + i] = mats[k][(size_t)i * n + j];
+    IKR_HIP(hipMemcpyAsync(A.get(), cm.data(), cm.size() * sizeof(cd), hipMemcpyHostToDevice, st));
+    const rocblas_status r = rocsolver_zheevd_strided_batched(
+        h, rocblas_evect_original, rocblas_fill_upper, n,
+        reinterpret_cast<rocblas_double_complex*>(A.get()), n, (rocblas_stride)nn, D.get(), n,
+        E.get(), n, info.get(), nb);
+    IKR_CHECK(r == rocblas_status_success, 7, "rocsolver zheevd failed");
+    std::vector<int> inf(nb);
+    std::vector<double> d((size_t)n * nb);
+    IKR_HIP(hipMemcpyAsync(cm.data(), A.get(), cm.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
+    IKR_HIP(hipMemcpyAsync(d.data(), D.get(), d.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    IKR_HIP(hipMemcpyAsync(inf.data(), info.get(), nb * sizeof(int), hipMemcpyDeviceToHost, st));
+    IKR_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < nb; ++k) IKR_CHECK(inf[k] == 0, 4, "Hermitian eigensolver did not converge");
+    lam.assign((size_t)nb * n, 0.0);
+    U.assign(nb, std::vector<cd>(nn));
+    for (int k = 0; k < nb; ++k)
+      for (int c = 0; c < n; ++c) {
+        lam[(size_t)k * n + c] = d[(size_t)k * n + c];
+        for (int i = 0; i < n; ++i) U[k][(size_t)i * n + c] = cm[k * nn + (size_t)c * n + i];
       }
-    double nr = 0;
-    for (int i = 0; i < n; ++i) nr += z[i].x * z[i].x + z[i].y * z[i].y;
-    nr = std::sqrt(nr);
-    if (nr < 0.5) continue;
-    for (int i = 0; i < n; ++i) U[(size_t)i * n + got] = cscale<double>(z[i], 1.0 / nr);
-    lam.push_back(w[c]);
-    ++got;
   }
-  IKR_CHECK(got == n, 8, "Hermitian eigensolver lost a vector");
-}
+};
 
 // M = L^{-H} for G = L L^H (in place Cholesky with a diagonal shift on
 // failure); returns the upper-triangular M (row-major n x n).
@@ -303,14 +267,15 @@ void compute_ground_state(System& s) {
   std::vector<double> rnorm(ns, 1.0);
 
   // Rayleigh-Ritz on the orthonormal block Y: X = Y U, HX = (HY) U
+  BatchEig eig;
   auto rayleigh_ritz = [&]() {
     std::vector<double> zero(ns, 0.0);
     IKR_HIP(hipMemcpyAsync(dshift.get(), zero.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
     hpsi(Y, Z, dshift.get());
     auto Hs = gram_host(Y, Z);
-    std::vector<std::vector<cd>> U(nk);
+    std::vector<std::vector<cd>> U;
     for (int k = 0; k < nk; ++k) {
-      std::vector<cd> Ak(Hs[k]);
+      std::vector<cd>& Ak = Hs[k];
       for (int i = 0; i < nblk; ++i)
         for (int j = 0; j < i; ++j) {   // Hermitian average
           const cd a = Ak[(size_t)i * nblk + j], b = Ak[(size_t)j * nblk + i];
@@ -319,10 +284,8 @@ void compute_ground_state(System& s) {
           Ak[(size_t)j * nblk + i] = mk<double>(m.x, -m.y);
         }
       for (int i = 0; i < nblk; ++i) Ak[(size_t)i * nblk + i].y = 0;
-      std::vector<double> w;
-      herm_eig(nblk, Ak, w, U[k]);
-      for (int i = 0; i < nblk; ++i) lam[(size_t)k * nblk + i] = w[i];
     }
+    eig.run(st, nblk, Hs, lam, U);
     combine(Y, U, W);      // X
     combine(Z, U, HX.get());
     std::swap(Y, W);       // Y now holds X
@@ -345,7 +308,7 @@ void compute_ground_state(System& s) {
     double worst = 0;
     for (int k = 0; k < nk; ++k)
       for (int n = 0; n < nbn; ++n) worst = std::max(worst, rnorm[(size_t)k * nblk + n]);
-    if (verbose && (outer % 10 == 0))
+    if (verbose)
       std::fprintf(stderr, "[ikr eig] step %d worst residual %.3e  cut %.5f  top %.5f\n", outer,
                    worst, lam[nblk - 1], bup);
     if (worst <= tol) break;

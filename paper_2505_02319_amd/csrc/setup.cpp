@@ -3,6 +3,8 @@
 // projectors of the model, occupations, density and per-band caches.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <memory>
 
 #include "system.h"
@@ -330,6 +332,12 @@ void import_ground_state(System& s, const double* eps, const double* coeffs) {
 // Occupations (eq. density with f = 2/(1+e^x)), Fermi level, occupied
 // slots, column transforms of the occupied orbitals, density, the Slater
 // kernel and the grt orbital norms.
+// Setup progress on stderr when IKR_VERBOSE is set (large cells take minutes).
+static void progress(const char* stage) {
+  static const bool on = std::getenv("IKR_VERBOSE") != nullptr;
+  if (on) std::fprintf(stderr, "[ikr setup] %s\n", stage);
+}
+
 void finish_setup(System& s) {
   const int nk = s.nk, nbn = s.nbands;
   s.w32.x.alloc(0);   // FP32 copies are rebuilt from this ground state on demand
@@ -446,6 +454,7 @@ void finish_setup(System& s) {
   s.d_wb.alloc(s.J);
   s.d_multi.alloc((size_t)64 * 256);
 
+  progress("occupations, slots and work space ready");
   // -- column transforms of the occupied orbitals (slot order)
   s.d_Tphi.alloc(tbuf);
   for (int j = 0; j < s.J; ++j)
@@ -477,6 +486,7 @@ void finish_setup(System& s) {
     s.w64.shift.upload(sh, st);
   }
 
+  progress("column transforms and preconditioner shifts ready");
   // -- fused CG projections: W_k = [projectors | phi_1, H phi_1, phi_2, H phi_2, ...],
   //    G^T[k][j][m] = <phi_m, H phi_j> and S^T[k][j][m] = <phi_m, phi_j>
   {
@@ -519,6 +529,7 @@ void finish_setup(System& s) {
     IKR_HIP(hipStreamSynchronize(st));
   }
 
+  progress("fused CG tables ready");
   // -- density rho = sum_k w_k sum_n f |psi|^2 (grid values)
   {
     const int gs = 8;
@@ -551,37 +562,37 @@ void finish_setup(System& s) {
     const double bmin = std::min({s.b[0], s.b[1], s.b[2]});
     s.knorm_bound = 4.0 * PI / (bmin * bmin) + fxmax;
   }
+  progress("density and exchange kernel ready");
   // -- ||Re F_k^-1 Phi_k||_{2,inf} per k (grt strategy)
   {
     s.orbnorm_k.assign(nk, 0.0);
     s.orbnorm_full_k.assign(nk, 0.0);
     DBuf<double2> grid;
+    DBuf<double> dfull, dre;
     int maxo = s.nocc_max;
     grid.alloc((size_t)maxo * s.ng);
-    std::vector<double2> hg((size_t)maxo * s.ng);
+    dfull.alloc(s.ng);
+    dre.alloc(s.ng);
+    std::vector<double> hf(s.ng), hr(s.ng);
     for (int k = 0; k < nk; ++k) {
       const int j0 = s.slot0_k[k], no = s.nocc_k[k];
       launch_plane_grid(s.geom, s.fft, no, s.d_slot_k.get() + j0,
                         s.d_Tphi.get() + (size_t)j0 * s.L.C * s.ncol_max, grid.get(), st);
-      IKR_HIP(hipMemcpyAsync(hg.data(), grid.get(), (size_t)no * s.ng * sizeof(double2),
-                             hipMemcpyDeviceToHost, st));
+      grid_row_norms(s.ng, no, grid.get(), dfull.get(), dre.get(), st);
+      IKR_HIP(hipMemcpyAsync(hf.data(), dfull.get(), s.ng * sizeof(double), hipMemcpyDeviceToHost, st));
+      IKR_HIP(hipMemcpyAsync(hr.data(), dre.get(), s.ng * sizeof(double), hipMemcpyDeviceToHost, st));
       IKR_HIP(hipStreamSynchronize(st));
       double mx = 0, mxf = 0;
       for (int i = 0; i < s.ng; ++i) {
-        double acc = 0, accf = 0;
-        for (int n = 0; n < no; ++n) {
-          const double2 v = hg[(size_t)n * s.ng + i];
-          acc += v.x * v.x;
-          accf += v.x * v.x + v.y * v.y;
-        }
-        mx = std::max(mx, acc);
-        mxf = std::max(mxf, accf);
+        mx = std::max(mx, hr[i]);
+        mxf = std::max(mxf, hf[i]);
       }
       s.orbnorm_k[k] = std::sqrt(mx / s.volume);
       s.orbnorm_full_k[k] = std::sqrt(mxf / s.volume);
     }
   }
   IKR_HIP(hipStreamSynchronize(st));
+  progress("orbital norms ready");
   s.have_gs = true;
 }
 

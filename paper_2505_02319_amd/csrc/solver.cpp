@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 
 #include "cg.h"
 #include "ktimer.h"
@@ -208,8 +209,6 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   if (w.r.get() != rhs)
     IKR_HIP(hipMemcpyAsync(w.r.get(), rhs, (size_t)J * nbm * sizeof(cplx<R>),
                            hipMemcpyDeviceToDevice, st));
-  IKR_HIP(hipMemsetAsync(w.x.get(), 0, (size_t)J * nbm * sizeof(cplx<R>), st));
-  IKR_HIP(hipMemsetAsync(w.p.get(), 0, (size_t)J * nbm * sizeof(cplx<R>), st));
   std::vector<double> tol2(J);
   for (int j = 0; j < J; ++j) tol2[j] = tol_slot[j] * tol_slot[j];
   IKR_HIP(hipMemcpyAsync(s.d_tol2.get(), tol2.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
@@ -236,6 +235,9 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   }
   int nact = nmem;
   compact(-1);
+  // x = p = 0 for the members only: other slots keep what they hold
+  cg_zero<R>(Slots{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt}, nbm, w.x.get(),
+             w.p.get(), st);
   {
     // z = M^-1 r, rz = <r, z>, beta = 0
     Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
@@ -457,7 +459,23 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
                                       max_iter, dMq, Mq_max, dMcg);
     convert_slots(n32, dl32.get(), s.d_slot_k.get(), s.d_nb.get(), nbm, s.w32.x.get(), w.x.get(), st);
     res.n_ham32 = o32.n_ham;
-    res.noconv += o32.noconv;
+    // FP64 fallback: an FP32 band that broke down, hit the cap or ended
+    // non-finite is solved again in FP64 from its right-hand side (still in
+    // the FP64 r, which the FP32 solve did not touch)
+    if (o32.noconv > 0) {
+      const std::vector<float> rn = download(s.w32.rnorm2.get(), J, st);
+      std::vector<int> mf(J, 0);
+      int nf = 0;
+      for (int j = 0; j < J; ++j)
+        if (m32[j] && !((double)rn[j] <= tol_slot[j] * tol_slot[j])) { mf[j] = 1; ++nf; }
+      if (nf > 0) {
+        const CgOut of = run_cg<double>(s, s.w64, w.r.get(), mf, tol_slot, min_iter, max_iter,
+                                        dMq, Mq_max, dMcg);
+        res.n_ham64 += of.n_ham;
+        res.noconv += of.noconv;
+        res.fallback += nf;
+      }
+    }
   }
   res.n_ham = res.n_ham64 + res.n_ham32;
   UpdTerm<double> phiA{s.d_phi.get(), phik, nbm, dMq, w.coefA.get(), MAXM, -1.0, Mq_max};
@@ -547,6 +565,30 @@ static std::vector<double> prefactors(const System& s, int strategy, double knor
 }
 
 // ---------------------------------------------------------------- E v
+// Euclidean norm of a grid vector (fixed-order reduction).
+static double grid_norm(System& s, const double* v) {
+  const int nbl = multidot_nblocks(s.ng);
+  multidot(s.ng, 1, v, s.ng, v, s.d_multi.get(), s.stream);
+  const std::vector<double> h = download(s.d_multi.get(), nbl, s.stream);
+  double a = 0;
+  for (double x : h) a += x;
+  return std::sqrt(a);
+}
+
+// Rejects a non-finite chi0 result with what went into it.
+static void check_finite_response(System& s, const Chi0Result& r, const std::vector<double>& tol) {
+  const double nr = grid_norm(s, s.d_drho.get());
+  if (std::isfinite(nr)) return;
+  double tmin = 1e300, tmax = 0;
+  for (double t : tol) { tmin = std::min(tmin, t); tmax = std::max(tmax, t); }
+  char msg[256];
+  std::snprintf(msg, sizeof msg,
+                "non-finite chi0 response (H applications FP64 %lld, FP32 %lld, unconverged %d, "
+                "CG tolerances %.2e..%.2e)",
+                r.n_ham64, r.n_ham32, r.noconv, tmin, tmax);
+  throw Error(5, msg);
+}
+
 void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext, double common,
                           const ikr_solver_opts& o, double bnorm, ikr_stats* stt) {
   const hipStream_t st = s.stream;
@@ -570,19 +612,11 @@ void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext, double
     stt->n_ham_fp64 += r.n_ham64;
     stt->n_ham_fp32 += r.n_ham32;
     stt->cg_unconverged += r.noconv;
+    stt->fp64_fallback += r.fallback;
   }
+  check_finite_response(s, r, tol);
   to_external(s.L, s.d_drho.get(), ev_ext, -nu, v_ext, 1.0, st);
   IKR_HIP(hipStreamSynchronize(st));
-}
-
-// Euclidean norm of a grid vector (fixed-order reduction).
-static double grid_norm(System& s, const double* v) {
-  const int nbl = multidot_nblocks(s.ng);
-  multidot(s.ng, 1, v, s.ng, v, s.d_multi.get(), s.stream);
-  const std::vector<double> h = download(s.d_multi.get(), nbl, s.stream);
-  double a = 0;
-  for (double x : h) a += x;
-  return std::sqrt(a);
 }
 
 // ev = E~^T v = v - ||v|| K chi0~(v / ||v||).  K and chi0 are symmetric in
@@ -612,7 +646,9 @@ void apply_dielectric_adjoint_ext(System& s, const double* v_ext, double* ev_ext
     stt->n_ham_fp64 += r.n_ham64;
     stt->n_ham_fp32 += r.n_ham32;
     stt->cg_unconverged += r.noconv;
+    stt->fp64_fallback += r.fallback;
   }
+  check_finite_response(s, r, tol);
   apply_kernel(s, s.d_drho.get(), s.d_u.get());
   to_external(s.L, s.d_u.get(), ev_ext, -nu, v_ext, 1.0, st);
   IKR_HIP(hipStreamSynchronize(st));
@@ -694,7 +730,12 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
       for (int j = 0; j < i; ++j) { neg[j] = -h2[j]; h[j] += h2[j]; }
       axpy(i, V.get(), neg, 1.0, vi);
       const double hn = std::sqrt(dots(1, vi, vi)[0]);
-      IKR_CHECK(std::isfinite(hn), 5, "non-finite Krylov vector");
+      if (!std::isfinite(hn)) {
+        char msg[128];
+        std::snprintf(msg, sizeof msg, "non-finite Krylov vector at GMRES step %d (restart %d)",
+                      iters, restarts);
+        throw Error(5, msg);
+      }
       for (int j = 0; j < i; ++j) H[(size_t)j * m + (i - 1)] = h[j];
       H[(size_t)i * m + (i - 1)] = hn;
       if (hn > 0) scale_copy(n, vi, 1.0 / hn, vi, st);
