@@ -1,5 +1,6 @@
-// In-LDS batched 1D FFTs for gfx950: mixed-radix (2, 3, 4, 5) Stockham
-// autosort stages, each thread holding its butterflies in registers for the
+// In-LDS batched 1D FFTs for gfx950: mixed-radix Stockham autosort stages
+// (butterflies of 2, 3, 4, 5 points and their composites 6, 8, 9, 12, 16,
+// so that the common lengths take two stages), each thread holding its butterflies in registers for the
 // duration of a stage, so that a stage reads every element of the line,
 // synchronises, then writes every element back in place (no ping-pong
 // buffer: a 60 x 108 FP64 plane already takes 101 KiB of the 160 KiB LDS).
@@ -20,39 +21,39 @@ template <int N> struct Rad;
     static constexpr int r[] = {__VA_ARGS__};                                  \
     static constexpr int S = sizeof(r) / sizeof(int);                          \
   };
-IKR_RAD(8, 4, 2)
-IKR_RAD(12, 4, 3)
-IKR_RAD(16, 4, 4)
-IKR_RAD(18, 3, 3, 2)
+IKR_RAD(8, 8)
+IKR_RAD(12, 12)
+IKR_RAD(16, 16)
+IKR_RAD(18, 6, 3)
 IKR_RAD(20, 4, 5)
-IKR_RAD(24, 4, 3, 2)
-IKR_RAD(30, 5, 3, 2)
-IKR_RAD(32, 4, 4, 2)
-IKR_RAD(36, 4, 3, 3)
-IKR_RAD(40, 4, 5, 2)
-IKR_RAD(48, 4, 4, 3)
-IKR_RAD(60, 4, 5, 3)
-IKR_RAD(64, 4, 4, 4)
-IKR_RAD(72, 4, 3, 3, 2)
-IKR_RAD(80, 4, 4, 5)
-IKR_RAD(90, 5, 3, 3, 2)
-IKR_RAD(96, 4, 4, 3, 2)
+IKR_RAD(24, 8, 3)
+IKR_RAD(30, 6, 5)
+IKR_RAD(32, 16, 2)
+IKR_RAD(36, 6, 6)
+IKR_RAD(40, 8, 5)
+IKR_RAD(48, 16, 3)
+IKR_RAD(60, 12, 5)
+IKR_RAD(64, 16, 4)
+IKR_RAD(72, 8, 9)
+IKR_RAD(80, 16, 5)
+IKR_RAD(90, 6, 5, 3)
+IKR_RAD(96, 16, 6)
 IKR_RAD(100, 4, 5, 5)
-IKR_RAD(108, 4, 3, 3, 3)
-IKR_RAD(120, 4, 5, 3, 2)
-IKR_RAD(128, 4, 4, 4, 2)
+IKR_RAD(108, 12, 9)
+IKR_RAD(120, 8, 5, 3)
+IKR_RAD(128, 16, 8)
 #undef IKR_RAD
 
 // ------------------------------------------------------------ small DFTs
 template <typename R, bool INV>
-__device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) {  // a * (-i) forward, a * (+i) inverse
+__host__ __device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) {  // a * (-i) forward, a * (+i) inverse
   return INV ? mk<R>(-a.y, a.x) : mk<R>(a.y, -a.x);
 }
 
 template <typename R, int RAD, bool INV> struct Dft;
 
 template <typename R, bool INV> struct Dft<R, 2, INV> {
-  __device__ __forceinline__ static void run(cplx<R>* v) {
+  __host__ __device__ __forceinline__ static void run(cplx<R>* v) {
     cplx<R> a = v[0], b = v[1];
     v[0] = cadd<R>(a, b);
     v[1] = csub<R>(a, b);
@@ -60,7 +61,7 @@ template <typename R, bool INV> struct Dft<R, 2, INV> {
 };
 
 template <typename R, bool INV> struct Dft<R, 3, INV> {
-  __device__ __forceinline__ static void run(cplx<R>* v) {
+  __host__ __device__ __forceinline__ static void run(cplx<R>* v) {
     const R s = R(0.86602540378443864676372317075294);   // sqrt(3)/2
     cplx<R> a = v[0], b = v[1], c = v[2];
     cplx<R> t1 = cadd<R>(b, c);
@@ -73,7 +74,7 @@ template <typename R, bool INV> struct Dft<R, 3, INV> {
 };
 
 template <typename R, bool INV> struct Dft<R, 4, INV> {
-  __device__ __forceinline__ static void run(cplx<R>* v) {
+  __host__ __device__ __forceinline__ static void run(cplx<R>* v) {
     cplx<R> a = v[0], b = v[1], c = v[2], d = v[3];
     cplx<R> t0 = cadd<R>(a, c), t1 = csub<R>(a, c);
     cplx<R> t2 = cadd<R>(b, d), t3 = mul_mi<R, INV>(csub<R>(b, d));
@@ -85,7 +86,7 @@ template <typename R, bool INV> struct Dft<R, 4, INV> {
 };
 
 template <typename R, bool INV> struct Dft<R, 5, INV> {
-  __device__ __forceinline__ static void run(cplx<R>* v) {
+  __host__ __device__ __forceinline__ static void run(cplx<R>* v) {
     // c1 = cos(2pi/5), c2 = cos(4pi/5), s1 = sin(2pi/5), s2 = sin(4pi/5)
     const R c1 = R(0.30901699437494742410229341718282);
     const R c2 = R(-0.80901699437494742410229341718282);
@@ -105,6 +106,73 @@ template <typename R, bool INV> struct Dft<R, 5, INV> {
     v[3] = csub<R>(u2, w2);
   }
 };
+
+// ------------------------------------------------------------ composite DFTs
+// e^{-2 pi i m / N} = c[m] - i s[m] for the composite radices (correctly
+// rounded values of the cosines and sines of 2 pi m / N).
+template <int N> struct TwConst;
+template <> struct TwConst<6> {
+  static constexpr double c[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+  static constexpr double s[6] = {0.0, 0.8660254037844386, 0.8660254037844386, 0.0, -0.8660254037844386, -0.8660254037844386};
+};
+template <> struct TwConst<8> {
+  static constexpr double c[8] = {1.0, 0.7071067811865476, 0.0, -0.7071067811865476, -1.0, -0.7071067811865476, 0.0, 0.7071067811865476};
+  static constexpr double s[8] = {0.0, 0.7071067811865476, 1.0, 0.7071067811865476, 0.0, -0.7071067811865476, -1.0, -0.7071067811865476};
+};
+template <> struct TwConst<9> {
+  static constexpr double c[9] = {1.0, 0.766044443118978, 0.17364817766693036, -0.5, -0.9396926207859084, -0.9396926207859084, -0.5, 0.17364817766693036, 0.766044443118978};
+  static constexpr double s[9] = {0.0, 0.6427876096865394, 0.984807753012208, 0.8660254037844386, 0.3420201433256687, -0.3420201433256687, -0.8660254037844386, -0.984807753012208, -0.6427876096865394};
+};
+template <> struct TwConst<12> {
+  static constexpr double c[12] = {1.0, 0.8660254037844386, 0.5, 0.0, -0.5, -0.8660254037844386, -1.0, -0.8660254037844386, -0.5, 0.0, 0.5, 0.8660254037844386};
+  static constexpr double s[12] = {0.0, 0.5, 0.8660254037844386, 1.0, 0.8660254037844386, 0.5, 0.0, -0.5, -0.8660254037844386, -1.0, -0.8660254037844386, -0.5};
+};
+template <> struct TwConst<16> {
+  static constexpr double c[16] = {1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898, 0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867, -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898, 0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867};
+  static constexpr double s[16] = {0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867, 1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898, 0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867, -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898};
+};
+
+// N = A * B point DFT: A-point DFTs over the B interleaved subsequences,
+// twiddles W_N^{j2 k1}, then B-point DFTs (output index k1 + A k2).
+template <typename R, int A, int B, bool INV> struct DftComp {
+  __host__ __host__ __device__ __forceinline__ static void run(cplx<R>* v) {
+    constexpr int N = A * B;
+    cplx<R> y[B][A];
+#pragma unroll
+    for (int j2 = 0; j2 < B; ++j2) {
+      cplx<R> t[A];
+#pragma unroll
+      for (int j1 = 0; j1 < A; ++j1) t[j1] = v[B * j1 + j2];
+      Dft<R, A, INV>::run(t);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        const int m = (j2 * k1) % N;
+        if (m == 0) {
+          y[j2][k1] = t[k1];
+        } else {
+          const R c = R(TwConst<N>::c[m]);
+          const R sn = INV ? R(TwConst<N>::s[m]) : R(-TwConst<N>::s[m]);
+          y[j2][k1] = mk<R>(t[k1].x * c - t[k1].y * sn, t[k1].x * sn + t[k1].y * c);
+        }
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      cplx<R> t[B];
+#pragma unroll
+      for (int j2 = 0; j2 < B; ++j2) t[j2] = y[j2][k1];
+      Dft<R, B, INV>::run(t);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = t[k2];
+    }
+  }
+};
+
+template <typename R, bool INV> struct Dft<R, 6, INV> : DftComp<R, 3, 2, INV> {};
+template <typename R, bool INV> struct Dft<R, 8, INV> : DftComp<R, 4, 2, INV> {};
+template <typename R, bool INV> struct Dft<R, 9, INV> : DftComp<R, 3, 3, INV> {};
+template <typename R, bool INV> struct Dft<R, 12, INV> : DftComp<R, 4, 3, INV> {};
+template <typename R, bool INV> struct Dft<R, 16, INV> : DftComp<R, 4, 4, INV> {};
 
 // ------------------------------------------------------------ stage driver
 // Lines live in LDS at buf[l * lstride + e * estride], l < nlines <= MAXL.
