@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (counter calibration)")
+    ap.add_argument("--gradient", action="store_true",
+                    help="time the forward solve and the adjoint backward (dL/db, dL/dA) "
+                         "and check them against central differences")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the response path here is single-GPU "
@@ -101,6 +104,9 @@ def main():
 
     spec = config(args.workload)
     torch.cuda.set_device(0)
+    if args.gradient:
+        gradient_bench(torch, spec, args)
+        return
     t0 = time.perf_counter()
     rs = ResponseSystem(spec, ground_state="compute")
     info = rs.setup_info()
@@ -187,6 +193,66 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(spec, n_ham / args.steps, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    rs.close()
+
+
+def gradient_bench(torch, spec, args):
+    """Loss L = ||drho - drho_t||^2 with drho = E^-1 b and drho_t = E^-1 b' (tight):
+    forward and backward (adjoint GMRES, dL/db, and dL/dA through the adjoint
+    Sternheimer solves) timed, then checked against central differences in b
+    (exact for a quadratic) and in the amplitude of atom 0 (ground state
+    recomputed at A +- h)."""
+    import numpy as np
+
+    from paper_2505_02319_amd import ResponseSystem, default_opts, dyson_solve
+    from workloads import B_SEED, BPRIME_SEED, random_field
+    opts = default_opts(strategy="grt", tol=1e-10, tol_is_relative=1, precision=0)
+    t0 = time.perf_counter()
+    rs = ResponseSystem(spec, ground_state="compute")
+    log(f"setup {spec.name}: {time.perf_counter() - t0:.1f} s")
+    b = torch.from_numpy(random_field(spec, B_SEED)).cuda()
+    target, _ = rs.solve(torch.from_numpy(random_field(spec, BPRIME_SEED)).cuda(),
+                         default_opts(strategy="grt", tol=1e-10, tol_is_relative=1))
+    amp = torch.tensor(np.asarray(spec.amp, float), requires_grad=True)
+    bl = b.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x = dyson_solve(bl, rs, opts, amplitudes=amp)
+    loss = torch.sum((x - target) ** 2)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t2
+    gb = bl.grad.detach()
+    ga = amp.grad.numpy().copy()
+    log(f"forward {t_fwd:.2f} s, backward {t_bwd:.2f} s")
+
+    def lossval(r, bv):
+        xv, _ = r.solve(bv, opts)
+        return float(torch.sum((xv - target) ** 2))
+    d = torch.from_numpy(random_field(spec, 7)).cuda()
+    h = 1e-3
+    fd_b = (lossval(rs, b + h * d) - lossval(rs, b - h * d)) / (2 * h)
+    an_b = float(torch.sum(gb * d))
+    ha = 1e-4
+    vals = []
+    for sgn in (1, -1):
+        a2 = np.array(spec.amp, float)
+        a2[0] += sgn * ha
+        r2 = ResponseSystem(spec.with_(amp=a2), ground_state="compute")
+        vals.append(lossval(r2, b))
+        r2.close()
+        log(f"amplitude {'+' if sgn > 0 else '-'}h done")
+    fd_a = (vals[0] - vals[1]) / (2 * ha)
+    out = {"metric": "gradient of ||drho - drho_t||^2 (dL/db, dL/dA)", "workload": spec.name,
+           "forward_s": t_fwd, "backward_s": t_bwd, "backward_over_forward": t_bwd / t_fwd,
+           "dLdb_directional_rel_err_vs_fd": abs(an_b - fd_b) / abs(fd_b),
+           "dLdA0": float(ga[0]), "dLdA0_fd": fd_a,
+           "dLdA0_rel_err_vs_fd": abs(ga[0] - fd_a) / abs(fd_a),
+           "fd_steps": {"b": h, "A": ha}, "gmres_tol": 1e-10, "loss": float(loss.detach())}
     print(json.dumps(out), flush=True)
     rs.close()
 

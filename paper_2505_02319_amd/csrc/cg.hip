@@ -240,11 +240,13 @@ __global__ __launch_bounds__(NT) void cg_step2_kernel(
     const size_t o = (size_t)slot * nb_max + g;
     const R a = alpha[slot];
     cplx<R> xv = x[o], rv = r[o];
-    const cplx<R> pv = p[o], wv = w[o];
-    xv = mk<R>(xv.x + a * pv.x, xv.y + a * pv.y);
-    rv = mk<R>(rv.x - a * wv.x, rv.y - a * wv.y);
-    x[o] = xv;
-    r[o] = rv;
+    if (a != R(0)) {       // alpha = 0: a breakdown, x and r stay as they are
+      const cplx<R> pv = p[o], wv = w[o];
+      xv = mk<R>(xv.x + a * pv.x, xv.y + a * pv.y);
+      rv = mk<R>(rv.x - a * wv.x, rv.y - a * wv.y);
+      x[o] = xv;
+      r[o] = rv;
+    }
     const R m = R(1) / (R(kin[(size_t)k * nb_max + g]) + pshift[slot]);
     w[o] = cscale<R>(rv, m);
     rr = rv.x * rv.x + rv.y * rv.y;
@@ -288,7 +290,9 @@ __global__ __launch_bounds__(NT) void cg_alpha_kernel(Slots s, int nparts,
   v = wsum(v);
   if (lane != 0) return;
   const R a = rz[slot] / v;
-  if (v > R(0) && a == a && a - a == R(0)) {
+  // alpha of a positive definite, kinetic-preconditioned operator stays far
+  // below 1e12; a larger value only comes from round-off in <p, Ap>
+  if (v > R(0) && a == a && a < R(1e12)) {
     alpha[slot] = a;
   } else {
     alpha[slot] = R(0);
@@ -321,7 +325,8 @@ __global__ __launch_bounds__(NT) void cg_finish_kernel(Slots s, int nparts,
   const int it = ++cs.iters[slot];
   cs.rnorm2[slot] = rr;
   const bool conv = it >= cs.min_iter && (double)rr <= cs.tol2[slot];
-  if (!active[slot]) {            // stopped by a breakdown in this iteration
+  if (!active[slot] || !(rr == rr && rr - rr == R(0))) {   // breakdown this iteration
+    active[slot] = 0;
     if (!conv) atomicAdd(cs.noconv, 1);
     return;
   }

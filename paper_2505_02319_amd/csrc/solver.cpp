@@ -17,7 +17,7 @@ namespace ikr {
 namespace {
 
 constexpr double DEGEN_TOL = 1e-8;
-constexpr double TOL_FLOOR = 1e-14;   // CG tolerances never below this times ||b_j||
+constexpr double TOL_FLOOR = 1e-13;   // CG tolerances never below this times ||b_j||
 
 double focc_dx(double x) {
   const double e = std::exp(-std::fabs(x));
@@ -429,7 +429,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   // right-hand side run the CG in FP32 (FP32 FFTs and projections); the
   // others, and everything after the CG, stay in FP64.
   // Tolerances are floored at TOL_FLOOR ||b_j||: below that the FP64
-  // recursion has nothing left to resolve (round-off level).
+  // recursion stagnates at round-off on the ill-conditioned bands.
   std::vector<double> tol_slot(tol_in);
   std::vector<int> m64(J, 1), m32(J, 0);
   int n32 = 0;
