@@ -372,8 +372,19 @@ def apply_dielectric_adjoint(sys: System, gs: GroundState, kern: HxcKernel,
 
 def orbital_row_norm(sys: System, gs: GroundState, ik: int, real_part: bool = True) -> float:
     """||F_k^-1 Phi_k||_{2,inf} (max over grid points of the row norm), or of
-    its real part (Sec. 3.4.1, used by the grt strategy)."""
+    its real part (Sec. 3.4.1, used by the grt strategy).
+
+    The real part depends on the phase of each orbital, which the eigensolver
+    leaves arbitrary.  Sec. 3.4.1 takes it where a real representation of the
+    orbitals can be chosen; each orbital is therefore first multiplied by the
+    phase that makes sum_r psi(r)^2 real and positive (this is the real
+    representation whenever one exists), and the result is floored at
+    ||F_k^-1 Phi_k||_{2,inf} / sqrt(2), the largest loss the section allows."""
     nocc = gs.nocc_k[ik]
     psi = sys.to_grid(ik, gs.phi[ik][:nocc]).reshape(nocc, -1)
-    a = psi.real if real_part else psi
-    return float(np.sqrt(np.max(np.sum(np.abs(a) ** 2, axis=0))))
+    full = float(np.sqrt(np.max(np.sum(np.abs(psi) ** 2, axis=0))))
+    if not real_part:
+        return full
+    theta = -0.5 * np.angle(np.sum(psi * psi, axis=1))
+    re = (psi * np.exp(1j * theta)[:, None]).real
+    return max(float(np.sqrt(np.max(np.sum(re ** 2, axis=0)))), full / np.sqrt(2.0))

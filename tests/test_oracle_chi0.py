@@ -120,6 +120,26 @@ def test_orbital_row_norm_bounds(name, oracle_case):
         assert orbital_row_norm(sys, gs, ik, real_part=True) <= val * (1 + 1e-12)
 
 
+@pytest.mark.parametrize("name", ["tiny_k", "tiny_metal"])
+def test_real_part_orbital_norm_is_phase_independent(name, oracle_case):
+    """The real-part orbital term of the grt strategy (Sec. 3.4.1) does not
+    depend on the phases the eigensolver gives the orbitals; it lies between
+    ||F^-1 Phi||_{2,inf} / sqrt(2) and ||F^-1 Phi||_{2,inf}; and for a single
+    Gamma orbital (real up to a phase: time reversal) it equals the full norm."""
+    import dataclasses
+    sys, gs = oracle_case(name)
+    rng = np.random.default_rng(7)
+    phased = dataclasses.replace(
+        gs, phi=[p * np.exp(2j * np.pi * rng.random(p.shape[0]))[:, None] for p in gs.phi])
+    for ik in range(len(sys.bases)):
+        re = orbital_row_norm(sys, gs, ik, real_part=True)
+        full = orbital_row_norm(sys, gs, ik, real_part=False)
+        assert abs(orbital_row_norm(sys, phased, ik, real_part=True) - re) < 1e-12 * full
+        assert full / np.sqrt(2) * (1 - 1e-12) <= re <= full * (1 + 1e-12)
+        if np.allclose(sys.bases[ik].kfrac, 0) and gs.nocc_k[ik] == 1:
+            assert abs(re - full) < 1e-10 * full
+
+
 def test_lemma_cgtol_bound_holds(oracle_case):
     """||(E - E~) v|| <= 2 ||Kv|| ||F^-1 Phi||_{2,inf} sqrt(N_g N_occ)/sqrt|Omega|
     * max_n f_n tau_n / (e_{N+1} - e_n)   (Lemma cgtol_E, Gamma only)."""
