@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--no-checks", action="store_true",
                     help="skip the untimed accuracy and FP64 comparison solves")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--graph-steps", type=int, default=2,
+                    help="solves timed again with each CG iteration replayed from a HIP graph "
+                         "(reported beside the headline, which uses plain launches)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (counter calibration)")
     ap.add_argument("--gradient", action="store_true",
@@ -149,6 +152,22 @@ def main():
     profile_enable(False)
     prof = profile_query()
 
+    # the same solves with every CG iteration replayed from a captured graph
+    graph = None
+    if args.graph_steps > 0:
+        gopts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
+                             precision=args.precision, schur=args.schur, batching=1)
+        rs.solve(b, gopts)                       # captures the graphs
+        torch.cuda.synchronize()
+        t_g = time.perf_counter()
+        for _ in range(args.graph_steps):
+            xg, stg = rs.solve(b, gopts)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t_g) / args.graph_steps
+        graph = {"seconds_per_solve": sec, "solves_per_s": 1.0 / sec, "n_ham": stg["n_ham"],
+                 "rel_diff_vs_launches": float(torch.linalg.norm(xg - x) / torch.linalg.norm(x))}
+        log(f"graph replay: {sec:.3f} s per solve, N_ham {stg['n_ham']}")
+
     bnorm = float(torch.linalg.norm(b))
     true_rel, fp64, n32 = None, None, None
     if not args.no_checks:
@@ -174,6 +193,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == 0 else "f32/f64",
         "fp64_cg_solve": fp64,
+        "graph_replay_solve": graph,
         "n_ham_fp32_per_solve": n32,
         "data": "synthetic",
         "config": {"workload": describe(spec, args), "global_batch": 1,

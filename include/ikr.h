@@ -115,6 +115,17 @@ typedef struct {
                                extra-band / Schur-complement treatment the paper's
                                runs use, Sec. 4.1.2); 0: CG on the complement of
                                the occupied bands only (default 1) */
+  int batching;             /* 0: one launch per kernel in every Sternheimer CG
+                               iteration; 1: each iteration is one replay of a
+                               captured HIP graph (graphs are cached on the handle
+                               per grid size; the caller's stream may be the
+                               default stream: capture and replay use a private
+                               stream joined to it).  Results agree with mode 0
+                               to rounding (grids sized to a power of two may
+                               split sums differently); replays are bitwise
+                               reproducible.
+                               Kernel profiling (ikr_profile_enable) switches
+                               graphs off.  Default 0 */
 } ikr_solver_opts;
 
 typedef struct {
@@ -176,6 +187,14 @@ ikr_status ikr_get_ground_state(ikr_handle h, double* eps_host,
  * eigen-residual norm ||H phi - e phi|| it reached.  Any pointer may be NULL. */
 ikr_status ikr_get_setup_info(ikr_handle h, double* gaps_host, int* gs_iters,
                               double* gs_residual);
+
+/* Orbital terms of the tolerance strategies (host, [nk] each, may be NULL):
+ * full_host[k] = ||F_k^-1 Phi_k||_{2,inf} over the occupied orbitals (the
+ * maximum over grid points of the row norm, with psi normalised on the cell;
+ * Lemma cgtol_E and Theorem 2) and re_host[k] the same of the real parts
+ * (grt, Sec. 3.4.1), each orbital taken with the phase that makes
+ * sum_r psi(r)^2 real and positive, floored at full_host[k] / sqrt(2). */
+ikr_status ikr_get_orbital_norms(ikr_handle h, double* re_host, double* full_host);
 
 /* Ground-state density on the grid (device, C order). */
 ikr_status ikr_get_density(ikr_handle h, double* rho_dev);

@@ -49,7 +49,7 @@ class SolverOpts(C.Structure):
                 ("precision", C.c_int), ("cg_min_iter", C.c_int), ("cg_max_iter", C.c_int),
                 ("fp32_theta", C.c_double), ("b_norm", C.c_double),
                 ("want_true_residual", C.c_int), ("true_res_cg_tol", C.c_double),
-                ("schur", C.c_int)]
+                ("schur", C.c_int), ("batching", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -80,6 +80,7 @@ SIGNATURES = {
     "ikr_get_setup_info": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_int),
                                      C.POINTER(C.c_double)]),
     "ikr_get_density": (C.c_int, [_VP, _VP]),
+    "ikr_get_orbital_norms": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ikr_apply_hamiltonian": (C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "ikr_apply_hxc_kernel": (C.c_int, [_VP, _VP, _VP]),
     "ikr_apply_chi0": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(C.c_double),
@@ -267,6 +268,13 @@ class ResponseSystem:
                                           cf.ctypes.data_as(C.POINTER(C.c_double)),
                                           C.byref(fermi)))
         return eps, occ, cf, fermi.value
+
+    def orbital_norms(self):
+        """(||Re F_k^-1 Phi_k||_{2,inf}, ||F_k^-1 Phi_k||_{2,inf}) per k."""
+        inf = self.info()
+        re, full = np.zeros(inf.nk), np.zeros(inf.nk)
+        _check(lib().ikr_get_orbital_norms(self.h, _dptr(re), _dptr(full)))
+        return re, full
 
     def setup_info(self):
         inf = self.info()

@@ -51,7 +51,15 @@ void check_opts(const ikr_solver_opts* o) {
   IKR_CHECK(o->cg_min_iter >= 0 && o->cg_max_iter >= 1, IKR_E_ARG, "bad CG iteration limits");
   IKR_CHECK(o->s0 > 0, IKR_E_ARG, "s0 must be positive");
   IKR_CHECK(o->precision == 0 || o->precision == 1, IKR_E_ARG, "precision must be 0 or 1");
+  IKR_CHECK(o->batching == 0 || o->batching == 1, IKR_E_ARG, "batching must be 0 or 1");
 }
+
+// The CG launch mode of one call (restored on exit, also on errors).
+struct GraphMode {
+  System* s;
+  GraphMode(System* sys, const ikr_solver_opts* o) : s(sys) { s->cg_graph = o->batching; }
+  ~GraphMode() { s->cg_graph = 0; }
+};
 
 }  // namespace
 
@@ -160,6 +168,16 @@ ikr_status ikr_get_setup_info(ikr_handle h, double* gaps_host, int* gs_iters,
   });
 }
 
+ikr_status ikr_get_orbital_norms(ikr_handle h, double* re_host, double* full_host) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    if (re_host) std::memcpy(re_host, s->orbnorm_k.data(), s->orbnorm_k.size() * sizeof(double));
+    if (full_host)
+      std::memcpy(full_host, s->orbnorm_full_k.data(), s->orbnorm_full_k.size() * sizeof(double));
+  });
+}
+
 ikr_status ikr_get_density(ikr_handle h, double* rho_dev) {
   return guarded([&] {
     System* s = sys_of(h);
@@ -227,6 +245,7 @@ ikr_status ikr_apply_dielectric(ikr_handle h, const double* v_dev, double* ev_de
   return guarded([&] {
     System* s = sys_of(h);
     check_opts(opts);
+    GraphMode mode(s, opts);
     IKR_CHECK(v_dev && ev_dev && v_dev != ev_dev, IKR_E_ARG, "bad vector pointers");
     IKR_CHECK(common > 0, IKR_E_ARG, "common tolerance factor must be positive");
     IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
@@ -242,6 +261,7 @@ ikr_status ikr_solve_response(ikr_handle h, const double* b_dev, double* drho_de
   return guarded([&] {
     System* s = sys_of(h);
     check_opts(opts);
+    GraphMode mode(s, opts);
     IKR_CHECK(b_dev && drho_dev && b_dev != drho_dev, IKR_E_ARG, "bad vector pointers");
     IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
     ikr_stats local{};
@@ -262,6 +282,7 @@ ikr_status ikr_apply_dielectric_adjoint(ikr_handle h, const double* v_dev, doubl
   return guarded([&] {
     System* s = sys_of(h);
     check_opts(opts);
+    GraphMode mode(s, opts);
     IKR_CHECK(v_dev && ev_dev && v_dev != ev_dev, IKR_E_ARG, "bad vector pointers");
     IKR_CHECK(common > 0, IKR_E_ARG, "common tolerance factor must be positive");
     IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
@@ -277,6 +298,7 @@ ikr_status ikr_solve_response_adjoint(ikr_handle h, const double* g_dev, double*
   return guarded([&] {
     System* s = sys_of(h);
     check_opts(opts);
+    GraphMode mode(s, opts);
     IKR_CHECK(g_dev && lambda_dev && g_dev != lambda_dev, IKR_E_ARG, "bad vector pointers");
     IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
     ikr_stats local{};

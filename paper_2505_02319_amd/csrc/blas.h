@@ -64,6 +64,13 @@ void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
           int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st,
           const int* active = nullptr);
 
+// The first stage of gram alone: partial sums over the super-chunks,
+// part[((t * nsc + sc) * Mmax + m) * BT + b] for rows m < Mk[k]; returns nsc.
+template <typename R>
+int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
+                  const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
+                  int x_stride, cplx<R>* part, hipStream_t st, const int* active = nullptr);
+
 template <typename R>
 void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
             cplx<R>* Y, int y_stride, R a, const UpdTerm<R>& t1,
@@ -103,9 +110,13 @@ void multidot(int n, int nv, const double* V, size_t vstride, const double* w,
 void multiaxpy(int n, int nv, const double* V, size_t vstride, const double* c, double a,
                double* y, hipStream_t st);
 void scale_copy(size_t n, const double* x, double a, double* y, hipStream_t st);
-// full[i] = sum_n |G[n][i]|^2, re[i] = sum_n (Re G[n][i])^2 for n < nv (grid rows)
-void grid_row_norms(size_t ng, int nv, const double2* G, double* full, double* re,
-                    hipStream_t st);
+// full[i] = sum_n |G[n][i]|^2, re[i] = sum_n (Re(phase[n] G[n][i]))^2 for n < nv
+// (grid rows; phase[n] = (cos, sin), null for none)
+void grid_row_norms(size_t ng, int nv, const double2* G, const double2* phase, double* full,
+                    double* re, hipStream_t st);
+// part[n * grid_square_nblocks(ng) + b]: block partial sums of G[n][i]^2 (complex)
+int grid_square_nblocks(size_t ng);
+void grid_square_sums(size_t ng, int nv, const double2* G, double2* part, hipStream_t st);
 template <typename R>
 void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st);
 

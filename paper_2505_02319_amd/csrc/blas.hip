@@ -503,19 +503,50 @@ __global__ __launch_bounds__(NT) void resid_kernel(
   if (tid == 0) part[(size_t)slot * gridDim.x + blockIdx.x] = red[0];
 }
 
-// full[i] = sum_n |G[n][i]|^2 and re[i] = sum_n (Re G[n][i])^2 over the nv rows
+// full[i] = sum_n |G[n][i]|^2 and re[i] = sum_n (Re(ph[n] G[n][i]))^2 over the
+// nv rows (ph[n] = (cos, sin) of a phase; null: no phase)
 __global__ void grid_row_norms_kernel(size_t ng, int nv, const double2* __restrict__ G,
+                                      const double2* __restrict__ ph,
                                       double* __restrict__ full, double* __restrict__ re) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ng) return;
   double f = 0, r = 0;
   for (int n = 0; n < nv; ++n) {
     const double2 v = G[(size_t)n * ng + i];
+    const double x = ph ? v.x * ph[n].x - v.y * ph[n].y : v.x;
     f += v.x * v.x + v.y * v.y;
-    r += v.x * v.x;
+    r += x * x;
   }
   full[i] = f;
   re[i] = r;
+}
+
+// part[n * gridDim.x + b] = sum over block b's points of G[n][i]^2 (complex)
+__global__ __launch_bounds__(NT) void grid_square_sums_kernel(size_t ng, const double2* __restrict__ G,
+                                                             double2* __restrict__ part) {
+  __shared__ double rx[NT / 64], ry[NT / 64];
+  const int n = blockIdx.y;
+  const size_t i = (size_t)blockIdx.x * NT + threadIdx.x;
+  double sx = 0, sy = 0;
+  if (i < ng) {
+    const double2 v = G[(size_t)n * ng + i];
+    sx = v.x * v.x - v.y * v.y;
+    sy = 2 * v.x * v.y;
+  }
+  sx = wave_sum(sx);
+  sy = wave_sum(sy);
+  if ((threadIdx.x & 63) == 0) {
+    rx[threadIdx.x >> 6] = sx;
+    ry[threadIdx.x >> 6] = sy;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < NT / 64; ++w) {
+      rx[0] += rx[w];
+      ry[0] += ry[w];
+    }
+    part[(size_t)n * gridDim.x + blockIdx.x] = make_double2(rx[0], ry[0]);
+  }
 }
 
 // out[slot] = in[slot] over the sphere of the listed slots (precision change)
@@ -581,14 +612,12 @@ size_t gram_part_elems(int ntiles, int nb_max, int Mmax) {
 }
 
 template <typename R>
-void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
-          const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
-          int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st,
-          const int* active) {
-  IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Mk && W && X && part && coef, 8,
+int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
+                  const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
+                  int x_stride, cplx<R>* part, hipStream_t st, const int* active) {
+  IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Mk && W && X && part, 8,
             "gram: null device pointer");
-  IKR_CHECK(Mmax <= cstride, 1, "gram: coefficient stride below the row count");
-  if (tl.n <= 0) return;
+  if (tl.n <= 0) return 0;
   int sc_len;
   const int nsc = nsc_for(nb_max, tl.n, sc_len);
   // rows per pass: 16, 32 or 48 (the smallest that holds Mmax, else 48)
@@ -601,6 +630,19 @@ void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
   else IKR_GRAM(6, 8);
 #undef IKR_GRAM
   IKR_HIP(hipGetLastError());
+  return nsc;
+}
+
+template <typename R>
+void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
+          const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
+          int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st,
+          const int* active) {
+  IKR_CHECK(coef, 8, "gram: null device pointer");
+  IKR_CHECK(Mmax <= cstride, 1, "gram: coefficient stride below the row count");
+  const int nsc = gram_partials<R>(tl, nb, nb_max, Mk, Mmax, W, wk_stride, w_stride, X,
+                                   x_stride, part, st, active);
+  if (nsc <= 0) return;
   const int outs_per_block = NT / 64;
   hipLaunchKernelGGL((gram_reduce_kernel<R>),
                      dim3(tl.n, (Mmax * BT + outs_per_block - 1) / outs_per_block), dim3(NT),
@@ -712,10 +754,19 @@ void multiaxpy(int n, int nv, const double* V, size_t vstride, const double* c, 
   IKR_HIP(hipGetLastError());
 }
 
-void grid_row_norms(size_t ng, int nv, const double2* G, double* full, double* re,
-                    hipStream_t st) {
+void grid_row_norms(size_t ng, int nv, const double2* G, const double2* phase, double* full,
+                    double* re, hipStream_t st) {
   hipLaunchKernelGGL(grid_row_norms_kernel, dim3((ng + 255) / 256), dim3(256), 0, st, ng, nv, G,
-                     full, re);
+                     phase, full, re);
+  IKR_HIP(hipGetLastError());
+}
+
+int grid_square_nblocks(size_t ng) { return (int)((ng + NT - 1) / NT); }
+
+void grid_square_sums(size_t ng, int nv, const double2* G, double2* part, hipStream_t st) {
+  if (nv <= 0) return;
+  hipLaunchKernelGGL(grid_square_sums_kernel, dim3(grid_square_nblocks(ng), nv), dim3(NT), 0, st,
+                     ng, G, part);
   IKR_HIP(hipGetLastError());
 }
 
@@ -778,6 +829,9 @@ void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st) {
   template void gram<R>(const Tiles&, const int*, int, const int*, int, const cplx<R>*,   \
                         size_t, int, const cplx<R>*, int, cplx<R>*, cplx<R>*, int,        \
                         hipStream_t, const int*);                                         \
+  template int gram_partials<R>(const Tiles&, const int*, int, const int*, int,           \
+                                const cplx<R>*, size_t, int, const cplx<R>*, int,         \
+                                cplx<R>*, hipStream_t, const int*);                       \
   template void update<R>(const Tiles&, const int*, int, const int*, cplx<R>*, int, R,    \
                           const UpdTerm<R>&, const UpdTerm<R>&, const cplx<R>*, R*,       \
                           hipStream_t);                                                   \

@@ -40,24 +40,40 @@ void cg_combine(const Slots& sl, int Na, const int* Mq, int Mq_max, const cplx<R
 // place in P), partial <p, Ap> -> dpart[slot * update_nblocks(nb_max) + gb].
 template <typename R>
 void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, size_t wk,
-               int Na, const int* Mq, int Mq_max, const cplx<R>* gam, const cplx<R>* craw,
-               int cstride, cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st);
+               int Na, const int* Mq, int Mq_max, const cplx<R>* gam, int cstride,
+               cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st);
 
-// x += alpha p ; r -= alpha Ap ; z = M^-1 r (into w) ; partials |r|^2, <r, z>.
+// alpha = rz / <p, Ap> per listed slot (from dpart); on a breakdown (<p, Ap>
+// <= 0 or a non-finite alpha) alpha = 0 and the slot leaves the active set.
+// Then x += alpha p ; r -= alpha Ap ; z = M^-1 r (into w) ; partials |r|^2
+// and <r, z> (rpart must not alias dpart).
 template <typename R>
-void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, const R* alpha,
-              const R* pshift, cplx<R>* x, cplx<R>* r, const cplx<R>* p, cplx<R>* w,
-              R* rpart, R* zpart, hipStream_t st);
+void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, const R* dpart,
+              const R* rz, R* alpha, int* active, const R* pshift, cplx<R>* x, cplx<R>* r,
+              const cplx<R>* p, cplx<R>* w, R* rpart, R* zpart, hipStream_t st);
 
 // x = p = 0 on the whole rows of the listed slots (the CG's start).
 template <typename R>
 void cg_zero(const Slots& sl, int nb_max, cplx<R>* x, cplx<R>* p, hipStream_t st);
 
-// alpha = rz / <p, Ap> per listed slot; on a breakdown (<p, Ap> <= 0 or a
-// non-finite alpha) alpha = 0 and the slot leaves the active set.
-template <typename R>
-void cg_alpha(const Slots& sl, int nparts, const R* dpart, const R* rz, R* alpha, int* active,
-              hipStream_t st);
+// Active-set compaction: list[] of active slots (k order), tiles of up to BT
+// of them per k (ctk, cto = offset into list, ctn), cnt[0] = active slots,
+// cnt[1] = tiles; with hist set, hist[2 * it ..] the same, it = step[0]
+// (a device counter, then incremented; entries past hist_len pairs are
+// dropped).
+struct CgCompact {
+  int nk;
+  const int* slot0_k;
+  const int* nslot_k;
+  int* list;
+  int* ctk;
+  int* cto;
+  int* ctn;
+  int* cnt;
+  int* hist;
+  int hist_len;
+  int* step;
+};
 
 // start: rz = <r, z>, beta = 0.  Otherwise: iteration count, |r|^2,
 // convergence (|r|^2 <= tol2 after at least min_iter iterations, or the
@@ -66,11 +82,7 @@ template <typename R>
 void cg_finish(const Slots& sl, int nparts, const R* rpart, const R* zpart,
                const CgScalars<R>& cs, int* active, int start, hipStream_t st);
 
-// Active-set compaction on the device: list[] of active slots (k order),
-// tiles of up to BT of them per k (ctk, cto = offset into list, ctn),
-// cnt[0] = active slots, cnt[1] = tiles; hist[2 * it ..] the same (if not null).
-void cg_compact(int nk, const int* slot0_k, const int* nslot_k, const int* active,
-                int* list, int* ctk, int* cto, int* ctn, int* cnt, int* hist, int it,
-                hipStream_t st);
+// The compaction (one block).
+void cg_compact(const CgCompact& cp, const int* active, hipStream_t st);
 
 }  // namespace ikr

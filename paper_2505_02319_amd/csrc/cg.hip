@@ -66,32 +66,54 @@ __global__ __launch_bounds__(NT) void cg_start_kernel(
   }
 }
 
-// One wavefront per slot; lane m takes rows m, m + 64, ...
+// One block per listed slot.  The slot's raw coefficients (q, then a_m,
+// h_m interleaved) are staged in LDS; the j-sum of c is split over the
+// wavefronts (j = wave, wave + NW, ...) and the partials are added in wave
+// order.  LDS: c [Mr], wave partials [NW][Mq_max].
 template <typename R>
-__global__ __launch_bounds__(64) void cg_combine_kernel(
-    Slots s, int Na, const int* __restrict__ Mq, const cplx<R>* __restrict__ craw, int cstride,
-    const R* __restrict__ shift, const cplx<R>* __restrict__ GT, const cplx<R>* __restrict__ ST,
-    int nbn, R dnl, cplx<R>* __restrict__ gam) {
+__global__ __launch_bounds__(NT) void cg_combine_kernel(
+    Slots s, int Na, const int* __restrict__ Mq, int Mq_max, const cplx<R>* __restrict__ craw,
+    int cstride, const R* __restrict__ shift, const cplx<R>* __restrict__ GT,
+    const cplx<R>* __restrict__ ST, int nbn, R dnl, cplx<R>* __restrict__ gam) {
+  extern __shared__ __align__(16) unsigned char cgc_smem[];
   if (!row_live(s, blockIdx.x)) return;
   const int slot = slot_of(s, blockIdx.x);
   const int k = s.k[slot];
-  const int M = Mq[k];
+  const int M = min(Mq[k], Mq_max);
+  const int Mr = Na + 2 * M;
+  cplx<R>* c = reinterpret_cast<cplx<R>*>(cgc_smem);
+  cplx<R>* wp = c + Na + 2 * Mq_max;
+  const cplx<R>* cr = craw + (size_t)slot * cstride;
+  for (int r = threadIdx.x; r < Mr; r += NT) c[r] = cr[r];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const R e = shift[slot];
-  const cplx<R>* c = craw + (size_t)slot * cstride;
-  cplx<R>* o = gam + (size_t)slot * cstride;
   const cplx<R>* G = GT + (size_t)k * nbn * nbn;
   const cplx<R>* S = ST + (size_t)k * nbn * nbn;
-  for (int r = threadIdx.x; r < Na; r += 64) o[r] = cscale<R>(c[r], dnl);
-  for (int m = threadIdx.x; m < M; m += 64) {
-    const cplx<R> am = c[Na + 2 * m], hm = c[Na + 2 * m + 1];
-    R cx = hm.x - e * am.x, cy = hm.y - e * am.y;
-    for (int j = 0; j < M; ++j) {
+  for (int m = lane; m < M; m += 64) {
+    R cx = 0, cy = 0;
+#pragma unroll 4
+    for (int j = wave; j < M; j += NW) {
       const cplx<R> aj = c[Na + 2 * j];
       const cplx<R> g = G[(size_t)j * nbn + m], sv = S[(size_t)j * nbn + m];
       const R dx = g.x - e * sv.x, dy = g.y - e * sv.y;
-      cx -= dx * aj.x - dy * aj.y;
-      cy -= dx * aj.y + dy * aj.x;
+      cx += dx * aj.x - dy * aj.y;
+      cy += dx * aj.y + dy * aj.x;
     }
+    wp[wave * Mq_max + m] = mk<R>(cx, cy);
+  }
+  __syncthreads();
+  cplx<R>* o = gam + (size_t)slot * cstride;
+  for (int r = threadIdx.x; r < Na; r += NT) o[r] = cscale<R>(c[r], dnl);
+  for (int m = threadIdx.x; m < M; m += NT) {
+    R sx = wp[m].x, sy = wp[m].y;
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      sx += wp[w * Mq_max + m].x;
+      sy += wp[w * Mq_max + m].y;
+    }
+    const cplx<R> am = c[Na + 2 * m], hm = c[Na + 2 * m + 1];
+    const R cx = hm.x - e * am.x - sx, cy = hm.y - e * am.y - sy;
     o[Na + 2 * m] = mk<R>(e * am.x - cx, e * am.y - cy);
     o[Na + 2 * m + 1] = mk<R>(-am.x, -am.y);
   }
@@ -99,13 +121,13 @@ __global__ __launch_bounds__(64) void cg_combine_kernel(
 
 // Block layout as the generic update: NT coefficients g of BPT bands; band
 // groups split a tile when tiles are few; blocks sharing g are 8 apart (one
-// XCD).  LDS: gam [BPT][Mrows], neg a [BPT][Mq_max].
+// XCD).  LDS: gam [BPT][Mrows], -a [BPT][Mq_max].
 template <typename R, int BPT>
 __global__ __launch_bounds__(NT) void cg_update_kernel(
     Tiles tl, const int* __restrict__ nb, int nb_max, const cplx<R>* __restrict__ Wcg,
     size_t wk, int Na, const int* __restrict__ Mq, int Mq_max,
-    const cplx<R>* __restrict__ gam, const cplx<R>* __restrict__ craw, int cstride,
-    cplx<R>* __restrict__ Wv, cplx<R>* __restrict__ P, R* __restrict__ dpart, int nparts) {
+    const cplx<R>* __restrict__ gam, int cstride, cplx<R>* __restrict__ Wv,
+    cplx<R>* __restrict__ P, R* __restrict__ dpart, int nparts) {
   constexpr int G = BT / BPT;
   extern __shared__ __align__(16) unsigned char cgu_smem[];
   const int Mr = Na + 2 * Mq_max;
@@ -128,11 +150,9 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(
     const int b = i / Mr, r = i % Mr;
     cg[i] = (b < nbg && r < Na + 2 * M) ? gam[(size_t)ss[b] * cstride + r] : mk<R>(0, 0);
   }
-  for (int i = tid; i < BPT * Mq_max; i += NT) {
+  for (int i = tid; i < BPT * Mq_max; i += NT) {   // -a_m, held by gam
     const int b = i / Mq_max, m = i % Mq_max;
-    const cplx<R> a = (b < nbg && m < M) ? craw[(size_t)ss[b] * cstride + Na + 2 * m]
-                                         : mk<R>(0, 0);
-    ca[i] = mk<R>(-a.x, -a.y);
+    ca[i] = (b < nbg && m < M) ? gam[(size_t)ss[b] * cstride + Na + 2 * m + 1] : mk<R>(0, 0);
   }
   __syncthreads();
   const int g = gb * NT + tid;
@@ -224,23 +244,49 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(
   }
 }
 
+// alpha = rz / <p, Ap> from the update's partials (every block of a slot
+// forms the same sum in the same order; block 0 records alpha and, on a
+// breakdown, takes the slot out of the active set), then
+// x += alpha p ; r -= alpha Ap ; z = M^-1 r (into w) ; partials |r|^2, <r, z>.
+// A breakdown (<p, Ap> not positive or not finite: the operator is positive
+// definite on range Q, so this only comes from round-off once the residual
+// is at the precision floor) leaves x and r as they are (alpha = 0).
 template <typename R>
 __global__ __launch_bounds__(NT) void cg_step2_kernel(
-    Slots s, const int* __restrict__ nb, const double* __restrict__ kin, int nb_max,
-    const R* __restrict__ alpha, const R* __restrict__ pshift, cplx<R>* __restrict__ x,
+    Slots s, const int* __restrict__ nb, const double* __restrict__ kin, int nb_max, int nup,
+    const R* __restrict__ dpart, const R* __restrict__ rzs, R* __restrict__ alpha,
+    int* __restrict__ active, const R* __restrict__ pshift, cplx<R>* __restrict__ x,
     cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p, cplx<R>* __restrict__ w,
     R* __restrict__ rpart, R* __restrict__ zpart) {
   __shared__ R red[2 * NW];
+  __shared__ R a_sh;
   if (!row_live(s, blockIdx.y)) return;
   const int slot = slot_of(s, blockIdx.y);
+  if (threadIdx.x < 64) {
+    R v = 0;
+    for (int i = threadIdx.x; i < nup; i += 64) v += dpart[(size_t)slot * nup + i];
+    v = wsum(v);
+    if (threadIdx.x == 0) {
+      const R a = rzs[slot] / v;
+      // alpha of a positive definite, kinetic-preconditioned operator stays
+      // far below 1e12; a larger value only comes from round-off in <p, Ap>
+      const bool ok = v > R(0) && a == a && a < R(1e12);
+      a_sh = ok ? a : R(0);
+      if (blockIdx.x == 0) {
+        alpha[slot] = a_sh;
+        if (!ok) active[slot] = 0;
+      }
+    }
+  }
+  __syncthreads();
   const int k = s.k[slot];
   const int g = blockIdx.x * NT + threadIdx.x;
   R rr = 0, rz = 0;
   if (g < nb[k]) {
     const size_t o = (size_t)slot * nb_max + g;
-    const R a = alpha[slot];
+    const R a = a_sh;
     cplx<R> xv = x[o], rv = r[o];
-    if (a != R(0)) {       // alpha = 0: a breakdown, x and r stay as they are
+    if (a != R(0)) {
       const cplx<R> pv = p[o], wv = w[o];
       xv = mk<R>(xv.x + a * pv.x, xv.y + a * pv.y);
       rv = mk<R>(rv.x - a * wv.x, rv.y - a * wv.y);
@@ -272,51 +318,59 @@ __global__ __launch_bounds__(NT) void cg_zero_kernel(Slots s, int nb_max, cplx<R
   p[o] = mk<R>(0, 0);
 }
 
-// One wavefront per listed slot.  A breakdown (<p, Ap> not positive or not
-// finite: the operator is positive definite on range Q, so this only comes
-// from round-off once the residual is at the precision floor) leaves x and r
-// as they are (alpha = 0) and takes the slot out of the active set.
-template <typename R>
-__global__ __launch_bounds__(NT) void cg_alpha_kernel(Slots s, int nparts,
-                                                      const R* __restrict__ dpart,
-                                                      const R* __restrict__ rz,
-                                                      R* __restrict__ alpha,
-                                                      int* __restrict__ active) {
-  const int row = blockIdx.x * NW + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= s.n || !row_live(s, row)) return;
-  const int slot = slot_of(s, row);
-  R v = 0;
-  for (int i = lane; i < nparts; i += 64) v += dpart[(size_t)slot * nparts + i];
-  v = wsum(v);
-  if (lane != 0) return;
-  const R a = rz[slot] / v;
-  // alpha of a positive definite, kinetic-preconditioned operator stays far
-  // below 1e12; a larger value only comes from round-off in <p, Ap>
-  if (v > R(0) && a == a && a < R(1e12)) {
-    alpha[slot] = a;
-  } else {
-    alpha[slot] = R(0);
-    active[slot] = 0;
+// Lists the active slots (k order) and their tiles of up to BT per k, with
+// the whole block; sh holds 3 nk + 1 ints.
+__device__ void compact_block(const CgCompact& cp, const int* active, int* sh) {
+  const int nk = cp.nk, tid = threadIdx.x;
+  int* na = sh;
+  int* lb = sh + nk;
+  int* tb = sh + 2 * nk;
+  for (int k = tid; k < nk; k += blockDim.x) {
+    int c = 0;
+    const int j0 = cp.slot0_k[k], m = cp.nslot_k[k];
+    for (int i = 0; i < m; ++i) c += active[j0 + i] != 0;
+    na[k] = c;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int a = 0, t = 0;
+    for (int k = 0; k < nk; ++k) {
+      lb[k] = a;
+      tb[k] = t;
+      a += na[k];
+      t += (na[k] + BT - 1) / BT;
+    }
+    tb[nk] = t;
+    cp.cnt[0] = a;
+    cp.cnt[1] = t;
+    if (cp.hist) {
+      const int it = cp.step[0];
+      cp.step[0] = it + 1;
+      if (it < cp.hist_len) {
+        cp.hist[2 * it] = a;
+        cp.hist[2 * it + 1] = t;
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < nk; k += blockDim.x) {
+    const int j0 = cp.slot0_k[k], m = cp.nslot_k[k];
+    int pos = lb[k];
+    for (int i = 0; i < m; ++i)
+      if (active[j0 + i]) cp.list[pos++] = j0 + i;
+    for (int t = tb[k]; t < tb[k + 1]; ++t) {
+      const int o = (t - tb[k]) * BT;
+      cp.ctk[t] = k;
+      cp.cto[t] = lb[k] + o;
+      cp.ctn[t] = min(BT, na[k] - o);
+    }
   }
 }
 
+// Per-slot end of an iteration (lane 0 of the slot's wavefront).
 template <typename R>
-__global__ __launch_bounds__(NT) void cg_finish_kernel(Slots s, int nparts,
-                                                       const R* __restrict__ rpart,
-                                                       const R* __restrict__ zpart,
-                                                       CgScalars<R> cs, int* __restrict__ active,
-                                                       int start) {
-  const int row = blockIdx.x * NW + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (row >= s.n || !row_live(s, row)) return;
-  const int slot = slot_of(s, row);
-  R rr = 0, rz = 0;
-  for (int i = lane; i < nparts; i += 64) {
-    rr += rpart[(size_t)slot * nparts + i];
-    rz += zpart[(size_t)slot * nparts + i];
-  }
-  rr = wsum(rr);
-  rz = wsum(rz);
-  if (lane != 0) return;
+__device__ __forceinline__ void finish_slot(int slot, R rr, R rz, const CgScalars<R>& cs,
+                                            int* active, int start) {
   if (start) {
     cs.rz[slot] = rz;
     cs.beta[slot] = 0;
@@ -345,51 +399,30 @@ __global__ __launch_bounds__(NT) void cg_finish_kernel(Slots s, int nparts,
   cs.rz[slot] = rz;
 }
 
-// Thread k (< nk) counts and lists the active slots of k-point k; thread 0
-// turns the per-k counts into list and tile offsets (k order).
-__global__ __launch_bounds__(CT) void cg_compact_kernel(
-    int nk, const int* __restrict__ slot0_k, const int* __restrict__ nslot_k,
-    const int* __restrict__ active, int* __restrict__ list, int* __restrict__ ctk,
-    int* __restrict__ cto, int* __restrict__ ctn, int* __restrict__ cnt,
-    int* __restrict__ hist, int it) {
-  __shared__ int na[CT], lb[CT], tb[CT + 1];
-  const int tid = threadIdx.x;
-  if (tid < nk) {
-    int c = 0;
-    const int j0 = slot0_k[tid], m = nslot_k[tid];
-    for (int i = 0; i < m; ++i) c += active[j0 + i] != 0;
-    na[tid] = c;
+// One wavefront per listed slot.
+template <typename R>
+__global__ __launch_bounds__(NT) void cg_finish_kernel(Slots s, int nparts,
+                                                       const R* __restrict__ rpart,
+                                                       const R* __restrict__ zpart,
+                                                       CgScalars<R> cs, int* __restrict__ active,
+                                                       int start) {
+  const int row = blockIdx.x * NW + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= s.n || !row_live(s, row)) return;
+  const int slot = slot_of(s, row);
+  R rr = 0, rz = 0;
+  for (int i = lane; i < nparts; i += 64) {
+    rr += rpart[(size_t)slot * nparts + i];
+    rz += zpart[(size_t)slot * nparts + i];
   }
-  __syncthreads();
-  if (tid == 0) {
-    int a = 0, t = 0;
-    for (int k = 0; k < nk; ++k) {
-      lb[k] = a;
-      tb[k] = t;
-      a += na[k];
-      t += (na[k] + BT - 1) / BT;
-    }
-    tb[nk] = t;
-    cnt[0] = a;
-    cnt[1] = t;
-    if (hist) {
-      hist[2 * it] = a;
-      hist[2 * it + 1] = t;
-    }
-  }
-  __syncthreads();
-  if (tid < nk) {
-    const int j0 = slot0_k[tid], m = nslot_k[tid];
-    int pos = lb[tid];
-    for (int i = 0; i < m; ++i)
-      if (active[j0 + i]) list[pos++] = j0 + i;
-    for (int t = tb[tid]; t < tb[tid + 1]; ++t) {
-      const int o = (t - tb[tid]) * BT;
-      ctk[t] = tid;
-      cto[t] = lb[tid] + o;
-      ctn[t] = min(BT, na[tid] - o);
-    }
-  }
+  rr = wsum(rr);
+  rz = wsum(rz);
+  if (lane == 0) finish_slot<R>(slot, rr, rz, cs, active, start);
+}
+
+// The compaction alone (one block).
+__global__ __launch_bounds__(CT) void cg_compact_kernel(CgCompact cp, const int* active) {
+  extern __shared__ int cgk_smem[];
+  compact_block(cp, active, cgk_smem);
 }
 
 }  // namespace
@@ -411,15 +444,17 @@ void cg_combine(const Slots& sl, int Na, const int* Mq, int Mq_max, const cplx<R
                 R dnl, cplx<R>* gam, hipStream_t st) {
   if (sl.n <= 0) return;
   IKR_CHECK(Na + 2 * Mq_max <= cstride && Mq_max <= nbn, 1, "cg_combine: row count");
-  hipLaunchKernelGGL((cg_combine_kernel<R>), dim3(sl.n), dim3(64), 0, st, sl, Na, Mq, craw,
-                     cstride, shift, GT, ST, nbn, dnl, gam);
+  const size_t lds = ((size_t)Na + (size_t)(2 + NW) * Mq_max) * sizeof(cplx<R>);
+  IKR_CHECK(lds <= 65536, 1, "cg_combine: too many projection rows");
+  hipLaunchKernelGGL((cg_combine_kernel<R>), dim3(sl.n), dim3(NT), lds, st, sl, Na, Mq, Mq_max,
+                     craw, cstride, shift, GT, ST, nbn, dnl, gam);
   IKR_HIP(hipGetLastError());
 }
 
 template <typename R>
 void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, size_t wk,
-               int Na, const int* Mq, int Mq_max, const cplx<R>* gam, const cplx<R>* craw,
-               int cstride, cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st) {
+               int Na, const int* Mq, int Mq_max, const cplx<R>* gam, int cstride,
+               cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st) {
   if (tl.n <= 0) return;
   IKR_CHECK(Na + 2 * Mq_max <= cstride, 1, "cg_update: row count");
   const int ngb = update_nblocks(nb_max);
@@ -432,7 +467,7 @@ void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, s
   const dim3 grid(ngb * (BT / bpt), tl.n);
 #define IKR_CGU(B)                                                                         \
   hipLaunchKernelGGL((cg_update_kernel<R, B>), grid, dim3(NT), lds, st, tl, nb, nb_max, Wcg, \
-                     wk, Na, Mq, Mq_max, gam, craw, cstride, Wv, P, dpart, ngb)
+                     wk, Na, Mq, Mq_max, gam, cstride, Wv, P, dpart, ngb)
   if (bpt == 16) IKR_CGU(16);
   else if (bpt == 8) IKR_CGU(8);
   else IKR_CGU(4);
@@ -441,12 +476,14 @@ void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, s
 }
 
 template <typename R>
-void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, const R* alpha,
-              const R* pshift, cplx<R>* x, cplx<R>* r, const cplx<R>* p, cplx<R>* w,
-              R* rpart, R* zpart, hipStream_t st) {
+void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, const R* dpart,
+              const R* rz, R* alpha, int* active, const R* pshift, cplx<R>* x, cplx<R>* r,
+              const cplx<R>* p, cplx<R>* w, R* rpart, R* zpart, hipStream_t st) {
   if (sl.n <= 0) return;
+  IKR_CHECK(rpart != dpart, 1, "cg_step2: the residual partials must not overwrite <p, Ap>");
   hipLaunchKernelGGL((cg_step2_kernel<R>), dim3(cg_vec_blocks(nb_max), sl.n), dim3(NT), 0, st,
-                     sl, nb, kin, nb_max, alpha, pshift, x, r, p, w, rpart, zpart);
+                     sl, nb, kin, nb_max, update_nblocks(nb_max), dpart, rz, alpha, active,
+                     pshift, x, r, p, w, rpart, zpart);
   IKR_HIP(hipGetLastError());
 }
 
@@ -458,14 +495,7 @@ void cg_zero(const Slots& sl, int nb_max, cplx<R>* x, cplx<R>* p, hipStream_t st
   IKR_HIP(hipGetLastError());
 }
 
-template <typename R>
-void cg_alpha(const Slots& sl, int nparts, const R* dpart, const R* rz, R* alpha, int* active,
-              hipStream_t st) {
-  if (sl.n <= 0) return;
-  hipLaunchKernelGGL((cg_alpha_kernel<R>), dim3((sl.n + NW - 1) / NW), dim3(NT), 0, st, sl,
-                     nparts, dpart, rz, alpha, active);
-  IKR_HIP(hipGetLastError());
-}
+static size_t compact_lds(const CgCompact& cp) { return (3 * (size_t)cp.nk + 1) * sizeof(int); }
 
 template <typename R>
 void cg_finish(const Slots& sl, int nparts, const R* rpart, const R* zpart,
@@ -476,11 +506,11 @@ void cg_finish(const Slots& sl, int nparts, const R* rpart, const R* zpart,
   IKR_HIP(hipGetLastError());
 }
 
-void cg_compact(int nk, const int* slot0_k, const int* nslot_k, const int* active, int* list,
-                int* ctk, int* cto, int* ctn, int* cnt, int* hist, int it, hipStream_t st) {
-  IKR_CHECK(nk <= CT, 1, "cg_compact: too many k-points for one block");
-  hipLaunchKernelGGL(cg_compact_kernel, dim3(1), dim3(CT), 0, st, nk, slot0_k, nslot_k, active,
-                     list, ctk, cto, ctn, cnt, hist, it);
+void cg_compact(const CgCompact& cp, const int* active, hipStream_t st) {
+  IKR_CHECK(cp.list && cp.cnt && cp.nk > 0, 8, "cg_compact: incomplete arguments");
+  const size_t lds = compact_lds(cp);
+  IKR_CHECK(lds <= 65536, 1, "cg_compact: too many k-points");
+  hipLaunchKernelGGL(cg_compact_kernel, dim3(1), dim3(CT), lds, st, cp, active);
   IKR_HIP(hipGetLastError());
 }
 
@@ -491,11 +521,11 @@ void cg_compact(int nk, const int* slot0_k, const int* nslot_k, const int* activ
                               const R*, const cplx<R>*, const cplx<R>*, int, R, cplx<R>*,      \
                               hipStream_t);                                                    \
   template void cg_update<R>(const Tiles&, const int*, int, const cplx<R>*, size_t, int,       \
-                             const int*, int, const cplx<R>*, const cplx<R>*, int, cplx<R>*,   \
-                             cplx<R>*, R*, hipStream_t);                                       \
+                             const int*, int, const cplx<R>*, int, cplx<R>*, cplx<R>*, R*,     \
+                             hipStream_t);                                                     \
   template void cg_step2<R>(const Slots&, const int*, const double*, int, const R*, const R*,  \
-                            cplx<R>*, cplx<R>*, const cplx<R>*, cplx<R>*, R*, R*, hipStream_t); \
-  template void cg_alpha<R>(const Slots&, int, const R*, const R*, R*, int*, hipStream_t);     \
+                            R*, int*, const R*, cplx<R>*, cplx<R>*, const cplx<R>*, cplx<R>*,  \
+                            R*, R*, hipStream_t);                                              \
   template void cg_zero<R>(const Slots&, int, cplx<R>*, cplx<R>*, hipStream_t);               \
   template void cg_finish<R>(const Slots&, int, const R*, const R*, const CgScalars<R>&, int*,  \
                              int, hipStream_t);

@@ -306,7 +306,8 @@ void ensure_fp32(System& s) {
   convert_array(d.gT.n, d.gT.get(), w.gT.get(), st);
   w.sT.alloc(d.sT.n);
   convert_array(d.sT.n, d.sT.get(), w.sT.get(), st);
-  w.craw.alloc(d.craw.n); w.gam.alloc(d.gam.n); w.zpart.alloc(d.zpart.n);
+  w.craw.alloc(d.craw.n); w.gam.alloc(d.gam.n); w.rpart.alloc(d.rpart.n);
+  w.zpart.alloc(d.zpart.n);
   IKR_HIP(hipStreamSynchronize(st));
 }
 
@@ -339,6 +340,7 @@ static void progress(const char* stage) {
 }
 
 void finish_setup(System& s) {
+  s.graphs.clear();   // captured CG graphs refer to the buffers set up here
   const int nk = s.nk, nbn = s.nbands;
   s.w32.x.alloc(0);   // FP32 copies are rebuilt from this ground state on demand
   s.mcg = s.natoms + 2 * nbn;
@@ -429,6 +431,7 @@ void finish_setup(System& s) {
   w.part.alloc(gram_part_elems(s.tiles.n, s.nb_max, std::max({mrows, s.nbands, s.mcg})));
   w.craw.alloc((size_t)s.J * s.mcg);
   w.gam.alloc((size_t)s.J * s.mcg);
+  w.rpart.alloc((size_t)s.J * vec_nblocks(s.nb_max));
   w.zpart.alloc((size_t)s.J * vec_nblocks(s.nb_max));
   w.rz.alloc(s.J); w.alpha.alloc(s.J); w.beta.alloc(s.J); w.rnorm2.alloc(s.J);
   w.dpart.alloc((size_t)s.J * std::max(update_nblocks(s.nb_max), vec_nblocks(s.nb_max)));
@@ -439,7 +442,7 @@ void finish_setup(System& s) {
   s.d_cto.alloc(s.tiles.n);
   s.d_ctn.alloc(s.tiles.n);
   s.d_iters.alloc(s.J);
-  s.d_counters.alloc(4);
+  s.d_counters.alloc(8);
   s.d_slot0_k.upload(s.slot0_k, st);
   {
     std::vector<int> mo(nk), ma(nk, s.mcg);
@@ -563,22 +566,45 @@ void finish_setup(System& s) {
     s.knorm_bound = 4.0 * PI / (bmin * bmin) + fxmax;
   }
   progress("density and exchange kernel ready");
-  // -- ||Re F_k^-1 Phi_k||_{2,inf} per k (grt strategy)
+  // -- ||Re F_k^-1 Phi_k||_{2,inf} per k (grt strategy, Sec. 3.4.1).  The real
+  // part depends on the phase of each orbital, which the eigensolver leaves
+  // arbitrary: each orbital is taken with the phase that makes sum_r psi^2
+  // real and positive (the real representation when one exists), and the
+  // result is floored at ||F_k^-1 Phi_k||_{2,inf} / sqrt(2).
   {
     s.orbnorm_k.assign(nk, 0.0);
     s.orbnorm_full_k.assign(nk, 0.0);
-    DBuf<double2> grid;
+    DBuf<double2> grid, sq, ph;
     DBuf<double> dfull, dre;
     int maxo = s.nocc_max;
+    const int nsq = grid_square_nblocks(s.ng);
     grid.alloc((size_t)maxo * s.ng);
+    sq.alloc((size_t)maxo * nsq);
+    ph.alloc(maxo);
     dfull.alloc(s.ng);
     dre.alloc(s.ng);
     std::vector<double> hf(s.ng), hr(s.ng);
+    std::vector<double2> hsq((size_t)maxo * nsq), hph(maxo);
     for (int k = 0; k < nk; ++k) {
       const int j0 = s.slot0_k[k], no = s.nocc_k[k];
       launch_plane_grid(s.geom, s.fft, no, s.d_slot_k.get() + j0,
                         s.d_Tphi.get() + (size_t)j0 * s.L.C * s.ncol_max, grid.get(), st);
-      grid_row_norms(s.ng, no, grid.get(), dfull.get(), dre.get(), st);
+      grid_square_sums(s.ng, no, grid.get(), sq.get(), st);
+      IKR_HIP(hipMemcpyAsync(hsq.data(), sq.get(), (size_t)no * nsq * sizeof(double2),
+                             hipMemcpyDeviceToHost, st));
+      IKR_HIP(hipStreamSynchronize(st));
+      for (int n = 0; n < no; ++n) {
+        double x = 0, y = 0;
+        for (int b = 0; b < nsq; ++b) {
+          x += hsq[(size_t)n * nsq + b].x;
+          y += hsq[(size_t)n * nsq + b].y;
+        }
+        const double th = -0.5 * std::atan2(y, x);
+        hph[n] = make_double2(std::cos(th), std::sin(th));
+      }
+      IKR_HIP(hipMemcpyAsync(ph.get(), hph.data(), no * sizeof(double2), hipMemcpyHostToDevice,
+                             st));
+      grid_row_norms(s.ng, no, grid.get(), ph.get(), dfull.get(), dre.get(), st);
       IKR_HIP(hipMemcpyAsync(hf.data(), dfull.get(), s.ng * sizeof(double), hipMemcpyDeviceToHost, st));
       IKR_HIP(hipMemcpyAsync(hr.data(), dre.get(), s.ng * sizeof(double), hipMemcpyDeviceToHost, st));
       IKR_HIP(hipStreamSynchronize(st));
@@ -587,8 +613,8 @@ void finish_setup(System& s) {
         mx = std::max(mx, hr[i]);
         mxf = std::max(mxf, hf[i]);
       }
-      s.orbnorm_k[k] = std::sqrt(mx / s.volume);
       s.orbnorm_full_k[k] = std::sqrt(mxf / s.volume);
+      s.orbnorm_k[k] = std::max(std::sqrt(mx / s.volume), s.orbnorm_full_k[k] / std::sqrt(2.0));
     }
   }
   IKR_HIP(hipStreamSynchronize(st));

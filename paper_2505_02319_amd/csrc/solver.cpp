@@ -190,12 +190,17 @@ template <> const float2* wcg_of<float>(const System& s) { return s.w32.wcg.get(
 // one gram of p~ = z + beta p against [projectors | phi, H phi] provides.
 // The active set is compacted on the device after every iteration; the
 // host reads its size one iteration late (an upper bound, since bands only
-// leave the set), so the stream never drains between iterations.
+// leave the set), so the stream never drains between iterations.  With
+// s.cg_graph set (and no kernel timing), each iteration is one replay of a
+// captured graph whose grids cover the live count rounded up to a power of
+// two; the kernels skip rows past the device count, so a graph stays valid
+// while the set shrinks, and a smaller one is taken once the count halves.
 template <typename R>
 CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>& member,
              const std::vector<double>& tol_slot, int min_iter, int max_iter,
              const int* dMq, int Mq_max, const int* dMcg) {
-  const hipStream_t st = s.stream;
+  const bool use_graph = s.cg_graph != 0 && !KTimer::enabled();
+  const hipStream_t st = use_graph ? s.graphs.get_stream() : s.stream;
   const int J = s.J, nbm = s.nb_max, nbn = s.nbands, Na = s.natoms;
   const R inv_ng = R(1.0 / s.ng);
   const R* vloc = vloc_of<R>(s);
@@ -206,6 +211,14 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   int nmem = 0;
   for (int v : member) nmem += v != 0;
   if (nmem == 0 || max_iter <= 0) return out;
+  if (use_graph) {   // the private stream starts after the work queued so far
+    hipEvent_t j0;
+    IKR_HIP(hipEventCreateWithFlags(&j0, hipEventDisableTiming));
+    (void)hipEventRecord(j0, s.stream);
+    const hipError_t e = hipStreamWaitEvent(st, j0, 0);
+    (void)hipEventDestroy(j0);
+    IKR_HIP(e);
+  }
   if (w.r.get() != rhs)
     IKR_HIP(hipMemcpyAsync(w.r.get(), rhs, (size_t)J * nbm * sizeof(cplx<R>),
                            hipMemcpyDeviceToDevice, st));
@@ -214,18 +227,20 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   IKR_HIP(hipMemcpyAsync(s.d_tol2.get(), tol2.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
   IKR_HIP(hipMemcpyAsync(s.d_active.get(), member.data(), J * sizeof(int), hipMemcpyHostToDevice, st));
   IKR_HIP(hipMemsetAsync(s.d_iters.get(), 0, J * sizeof(int), st));
-  IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, 4 * sizeof(int), st));
-  if (s.d_hist.n < (size_t)2 * (max_iter + 1)) s.d_hist.alloc((size_t)2 * (max_iter + 1));
+  // counters: [1] slots that missed their tolerance, [2] compaction step
+  IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, 8 * sizeof(int), st));
+  if (s.d_hist.n < (size_t)2 * (max_iter + 1)) {
+    s.graphs.clear();   // captured graphs hold the old pointer
+    s.d_hist.alloc((size_t)2 * (max_iter + 1));
+  }
   CgScalars<R> cs{w.rz.get(), w.alpha.get(), w.beta.get(), w.rnorm2.get(), s.d_tol2.get(),
                   s.d_iters.get(), s.d_counters.get(), s.d_counters.get() + 1,
                   min_iter, max_iter};
-  const int nup = update_nblocks(nbm), nvb = vec_nblocks(nbm);
+  const int nvb = vec_nblocks(nbm);
   int* cnt = s.d_cnt.get();
-  auto compact = [&](int it) {
-    cg_compact(s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_active.get(), s.d_list.get(),
-               s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), cnt,
-               it >= 0 ? s.d_hist.get() : nullptr, it, st);
-  };
+  CgCompact cp{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_list.get(), s.d_ctk.get(),
+               s.d_cto.get(), s.d_ctn.get(), cnt, s.d_hist.get(), max_iter + 1,
+               s.d_counters.get() + 2};
   // host bound on the tiles of the member set
   int nct = 0;
   for (int k = 0; k < s.nk; ++k) {
@@ -234,7 +249,11 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
     nct += (c + BT - 1) / BT;
   }
   int nact = nmem;
-  compact(-1);
+  {
+    CgCompact c0 = cp;
+    c0.hist = nullptr;
+    cg_compact(c0, s.d_active.get(), st);
+  }
   // x = p = 0 for the members only: other slots keep what they hold
   cg_zero<R>(Slots{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt}, nbm, w.x.get(),
              w.p.get(), st);
@@ -242,9 +261,51 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
     // z = M^-1 r, rz = <r, z>, beta = 0
     Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
     cg_start<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.pshift.get(), w.r.get(), w.w.get(),
-                w.dpart.get(), w.zpart.get(), st);
-    cg_finish<R>(sl, nvb, w.dpart.get(), w.zpart.get(), cs, s.d_active.get(), 1, st);
+                w.rpart.get(), w.zpart.get(), st);
+    cg_finish<R>(sl, nvb, w.rpart.get(), w.zpart.get(), cs, s.d_active.get(), 1, st);
   }
+  // one CG iteration over grids of na rows and nt tiles
+  auto iteration = [&](int na, int nt) {
+    Slots sl{na, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
+    Tiles ctl{nt, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(), cnt + 1};
+    // p~ = z + beta p ; w~ = (H_loc - e) p~ through the pruned FFT
+    KTimer::begin(kid<R>(K_COL_INV), st);
+    launch_col_inv<R>(s.geom, s.fft, sl, w.p.get(), nbm, w.T1.get(), w.w.get(), w.beta.get(),
+                      w.p.get(), st);
+    KTimer::end(kid<R>(K_COL_INV), st, 0.0);
+    KTimer::begin(kid<R>(K_PLANE_HV), st);
+    launch_plane_hv<R>(s.geom, s.fft, sl, w.T1.get(), w.T2.get(), vloc, 0, st);
+    KTimer::end(kid<R>(K_PLANE_HV), st, 0.0);
+    KTimer::begin(kid<R>(K_COL_FWD), st);
+    launch_col_fwd<R>(s.geom, s.fft, sl, w.T2.get(), w.w.get(), nbm, w.p.get(), w.shift.get(),
+                      inv_ng, st);
+    KTimer::end(kid<R>(K_COL_FWD), st, 0.0);
+    // q, a, h = W_k^H p~ ; update coefficients ; Ap and p = Q p~ ; <p, Ap>
+    KTimer::begin(kid<R>(K_GRAM), st);
+    gram<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm, w.p.get(), nbm, w.part.get(),
+            w.craw.get(), s.mcg, st);
+    KTimer::end(kid<R>(K_GRAM), st, 0.0);
+    cg_combine<R>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
+                  w.sT.get(), nbn, R(s.dnl), w.gam.get(), st);
+    KTimer::begin(kid<R>(K_UPDATE), st);
+    cg_update<R>(ctl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), s.mcg,
+                 w.w.get(), w.p.get(), w.dpart.get(), st);
+    KTimer::end(kid<R>(K_UPDATE), st, 0.0);
+    // alpha ; x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, <r, z>
+    KTimer::begin(kid<R>(K_CG_STEP), st);
+    cg_step2<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.dpart.get(), w.rz.get(), w.alpha.get(),
+                s.d_active.get(), w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(),
+                w.rpart.get(), w.zpart.get(), st);
+    KTimer::end(kid<R>(K_CG_STEP), st, 0.0);
+    // beta, convergence, and the active set of the next iteration
+    cg_finish<R>(sl, nvb, w.rpart.get(), w.zpart.get(), cs, s.d_active.get(), 0, st);
+    cg_compact(cp, s.d_active.get(), st);
+  };
+  auto pow2_cap = [](int n, int cap) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return std::min(p, cap);
+  };
   hipEvent_t ev[2];
   IKR_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
   IKR_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -252,39 +313,15 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   const bool timing = KTimer::enabled();
   try {
     for (int it = 0; it < max_iter; ++it) {
-      Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
-      Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(), cnt + 1};
-      // p~ = z + beta p ; w~ = (H_loc - e) p~ through the pruned FFT
-      KTimer::begin(kid<R>(K_COL_INV), st);
-      launch_col_inv<R>(s.geom, s.fft, sl, w.p.get(), nbm, w.T1.get(), w.w.get(), w.beta.get(),
-                        w.p.get(), st);
-      KTimer::end(kid<R>(K_COL_INV), st, 0.0);
-      KTimer::begin(kid<R>(K_PLANE_HV), st);
-      launch_plane_hv<R>(s.geom, s.fft, sl, w.T1.get(), w.T2.get(), vloc, 0, st);
-      KTimer::end(kid<R>(K_PLANE_HV), st, 0.0);
-      KTimer::begin(kid<R>(K_COL_FWD), st);
-      launch_col_fwd<R>(s.geom, s.fft, sl, w.T2.get(), w.w.get(), nbm, w.p.get(), w.shift.get(),
-                        inv_ng, st);
-      KTimer::end(kid<R>(K_COL_FWD), st, 0.0);
-      // q, a, h = W_k^H p~ ; update coefficients ; Ap and p = Q p~ ; <p, Ap>
-      KTimer::begin(kid<R>(K_GRAM), st);
-      gram<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm, w.p.get(), nbm, w.part.get(),
-              w.craw.get(), s.mcg, st);
-      KTimer::end(kid<R>(K_GRAM), st, 0.0);
-      cg_combine<R>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
-                    w.sT.get(), nbn, R(s.dnl), w.gam.get(), st);
-      KTimer::begin(kid<R>(K_UPDATE), st);
-      cg_update<R>(ctl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), w.craw.get(),
-                   s.mcg, w.w.get(), w.p.get(), w.dpart.get(), st);
-      KTimer::end(kid<R>(K_UPDATE), st, 0.0);
-      cg_alpha<R>(sl, nup, w.dpart.get(), w.rz.get(), w.alpha.get(), s.d_active.get(), st);
-      // x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, <r, z>
-      KTimer::begin(kid<R>(K_CG_STEP), st);
-      cg_step2<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.alpha.get(), w.pshift.get(),
-                  w.x.get(), w.r.get(), w.p.get(), w.w.get(), w.dpart.get(), w.zpart.get(), st);
-      KTimer::end(kid<R>(K_CG_STEP), st, 0.0);
-      cg_finish<R>(sl, nvb, w.dpart.get(), w.zpart.get(), cs, s.d_active.get(), 0, st);
-      compact(it);
+      if (use_graph) {
+        const int na = pow2_cap(nact, J), nt = pow2_cap(nct, s.tiles.n);
+        const CgGraphs::Key key{(long long)sizeof(R), na, nt, (long long)(intptr_t)dMq,
+                                min_iter, max_iter};
+        const hipGraphExec_t ge = s.graphs.get(key, st, [&] { iteration(na, nt); });
+        IKR_HIP(hipGraphLaunch(ge, st));
+      } else {
+        iteration(nact, nct);
+      }
       iters = it + 1;
       IKR_HIP(hipMemcpyAsync(s.h_cnt.p + 2 * (it & 1), cnt, 2 * sizeof(int),
                              hipMemcpyDeviceToHost, st));

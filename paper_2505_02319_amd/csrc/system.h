@@ -1,6 +1,8 @@
 // Host-side state of one response system (opaque ikr_handle).
 #pragma once
 
+#include <array>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -54,9 +56,9 @@ template <typename R> struct CgWork {
   DBuf<R> vloc;
   // fused CG projections: W_k = [projectors | phi_1, H phi_1, phi_2, ...]
   // ([nk][mcg][nb_max]), G^T and S^T ([nk][nbands][nbands]), raw gram
-  // coefficients and update coefficients ([J][mcg]), <r, z> partials
+  // coefficients and update coefficients ([J][mcg]), |r|^2 and <r, z> partials
   DBuf<cplx<R>> wcg, gT, sT, craw, gam;
-  DBuf<R> zpart;
+  DBuf<R> rpart, zpart;
 };
 
 // Page-locked host memory (for asynchronous device-to-host copies).
@@ -69,6 +71,53 @@ template <typename T> struct HBuf {
   void alloc(size_t count) {
     if (p) { (void)hipHostFree(p); p = nullptr; }
     if (count) IKR_HIP(hipHostMalloc((void**)&p, count * sizeof(T), hipHostMallocDefault));
+  }
+};
+
+// Executable HIP graphs of one Sternheimer CG iteration, keyed by precision
+// and grid bounds, and the private stream they are captured and replayed on
+// (a caller's stream may be the legacy default stream, which cannot capture).
+struct CgGraphs {
+  using Key = std::array<long long, 6>;
+  hipStream_t stream = nullptr;
+  std::map<Key, hipGraphExec_t> exec;
+  long long captures = 0;
+  CgGraphs() = default;
+  CgGraphs(const CgGraphs&) = delete;
+  CgGraphs& operator=(const CgGraphs&) = delete;
+  ~CgGraphs() {
+    clear();
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+  void clear() {
+    for (auto& e : exec) (void)hipGraphExecDestroy(e.second);
+    exec.clear();
+  }
+  hipStream_t get_stream() {
+    if (!stream) IKR_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    return stream;
+  }
+  // The cached graph for key, else one captured from record() on st.
+  template <typename F> hipGraphExec_t get(const Key& key, hipStream_t st, F&& record) {
+    const auto it = exec.find(key);
+    if (it != exec.end()) return it->second;
+    hipGraph_t g = nullptr;
+    IKR_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      record();
+    } catch (...) {
+      (void)hipStreamEndCapture(st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    IKR_HIP(hipStreamEndCapture(st, &g));
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    IKR_HIP(e);
+    exec.emplace(key, ge);
+    ++captures;
+    return ge;
   }
 };
 
@@ -140,6 +189,8 @@ struct System {
   std::vector<double> dvloc;       // [natoms][ng] dV_loc/dA_a, internal layout (lazy)
   DBuf<double> d_tol2;
   std::vector<double> knorm_hist;
+  int cg_graph = 0;                // 1: CG iterations replayed from captured graphs
+  CgGraphs graphs;
 
   std::string name;
 };

@@ -152,3 +152,36 @@ def test_extra_band_split_matches_plain_and_dense(name):
     assert rel(to_host(e1), ref) < 1e-9
     assert rel(to_host(e0), ref) < 1e-9
     assert s1["n_ham"] <= s0["n_ham"]
+
+
+@pytest.mark.parametrize("name", ["tiny_k", "tiny_metal", "cfg1"])
+def test_orbital_norms_match_oracle(name):
+    """The orbital terms of the strategies (full and phase-fixed real part)
+    against the oracle's, from the same orbitals."""
+    from oracle.response import orbital_row_norm
+    rs, osys, ogs, perms = gpu_system(name)
+    re, full = rs.orbital_norms()
+    for ik in range(len(osys.bases)):
+        assert abs(full[ik] - orbital_row_norm(osys, ogs, ik, real_part=False)) < 1e-11 * full[ik]
+        assert abs(re[ik] - orbital_row_norm(osys, ogs, ik, real_part=True)) < 1e-11 * full[ik]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_grt_meets_its_tolerance_on_multi_k_cell(precision):
+    """Two k-points with an arbitrary orbital phase at Gamma: the grt solve
+    keeps its guarantee (true residual <= tau) against the dense operator."""
+    from oracle.response import HxcKernel, SumOverStates
+    from paper_2505_02319_amd import default_opts
+    rs, osys, ogs, perms = gpu_system("tiny_k")
+    kern = HxcKernel(osys, ogs.rho, xc=1)
+    chi = SumOverStates(osys, ogs).dense_matrix()
+    kmat = np.zeros((osys.ng, osys.ng))
+    for j in range(osys.ng):
+        e = np.zeros(osys.ng)
+        e[j] = 1
+        kmat[:, j] = kern.apply(e.reshape(osys.n)).ravel()
+    emat = np.eye(osys.ng) - chi @ kmat
+    b = random_field(osys.spec, 2)
+    tau = 1e-9 * np.linalg.norm(b)
+    x, st = rs.solve(to_dev(b), default_opts(strategy="grt", tol=1e-9, precision=precision))
+    assert np.linalg.norm(b.ravel() - emat @ to_host(x).ravel()) <= tau
