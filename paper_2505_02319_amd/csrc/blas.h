@@ -71,6 +71,11 @@ int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int
                   const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
                   int x_stride, cplx<R>* part, hipStream_t st, const int* active = nullptr);
 
+// The second stage: coef[slot * cstride + m] = sum over the nsc super-chunks.
+template <typename R>
+void gram_reduce(const Tiles& tl, const int* Mk, int Mmax, int nsc, const cplx<R>* part,
+                 cplx<R>* coef, int cstride, hipStream_t st, const int* active = nullptr);
+
 template <typename R>
 void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
             cplx<R>* Y, int y_stride, R a, const UpdTerm<R>& t1,

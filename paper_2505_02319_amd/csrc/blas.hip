@@ -16,7 +16,11 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int CH = 64;        // elements per inner chunk of the gram kernel
-constexpr int GRAM_BLOCKS = 2048;   // gram blocks aimed for (8 per CU)
+// gram blocks aimed for: few, long blocks amortise the per-block reduction
+// and partial writes (measured on 48^3 and 48^2 x 96 cells: FP64 fastest
+// near 256, FP32 near 512)
+template <typename R> constexpr int gram_blocks() { return sizeof(R) == 8 ? 256 : 512; }
+constexpr int GRAM_BLOCKS_MAX = 512;
 constexpr int UPD_BLOCKS = 1024;    // update blocks below which tiles are split
 
 // True when some slot of tile t takes part (active == null: all do).
@@ -590,11 +594,11 @@ __global__ void cscale_kernel(size_t n, cplx<R>* __restrict__ x, R a) {
 }  // namespace
 
 // ------------------------------------------------------------ launchers
-// Super-chunks per tile: enough blocks to fill the chip (about
-// GRAM_BLOCKS over all tiles), each at least one chunk long.
-static int nsc_for(int nb_max, int ntiles, int& sc_len) {
+// Super-chunks per tile: about `target` blocks over all tiles, each at
+// least one chunk long.
+static int nsc_for(int nb_max, int ntiles, int target, int& sc_len) {
   const int nch = (nb_max + CH - 1) / CH;
-  const int want = (GRAM_BLOCKS + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
+  const int want = (target + ntiles - 1) / (ntiles > 0 ? ntiles : 1);
   int nsc = std::max(1, std::min(nch, want));
   const int per = (nch + nsc - 1) / nsc;
   sc_len = per * CH;
@@ -606,7 +610,7 @@ size_t gram_part_elems(int ntiles, int nb_max, int Mmax) {
   size_t most = 0;
   for (int t = 1; t <= ntiles; ++t) {
     int sc_len;
-    most = std::max(most, (size_t)t * nsc_for(nb_max, t, sc_len));
+    most = std::max(most, (size_t)t * nsc_for(nb_max, t, GRAM_BLOCKS_MAX, sc_len));
   }
   return most * Mmax * BT;
 }
@@ -619,7 +623,7 @@ int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int
             "gram: null device pointer");
   if (tl.n <= 0) return 0;
   int sc_len;
-  const int nsc = nsc_for(nb_max, tl.n, sc_len);
+  const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(), sc_len);
   // rows per pass: 16, 32 or 48 (the smallest that holds Mmax, else 48)
 #define IKR_GRAM(RB, SBM)                                                              \
   hipLaunchKernelGGL((gram_kernel<R, RB, SBM>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, \
@@ -642,7 +646,15 @@ void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
   IKR_CHECK(Mmax <= cstride, 1, "gram: coefficient stride below the row count");
   const int nsc = gram_partials<R>(tl, nb, nb_max, Mk, Mmax, W, wk_stride, w_stride, X,
                                    x_stride, part, st, active);
-  if (nsc <= 0) return;
+  gram_reduce<R>(tl, Mk, Mmax, nsc, part, coef, cstride, st, active);
+}
+
+template <typename R>
+void gram_reduce(const Tiles& tl, const int* Mk, int Mmax, int nsc, const cplx<R>* part,
+                 cplx<R>* coef, int cstride, hipStream_t st, const int* active) {
+  if (tl.n <= 0 || nsc <= 0) return;
+  IKR_CHECK(coef && part, 8, "gram_reduce: null device pointer");
+  IKR_CHECK(Mmax <= cstride, 1, "gram_reduce: coefficient stride below the row count");
   const int outs_per_block = NT / 64;
   hipLaunchKernelGGL((gram_reduce_kernel<R>),
                      dim3(tl.n, (Mmax * BT + outs_per_block - 1) / outs_per_block), dim3(NT),
@@ -832,6 +844,8 @@ void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st) {
   template int gram_partials<R>(const Tiles&, const int*, int, const int*, int,           \
                                 const cplx<R>*, size_t, int, const cplx<R>*, int,         \
                                 cplx<R>*, hipStream_t, const int*);                       \
+  template void gram_reduce<R>(const Tiles&, const int*, int, int, const cplx<R>*,        \
+                               cplx<R>*, int, hipStream_t, const int*);                   \
   template void update<R>(const Tiles&, const int*, int, const int*, cplx<R>*, int, R,    \
                           const UpdTerm<R>&, const UpdTerm<R>&, const cplx<R>*, R*,       \
                           hipStream_t);                                                   \

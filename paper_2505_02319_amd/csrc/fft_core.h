@@ -177,10 +177,11 @@ template <typename R, bool INV> struct Dft<R, 16, INV> : DftComp<R, 4, 4, INV> {
 // ------------------------------------------------------------ stage driver
 // Lines live in LDS at buf[l * lstride + e * estride], l < nlines <= MAXL.
 // The (line, butterfly) pairs of a stage are dealt out flat over the NT
-// threads (pair i -> line i / NB, butterfly i % NB), so every thread has at
-// most ceil(MAXL * NB / NT) butterflies whatever the line count, and the
-// lanes of a wavefront touch consecutive butterflies (distinct LDS banks
-// along a line, and for strided lines too since the line pitch is odd).
+// threads with the line fastest (pair i -> line i % MAXL, butterfly
+// i / MAXL; lines past nlines idle), so every thread has at most
+// ceil(MAXL * NB / NT) butterflies, neighbouring lanes take the same
+// butterfly of neighbouring lines (an LDS stride of lstride, which is 1 or
+// an odd pitch: no bank conflicts) and read the same twiddle (a broadcast).
 template <typename R, int N, int NT, int MAXL, bool INV, int STAGE, int NS>
 struct Stages {
   __device__ __forceinline__ static void run(cplx<R>* buf, int nlines,
@@ -189,14 +190,14 @@ struct Stages {
     constexpr int RAD = Rad<N>::r[STAGE];
     constexpr int NB = N / RAD;                   // butterflies per line
     constexpr int NV = (MAXL * NB + NT - 1) / NT; // butterflies per thread
-    const int tot = nlines * NB;
+    constexpr int tot = MAXL * NB;
     const int tid = threadIdx.x;
     cplx<R> v[NV][RAD];
 #pragma unroll
     for (int vi = 0; vi < NV; ++vi) {
       const int i = tid + NT * vi;
-      if (i < tot) {
-        const int l = i / NB, b = i % NB;
+      const int l = i % MAXL, b = i / MAXL;
+      if (i < tot && l < nlines) {
         cplx<R>* line = buf + l * lstride;
 #pragma unroll
         for (int r = 0; r < RAD; ++r) {
@@ -215,8 +216,8 @@ struct Stages {
 #pragma unroll
     for (int vi = 0; vi < NV; ++vi) {
       const int i = tid + NT * vi;
-      if (i < tot) {
-        const int l = i / NB, b = i % NB;
+      const int l = i % MAXL, b = i / MAXL;
+      if (i < tot && l < nlines) {
         cplx<R>* line = buf + l * lstride;
         const int d = (b / NS) * NS * RAD + (b % NS);
 #pragma unroll

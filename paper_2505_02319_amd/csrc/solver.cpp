@@ -282,9 +282,10 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
     KTimer::end(kid<R>(K_COL_FWD), st, 0.0);
     // q, a, h = W_k^H p~ ; update coefficients ; Ap and p = Q p~ ; <p, Ap>
     KTimer::begin(kid<R>(K_GRAM), st);
-    gram<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm, w.p.get(), nbm, w.part.get(),
-            w.craw.get(), s.mcg, st);
+    const int nsc = gram_partials<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm,
+                                     w.p.get(), nbm, w.part.get(), st);
     KTimer::end(kid<R>(K_GRAM), st, 0.0);
+    gram_reduce<R>(ctl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
     cg_combine<R>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
                   w.sT.get(), nbn, R(s.dnl), w.gam.get(), st);
     KTimer::begin(kid<R>(K_UPDATE), st);
