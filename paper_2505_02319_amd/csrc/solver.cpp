@@ -632,6 +632,7 @@ void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext, double
   const hipStream_t st = s.stream;
   to_internal(s.L, v_ext, s.d_tmpg.get(), st);
   const double nu = apply_kernel(s, s.d_tmpg.get(), s.d_u.get());
+  IKR_CHECK(std::isfinite(nu), 5, "non-finite input: ||K v|| is not finite");
   s.knorm_hist.push_back(nu);
   if (stt) stt->knorm_last = nu;
   if (nu == 0.0) {
@@ -666,6 +667,7 @@ void apply_dielectric_adjoint_ext(System& s, const double* v_ext, double* ev_ext
                                   ikr_stats* stt) {
   const hipStream_t st = s.stream;
   const double nu = grid_norm(s, v_ext);
+  IKR_CHECK(std::isfinite(nu), 5, "non-finite input: ||v|| is not finite");
   if (stt) stt->knorm_last = nu;
   if (nu == 0.0) {
     IKR_HIP(hipMemcpyAsync(ev_ext, v_ext, s.ng * sizeof(double), hipMemcpyDeviceToDevice, st));
