@@ -81,21 +81,6 @@ void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
             cplx<R>* Y, int y_stride, R a, const UpdTerm<R>& t1,
             const UpdTerm<R>& t2, const cplx<R>* D, R* dpart, hipStream_t st);
 
-template <typename R>
-void cg_step(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
-             const int* active, const R* alpha, const R* pshift, cplx<R>* x, cplx<R>* r,
-             const cplx<R>* p, cplx<R>* w, R* rpart, hipStream_t st,
-             const int* list = nullptr);
-
-template <typename R>
-void precond(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
-             const R* pshift, const cplx<R>* r, cplx<R>* z, hipStream_t st);
-
-template <typename R>
-void cg_scalars(int nslots, int nparts, const R* part, int op, int* active,
-                const CgScalars<R>& cs, int start, hipStream_t st,
-                const int* list = nullptr);
-
 void sum_groups(int n, int ngroups, const double* part, double scale, double* out,
                 hipStream_t st);
 // precision changes: listed slots over their spheres, or whole arrays

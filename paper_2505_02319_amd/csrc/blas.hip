@@ -300,101 +300,6 @@ __global__ __launch_bounds__(NT) void update_kernel(
   }
 }
 
-// x += alpha p ; r -= alpha w ; z = r / (kin + c) ; partial |r|^2
-template <typename R>
-__global__ __launch_bounds__(NT) void cg_step_kernel(
-    const int* __restrict__ slot_k, const int* __restrict__ nb,
-    const double* __restrict__ kin, int nb_max, const int* __restrict__ active,
-    const R* __restrict__ alpha, const R* __restrict__ pshift,
-    cplx<R>* __restrict__ x, cplx<R>* __restrict__ r, const cplx<R>* __restrict__ p,
-    cplx<R>* __restrict__ w, R* __restrict__ rpart, int stride, const int* __restrict__ list) {
-  __shared__ R red[NT];
-  const int slot = list ? list[blockIdx.y] : blockIdx.y, tid = threadIdx.x;
-  if (active && !active[slot]) return;
-  const int k = slot_k[slot];
-  const int g = blockIdx.x * NT + tid;
-  R s = 0;
-  if (g < nb[k]) {
-    const size_t o = (size_t)slot * stride + g;
-    const R a = alpha[slot];
-    cplx<R> xv = x[o], rv = r[o];
-    const cplx<R> pv = p[o], wv = w[o];
-    xv = mk<R>(xv.x + a * pv.x, xv.y + a * pv.y);
-    rv = mk<R>(rv.x - a * wv.x, rv.y - a * wv.y);
-    x[o] = xv;
-    r[o] = rv;
-    const R m = R(1) / (R(kin[(size_t)k * nb_max + g]) + pshift[slot]);
-    w[o] = cscale<R>(rv, m);
-    s = rv.x * rv.x + rv.y * rv.y;
-  }
-  red[tid] = s;
-  __syncthreads();
-  for (int q = NT / 2; q > 0; q >>= 1) {
-    if (tid < q) red[tid] += red[tid + q];
-    __syncthreads();
-  }
-  if (tid == 0) rpart[(size_t)slot * gridDim.x + blockIdx.x] = red[0];
-}
-
-// z = r / (kin + c) (CG start), partial |r|^2
-template <typename R>
-__global__ __launch_bounds__(NT) void precond_kernel(
-    const int* __restrict__ slot_k, const int* __restrict__ nb,
-    const double* __restrict__ kin, int nb_max, const R* __restrict__ pshift,
-    const cplx<R>* __restrict__ r, cplx<R>* __restrict__ z, int stride) {
-  const int slot = blockIdx.y;
-  const int k = slot_k[slot];
-  const int g = blockIdx.x * NT + threadIdx.x;
-  if (g < nb[k]) {
-    const size_t o = (size_t)slot * stride + g;
-    z[o] = cscale<R>(r[o], R(1) / (R(kin[(size_t)k * nb_max + g]) + pshift[slot]));
-  }
-}
-
-// Per-slot scalar logic after a reduction of partials (fixed order).
-// op 0: pAp -> alpha = rz / pAp (0 if pAp == 0)
-// op 1: rnorm2 -> iteration count, convergence flags, active counter
-// op 2: rz_new -> beta = rz_new / rz, rz = rz_new  (start: beta = 0, rz = rz_new)
-// One wavefront per slot: lanes sum partials lane, lane + 64, ... then a
-// fixed shuffle tree.  op 0 also clears the active counter that op 1 of the
-// same iteration increments.
-template <typename R>
-__global__ __launch_bounds__(NT) void cg_scalar_kernel(int nslots, int nparts,
-                                                      const R* __restrict__ part, int op,
-                                                      int* __restrict__ active,
-                                                      CgScalars<R> cs, int start,
-                                                      const int* __restrict__ list) {
-  if (op == 0 && blockIdx.x == 0 && threadIdx.x == 0) *cs.nactive = 0;
-  const int row = blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= nslots) return;
-  const int slot = list ? list[row] : row;
-  if (active && !active[slot]) return;
-  R s = 0;
-  for (int i = lane; i < nparts; i += 64) s += part[(size_t)slot * nparts + i];
-  s = wave_sum(s);
-  if (lane != 0) return;
-  if (op == 0) {
-    cs.alpha[slot] = s != R(0) ? cs.rz[slot] / s : R(0);
-  } else if (op == 1) {
-    const int it = ++cs.iters[slot];
-    cs.rnorm2[slot] = s;
-    const bool conv = it >= cs.min_iter && (double)s <= cs.tol2[slot];
-    if (conv || it >= cs.max_iter) {
-      active[slot] = 0;
-      if (!conv) atomicAdd(cs.noconv, 1);
-    } else {
-      atomicAdd(cs.nactive, 1);
-    }
-  } else if (op == 2) {
-    if (start) {
-      cs.beta[slot] = 0;
-    } else {
-      cs.beta[slot] = cs.rz[slot] != R(0) ? s / cs.rz[slot] : R(0);
-    }
-    cs.rz[slot] = s;
-  }
-}
 
 // out[i] = sum_g part[g][i] (fixed order), optional scale
 __global__ void sum_groups_kernel(int n, int ngroups, const double* __restrict__ part,
@@ -695,35 +600,6 @@ void update(const Tiles& tl, const int* nb, int nb_max, const int* active,
 
 int vec_nblocks(int nb_max) { return (nb_max + NT - 1) / NT; }
 
-template <typename R>
-void cg_step(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
-             const int* active, const R* alpha, const R* pshift, cplx<R>* x, cplx<R>* r,
-             const cplx<R>* p, cplx<R>* w, R* rpart, hipStream_t st, const int* list) {
-  if (nslots <= 0) return;
-  hipLaunchKernelGGL((cg_step_kernel<R>), dim3(vec_nblocks(nb_max), nslots), dim3(NT), 0,
-                     st, slot_k, nb, kin, nb_max, active, alpha, pshift, x, r, p, w, rpart,
-                     nb_max, list);
-  IKR_HIP(hipGetLastError());
-}
-
-template <typename R>
-void precond(int nslots, const int* slot_k, const int* nb, const double* kin, int nb_max,
-             const R* pshift, const cplx<R>* r, cplx<R>* z, hipStream_t st) {
-  hipLaunchKernelGGL((precond_kernel<R>), dim3(vec_nblocks(nb_max), nslots), dim3(NT), 0, st,
-                     slot_k, nb, kin, nb_max, pshift, r, z, nb_max);
-  IKR_HIP(hipGetLastError());
-}
-
-template <typename R>
-void cg_scalars(int nslots, int nparts, const R* part, int op, int* active,
-                const CgScalars<R>& cs, int start, hipStream_t st, const int* list) {
-  if (nslots <= 0) return;
-  const int per_block = NT / 64;
-  hipLaunchKernelGGL((cg_scalar_kernel<R>), dim3((nslots + per_block - 1) / per_block),
-                     dim3(NT), 0, st, nslots, nparts, part, op, active, cs, start, list);
-  IKR_HIP(hipGetLastError());
-}
-
 void sum_groups(int n, int ngroups, const double* part, double scale, double* out,
                 hipStream_t st) {
   hipLaunchKernelGGL(sum_groups_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, ngroups,
@@ -849,13 +725,6 @@ void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st) {
   template void update<R>(const Tiles&, const int*, int, const int*, cplx<R>*, int, R,    \
                           const UpdTerm<R>&, const UpdTerm<R>&, const cplx<R>*, R*,       \
                           hipStream_t);                                                   \
-  template void cg_step<R>(int, const int*, const int*, const double*, int, const int*,   \
-                           const R*, const R*, cplx<R>*, cplx<R>*, const cplx<R>*,        \
-                           cplx<R>*, R*, hipStream_t, const int*);                        \
-  template void precond<R>(int, const int*, const int*, const double*, int, const R*,     \
-                           const cplx<R>*, cplx<R>*, hipStream_t);                        \
-  template void cg_scalars<R>(int, int, const R*, int, int*, const CgScalars<R>&, int,    \
-                              hipStream_t, const int*);                                   \
   template void cscale_vec<R>(size_t, cplx<R>*, R, hipStream_t);
 IKR_INST(double)
 IKR_INST(float)
