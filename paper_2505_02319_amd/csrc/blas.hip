@@ -16,11 +16,16 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int CH = 64;        // elements per inner chunk of the gram kernel
-// gram blocks aimed for: few, long blocks amortise the per-block reduction
-// and partial writes (measured on 48^3 and 48^2 x 96 cells: FP64 fastest
-// near 256, FP32 near 512)
-template <typename R> constexpr int gram_blocks() { return sizeof(R) == 8 ? 256 : 512; }
-constexpr int GRAM_BLOCKS_MAX = 512;
+// gram blocks aimed for over ntiles tiles: few, long blocks amortise the
+// per-block reduction and partial writes (measured on 48^3 and 48^2 x 96
+// cells with up to 16 tiles: FP64 fastest near 256, FP32 near 512); with
+// many tiles every block is long anyway, and about 2048 blocks keep the
+// last round of blocks from leaving most CUs idle (60 x 108^2 cell, 135
+// tiles: 270 blocks were 10% slower than 2160)
+constexpr int GRAM_BLOCKS_MAX = 2048;
+template <typename R> int gram_blocks(int ntiles) {
+  return std::max(sizeof(R) == 8 ? 256 : 512, std::min(GRAM_BLOCKS_MAX, 16 * ntiles));
+}
 constexpr int UPD_BLOCKS = 1024;    // update blocks below which tiles are split
 
 // True when some slot of tile t takes part (active == null: all do).
@@ -515,7 +520,9 @@ size_t gram_part_elems(int ntiles, int nb_max, int Mmax) {
   size_t most = 0;
   for (int t = 1; t <= ntiles; ++t) {
     int sc_len;
-    most = std::max(most, (size_t)t * nsc_for(nb_max, t, GRAM_BLOCKS_MAX, sc_len));
+    most = std::max(most, (size_t)t * nsc_for(nb_max, t, std::max(gram_blocks<double>(t),
+                                                                    gram_blocks<float>(t)),
+                                                 sc_len));
   }
   return most * Mmax * BT;
 }
@@ -528,7 +535,7 @@ int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int
             "gram: null device pointer");
   if (tl.n <= 0) return 0;
   int sc_len;
-  const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(), sc_len);
+  const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(tl.n), sc_len);
   // rows per pass: 16, 32 or 48 (the smallest that holds Mmax, else 48)
 #define IKR_GRAM(RB, SBM)                                                              \
   hipLaunchKernelGGL((gram_kernel<R, RB, SBM>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, \
