@@ -71,7 +71,11 @@ __global__ __launch_bounds__(NT) void gram_kernel(
   cplx<R>* Xs = smem;                     // [BT][LW]
   cplx<R>* Ws = smem + BT * LW;           // [MT][LW]
   cplx<R>* red = smem;                    // [NWAVE][MT * BT], after the chunks
-  const int t = blockIdx.y, sc = blockIdx.x, tid = threadIdx.x;
+  // items (super-chunk, tile) with the tile fastest: the tiles of one k-point
+  // read the same W_k chunk back to back on one XCD
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nsc * tl.n) return;
+  const int t = item % tl.n, sc = item / tl.n, tid = threadIdx.x;
   if (!tile_live(tl, t, active)) return;
   const int k = tl.k[t], nbt = tl.nb[t];
   const int M = Mk[k], n = nb[k];
@@ -538,7 +542,8 @@ int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int
   const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(tl.n), sc_len);
   // rows per pass: 16, 32 or 48 (the smallest that holds Mmax, else 48)
 #define IKR_GRAM(RB, SBM)                                                              \
-  hipLaunchKernelGGL((gram_kernel<R, RB, SBM>), dim3(nsc, tl.n), dim3(NT), 0, st, tl, nb, \
+  hipLaunchKernelGGL((gram_kernel<R, RB, SBM>), dim3(round8(nsc * tl.n)), dim3(NT), 0, st, \
+                     tl, nb,                                                              \
                      Mk, Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part,   \
                      active)
   if (Mmax <= 16) IKR_GRAM(4, 4);

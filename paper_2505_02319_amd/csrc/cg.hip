@@ -119,9 +119,8 @@ __global__ __launch_bounds__(NT) void cg_combine_kernel(
   }
 }
 
-// Block layout as the generic update: NT coefficients g of BPT bands; band
-// groups split a tile when tiles are few; blocks sharing g are 8 apart (one
-// XCD).  LDS: gam [BPT][Mrows], -a [BPT][Mq_max].
+// A block takes NT coefficients g of BPT bands; band groups split a tile
+// when tiles are few.  LDS: gam [BPT][Mrows], -a [BPT][Mq_max].
 template <typename R, int BPT>
 __global__ __launch_bounds__(NT) void cg_update_kernel(
     Tiles tl, const int* __restrict__ nb, int nb_max, const cplx<R>* __restrict__ Wcg,
@@ -135,9 +134,12 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(
   cplx<R>* ca = cg + BPT * Mr;                             // [BPT][Mq_max]
   __shared__ R red[NW * BPT];
   __shared__ int ss[BPT];
-  const int t = blockIdx.y, tid = threadIdx.x;
-  const int grp = (blockIdx.x >> 3) % G;
-  const int gb = (blockIdx.x / (8 * G)) * 8 + (blockIdx.x & 7);
+  // items (g block, tile, band group) with the band group fastest: every
+  // block that reads one chunk of W_k runs back to back on one XCD
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nparts * tl.n * G) return;
+  const int tid = threadIdx.x;
+  const int grp = item % G, t = (item / G) % tl.n, gb = item / (G * tl.n);
   if (tl.dn && t >= *tl.dn) return;
   const int k = tl.k[t];
   const int nbg = min(BPT, tl.nb[t] - grp * BPT);
@@ -464,7 +466,7 @@ void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, s
   if (sizeof(R) == 8 && bpt > 8) bpt = 8;
   const size_t lds = (size_t)bpt * (Na + 3 * Mq_max) * sizeof(cplx<R>);
   IKR_CHECK(lds <= 65536, 1, "cg_update: too many projection rows");
-  const dim3 grid(ngb * (BT / bpt), tl.n);
+  const dim3 grid(round8(ngb * (BT / bpt) * tl.n));
 #define IKR_CGU(B)                                                                         \
   hipLaunchKernelGGL((cg_update_kernel<R, B>), grid, dim3(NT), lds, st, tl, nb, nb_max, Wcg, \
                      wk, Na, Mq, Mq_max, gam, cstride, Wv, P, dpart, ngb)

@@ -82,6 +82,16 @@ struct Slots {
   const int* dn = nullptr;     // device count of live rows (may be null: all n)
 };
 
+// Work item of block `b` of a 1D launch of `nblk` blocks (a multiple of 8):
+// blocks are dealt round-robin to the 8 XCDs, so XCD x is given the
+// contiguous items [x * nblk / 8, (x + 1) * nblk / 8).  Items that share
+// operands are numbered consecutively by the caller and so run back to back
+// on one XCD, where they meet in its L2.
+__device__ __forceinline__ int xcd_item(int b, int nblk) {
+  return (b & 7) * (nblk >> 3) + (b >> 3);
+}
+inline int round8(int n) { return (n + 7) / 8 * 8; }
+
 __device__ __forceinline__ int slot_of(const Slots& s, int row) {
   return s.list ? s.list[row] : row;
 }
