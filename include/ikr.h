@@ -142,8 +142,13 @@ typedef struct {
   double sigma_min;
   double knorm_last;        /* ||K v|| of the last dielectric application */
   double seconds;
-  long long fp64_fallback;  /* FP32 Sternheimer solves that did not converge and
-                               were solved again in FP64 (mixed precision) */
+  long long fp64_fallback;  /* FP32 Sternheimer solves continued in FP64 because their
+                               true residual b - A x was above the tolerance (defect
+                               correction from the FP32 iterate; from zero if the FP32
+                               CG did not converge) */
+  long long fp32_checked;   /* FP32 Sternheimer solves whose true residual was checked
+                               with one FP64 H application (tolerance below 1e-3 ||b||,
+                               or FP32 CG not converged) */
 } ikr_stats;
 
 /* Fill opts with the defaults above (strategy bal, tol 1e-8 relative). */

@@ -59,7 +59,7 @@ class Stats(C.Structure):
                 ("est_res", C.c_double), ("true_res", C.c_double),
                 ("s_final", C.c_double), ("sigma_min", C.c_double),
                 ("knorm_last", C.c_double), ("seconds", C.c_double),
-                ("fp64_fallback", C.c_longlong)]
+                ("fp64_fallback", C.c_longlong), ("fp32_checked", C.c_longlong)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -234,6 +234,7 @@ ikr_status ikr_apply_chi0(ikr_handle h, const double* dv_dev, double* drho_dev, 
       stats->n_ham_fp32 = r.n_ham32;
       stats->cg_unconverged = r.noconv;
       stats->fp64_fallback = r.fallback;
+      stats->fp32_checked = r.checked;
       stats->true_res = -1;
     }
     IKR_CHECK(r.noconv == 0, IKR_E_NOCONV, "a Sternheimer CG hit the iteration cap");

@@ -52,9 +52,15 @@ void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, con
               const R* rz, R* alpha, int* active, const R* pshift, cplx<R>* x, cplx<R>* r,
               const cplx<R>* p, cplx<R>* w, R* rpart, R* zpart, hipStream_t st);
 
-// x = p = 0 on the whole rows of the listed slots (the CG's start).
+// x = p = 0 on the whole rows of the listed slots (the CG's start; x may be
+// null: p only).
 template <typename R>
 void cg_zero(const Slots& sl, int nb_max, cplx<R>* x, cplx<R>* p, hipStream_t st);
+
+// y += a x over the spheres of the listed slots.
+template <typename R>
+void cg_axpy(const Slots& sl, const int* nb, int nb_max, R a, const cplx<R>* x, cplx<R>* y,
+             hipStream_t st);
 
 // Active-set compaction: list[] of active slots (k order), tiles of up to BT
 // of them per k (ctk, cto = offset into list, ctn), cnt[0] = active slots,

@@ -307,17 +307,32 @@ __global__ __launch_bounds__(NT) void cg_step2_kernel(
   }
 }
 
-// x = p = 0 over the whole row of every listed slot.
+// x = p = 0 over the whole row of every listed slot (x may be null).
 template <typename R>
-__global__ __launch_bounds__(NT) void cg_zero_kernel(Slots s, int nb_max, cplx<R>* __restrict__ x,
+__global__ __launch_bounds__(NT) void cg_zero_kernel(Slots s, int nb_max, cplx<R>* x,
                                                      cplx<R>* __restrict__ p) {
   if (!row_live(s, blockIdx.y)) return;
   const int slot = slot_of(s, blockIdx.y);
   const int g = blockIdx.x * NT + threadIdx.x;
   if (g >= nb_max) return;
   const size_t o = (size_t)slot * nb_max + g;
-  x[o] = mk<R>(0, 0);
+  if (x) x[o] = mk<R>(0, 0);
   p[o] = mk<R>(0, 0);
+}
+
+// y += a x over the sphere of every listed slot.
+template <typename R>
+__global__ __launch_bounds__(NT) void cg_axpy_kernel(Slots s, const int* __restrict__ nb,
+                                                     int nb_max, R a,
+                                                     const cplx<R>* __restrict__ x,
+                                                     cplx<R>* __restrict__ y) {
+  if (!row_live(s, blockIdx.y)) return;
+  const int slot = slot_of(s, blockIdx.y);
+  const int g = blockIdx.x * NT + threadIdx.x;
+  if (g >= nb[s.k[slot]]) return;
+  const size_t o = (size_t)slot * nb_max + g;
+  const cplx<R> xv = x[o], yv = y[o];
+  y[o] = mk<R>(yv.x + a * xv.x, yv.y + a * xv.y);
 }
 
 // Lists the active slots (k order) and their tiles of up to BT per k, with
@@ -490,6 +505,15 @@ void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, con
 }
 
 template <typename R>
+void cg_axpy(const Slots& sl, const int* nb, int nb_max, R a, const cplx<R>* x, cplx<R>* y,
+             hipStream_t st) {
+  if (sl.n <= 0) return;
+  hipLaunchKernelGGL((cg_axpy_kernel<R>), dim3(cg_vec_blocks(nb_max), sl.n), dim3(NT), 0, st, sl,
+                     nb, nb_max, a, x, y);
+  IKR_HIP(hipGetLastError());
+}
+
+template <typename R>
 void cg_zero(const Slots& sl, int nb_max, cplx<R>* x, cplx<R>* p, hipStream_t st) {
   if (sl.n <= 0) return;
   hipLaunchKernelGGL((cg_zero_kernel<R>), dim3(cg_vec_blocks(nb_max), sl.n), dim3(NT), 0, st, sl,
@@ -529,6 +553,8 @@ void cg_compact(const CgCompact& cp, const int* active, hipStream_t st) {
                             R*, int*, const R*, cplx<R>*, cplx<R>*, const cplx<R>*, cplx<R>*,  \
                             R*, R*, hipStream_t);                                              \
   template void cg_zero<R>(const Slots&, int, cplx<R>*, cplx<R>*, hipStream_t);               \
+  template void cg_axpy<R>(const Slots&, const int*, int, R, const cplx<R>*, cplx<R>*,         \
+                           hipStream_t);                                                       \
   template void cg_finish<R>(const Slots&, int, const R*, const R*, const CgScalars<R>&, int*,  \
                              int, hipStream_t);
 IKR_INST(double)

@@ -99,6 +99,7 @@ std::vector<double> grad_amplitudes(System& s, const double* drho_ext, const dou
     stt->n_ham_fp64 += r.n_ham64;
     stt->cg_unconverged += r.noconv;
     stt->fp64_fallback += r.fallback;
+    stt->fp32_checked += r.checked;
   };
 
   DBuf<double> drho, lam, u, g1, g2, chil, sv, chis, one;

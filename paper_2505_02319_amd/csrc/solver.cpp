@@ -18,6 +18,8 @@ namespace {
 
 constexpr double DEGEN_TOL = 1e-8;
 constexpr double TOL_FLOOR = 1e-13;   // CG tolerances never below this times ||b_j||
+constexpr double CHECK_REL = 1e-3;    // FP32 results with tau_j below this times ||b_j||
+                                      // get an FP64 true-residual check
 
 double focc_dx(double x) {
   const double e = std::exp(-std::fabs(x));
@@ -195,10 +197,13 @@ template <> const float2* wcg_of<float>(const System& s) { return s.w32.wcg.get(
 // captured graph whose grids cover the live count rounded up to a power of
 // two; the kernels skip rows past the device count, so a graph stays valid
 // while the set shrinks, and a smaller one is taken once the count halves.
+//
+// keep_x: the member rows of w.x hold an initial guess and rhs the initial
+// residual b - A x (defect correction); otherwise the guess is zero and rhs = b.
 template <typename R>
 CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>& member,
              const std::vector<double>& tol_slot, int min_iter, int max_iter,
-             const int* dMq, int Mq_max, const int* dMcg) {
+             const int* dMq, int Mq_max, const int* dMcg, bool keep_x = false) {
   const bool use_graph = s.cg_graph != 0 && !KTimer::enabled();
   const hipStream_t st = use_graph ? s.graphs.get_stream() : s.stream;
   const int J = s.J, nbm = s.nb_max, nbn = s.nbands, Na = s.natoms;
@@ -254,9 +259,10 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
     c0.hist = nullptr;
     cg_compact(c0, s.d_active.get(), st);
   }
-  // x = p = 0 for the members only: other slots keep what they hold
-  cg_zero<R>(Slots{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt}, nbm, w.x.get(),
-             w.p.get(), st);
+  // p = 0 (and x = 0 unless it is the initial guess) for the members only:
+  // other slots keep what they hold
+  cg_zero<R>(Slots{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt}, nbm,
+             keep_x ? nullptr : w.x.get(), w.p.get(), st);
   {
     // z = M^-1 r, rz = <r, z>, beta = 0
     Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
@@ -382,6 +388,49 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   return out;
 }
 
+// w.w := Q (H - e_j) Q v (FP64) for the member slots, with v in the member
+// rows of w.w on entry; w.p := Q v.  It is the front half of a fused CG
+// iteration with p~ = v (p = 0, beta = 0).  On return s.d_list / s.d_cnt
+// hold the compacted member set.
+void apply_sternheimer_op(System& s, const std::vector<int>& member, const int* dMq,
+                          int Mq_max, const int* dMcg) {
+  const hipStream_t st = s.stream;
+  CgWork<double>& w = s.w64;
+  const int J = s.J, nbm = s.nb_max, nbn = s.nbands, Na = s.natoms;
+  const int Mrows = Na + 2 * Mq_max;
+  const size_t wk = (size_t)s.mcg * nbm;
+  int nact = 0, nct = 0;
+  for (int v : member) nact += v != 0;
+  if (nact == 0) return;
+  for (int k = 0; k < s.nk; ++k) {
+    int c = 0;
+    for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) c += member[j] != 0;
+    nct += (c + BT - 1) / BT;
+  }
+  IKR_HIP(hipMemcpyAsync(s.d_active.get(), member.data(), J * sizeof(int), hipMemcpyHostToDevice,
+                         st));
+  int* cnt = s.d_cnt.get();
+  cg_compact(CgCompact{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_list.get(), s.d_ctk.get(),
+                       s.d_cto.get(), s.d_ctn.get(), cnt, nullptr, 0, s.d_counters.get() + 2},
+             s.d_active.get(), st);
+  Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
+  Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(), cnt + 1};
+  IKR_HIP(hipMemsetAsync(w.beta.get(), 0, J * sizeof(double), st));
+  cg_zero<double>(sl, nbm, nullptr, w.p.get(), st);
+  launch_col_inv<double>(s.geom, s.fft, sl, w.p.get(), nbm, w.T1.get(), w.w.get(), w.beta.get(),
+                         w.p.get(), st);
+  launch_plane_hv<double>(s.geom, s.fft, sl, w.T1.get(), w.T2.get(), s.d_vloc.get(), 0, st);
+  launch_col_fwd<double>(s.geom, s.fft, sl, w.T2.get(), w.w.get(), nbm, w.p.get(), w.shift.get(),
+                         1.0 / s.ng, st);
+  const int nsc = gram_partials<double>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, w.wcg.get(), wk,
+                                        nbm, w.p.get(), nbm, w.part.get(), st);
+  gram_reduce<double>(ctl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
+  cg_combine<double>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
+                     w.sT.get(), nbn, s.dnl, w.gam.get(), st);
+  cg_update<double>(ctl, s.d_nb.get(), nbm, w.wcg.get(), wk, Na, dMq, Mq_max, w.gam.get(),
+                    s.mcg, w.w.get(), w.p.get(), w.dpart.get(), st);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- chi0
@@ -471,8 +520,8 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   std::vector<double> tol_slot(tol_in);
   std::vector<int> m64(J, 1), m32(J, 0);
   int n32 = 0;
+  const std::vector<double> bn = slot_norms(s, w.r.get());   // ||b_j||
   {
-    const std::vector<double> bn = slot_norms(s, w.r.get());
     for (int j = 0; j < J; ++j) {
       if (ex && ex->tol_relative) tol_slot[j] *= bn[j];
       tol_slot[j] = std::max(tol_slot[j], TOL_FLOOR * bn[j]);
@@ -497,18 +546,52 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
                                       max_iter, dMq, Mq_max, dMcg);
     convert_slots(n32, dl32.get(), s.d_slot_k.get(), s.d_nb.get(), nbm, s.w32.x.get(), w.x.get(), st);
     res.n_ham32 = o32.n_ham;
-    // FP64 fallback: an FP32 band that broke down, hit the cap or ended
-    // non-finite is solved again in FP64 from its right-hand side (still in
-    // the FP64 r, which the FP32 solve did not touch)
-    if (o32.noconv > 0) {
-      const std::vector<float> rn = download(s.w32.rnorm2.get(), J, st);
+    // FP64 check of the FP32 results: the true residual b - A x of every
+    // FP32 band whose tolerance is below CHECK_REL ||b_j||, and of every band
+    // the FP32 CG did not bring below its tolerance (one FP64 H application
+    // each).  A band that fails continues in FP64 from its FP32 iterate
+    // (defect correction); one that did not converge restarts from zero, as
+    // its iterate may not be finite.
+    const std::vector<float> rn = download(s.w32.rnorm2.get(), J, st);
+    std::vector<int> mc(J, 0), mz(J, 0);
+    int nc = 0, nz = 0;
+    for (int j = 0; j < J; ++j) {
+      if (!m32[j]) continue;
+      const bool conv = (double)rn[j] <= tol_slot[j] * tol_slot[j];
+      if (!conv || tol_slot[j] < CHECK_REL * bn[j]) {
+        mc[j] = 1;
+        ++nc;
+        if (!conv) { mz[j] = 1; ++nz; }
+      }
+    }
+    if (nc > 0) {
+      if (nz > 0) {
+        std::vector<int> lz;
+        for (int j = 0; j < J; ++j)
+          if (mz[j]) lz.push_back(j);
+        DBuf<int> dlz;
+        dlz.upload(lz, st);
+        cg_zero<double>(Slots{nz, s.d_slot_k.get(), nullptr, dlz.get()}, nbm, w.x.get(),
+                        w.p.get(), st);
+        IKR_HIP(hipStreamSynchronize(st));
+      }
+      IKR_HIP(hipMemcpyAsync(w.w.get(), w.x.get(), (size_t)J * nbm * sizeof(double2),
+                             hipMemcpyDeviceToDevice, st));
+      apply_sternheimer_op(s, mc, dMq, Mq_max, dMcg);
+      // r = b - A x on the checked rows (r still holds b there)
+      cg_axpy<double>(Slots{nc, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(),
+                            s.d_cnt.get()},
+                      s.d_nb.get(), nbm, -1.0, w.w.get(), w.r.get(), st);
+      res.n_ham64 += nc;
+      res.checked += nc;
+      const std::vector<double> rt = slot_norms(s, w.r.get());
       std::vector<int> mf(J, 0);
       int nf = 0;
       for (int j = 0; j < J; ++j)
-        if (m32[j] && !((double)rn[j] <= tol_slot[j] * tol_slot[j])) { mf[j] = 1; ++nf; }
+        if (mc[j] && !(rt[j] <= tol_slot[j])) { mf[j] = 1; ++nf; }
       if (nf > 0) {
         const CgOut of = run_cg<double>(s, s.w64, w.r.get(), mf, tol_slot, min_iter, max_iter,
-                                        dMq, Mq_max, dMcg);
+                                        dMq, Mq_max, dMcg, /*keep_x=*/true);
         res.n_ham64 += of.n_ham;
         res.noconv += of.noconv;
         res.fallback += nf;
@@ -652,6 +735,7 @@ void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext, double
     stt->n_ham_fp32 += r.n_ham32;
     stt->cg_unconverged += r.noconv;
     stt->fp64_fallback += r.fallback;
+    stt->fp32_checked += r.checked;
   }
   check_finite_response(s, r, tol);
   to_external(s.L, s.d_drho.get(), ev_ext, -nu, v_ext, 1.0, st);
@@ -687,6 +771,7 @@ void apply_dielectric_adjoint_ext(System& s, const double* v_ext, double* ev_ext
     stt->n_ham_fp32 += r.n_ham32;
     stt->cg_unconverged += r.noconv;
     stt->fp64_fallback += r.fallback;
+    stt->fp32_checked += r.checked;
   }
   check_finite_response(s, r, tol);
   apply_kernel(s, s.d_drho.get(), s.d_u.get());

@@ -209,7 +209,8 @@ double apply_kernel(System& s, const double* v_int, double* kv_int);
 struct Chi0Result {
   long long n_ham = 0, n_ham32 = 0, n_ham64 = 0;
   int noconv = 0;
-  int fallback = 0;     // FP32 bands solved again in FP64
+  int fallback = 0;     // FP32 bands continued in FP64 (true residual above tolerance)
+  int checked = 0;      // FP32 bands whose true residual was checked in FP64
 };
 // Optional inputs/outputs of the chi0 path beyond the density.
 struct Chi0Extra {

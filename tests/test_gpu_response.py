@@ -135,6 +135,34 @@ def test_mixed_precision_solve_matches_dense(tiny_dense, strategy):
     assert rel(x, np.linalg.solve(emat, b.ravel())) < 1e-7
 
 
+@pytest.mark.parametrize("name", ["tiny", "tiny_k"])
+def test_fp32_true_residual_check_and_defect_correction(name):
+    """theta = 1e-9 sends bands to FP32 at tolerances FP32 cannot reach: the
+    FP64 true-residual check catches them, the FP64 continuation from the FP32
+    iterate restores the grt guarantee against the dense operator, and with the
+    default theta the check passes the FP32 results through."""
+    from oracle.response import HxcKernel, SumOverStates
+    from paper_2505_02319_amd import default_opts
+    rs, osys, ogs, perms = gpu_system(name)
+    kern = HxcKernel(osys, ogs.rho, xc=1)
+    chi = SumOverStates(osys, ogs).dense_matrix()
+    kmat = np.zeros((osys.ng, osys.ng))
+    for j in range(osys.ng):
+        e = np.zeros(osys.ng)
+        e[j] = 1
+        kmat[:, j] = kern.apply(e.reshape(osys.n)).ravel()
+    emat = np.eye(osys.ng) - chi @ kmat
+    b = random_field(osys.spec, 2)
+    tau = 1e-10 * np.linalg.norm(b)
+    x, st = rs.solve(to_dev(b), default_opts(strategy="grt", tol=1e-10, precision=1,
+                                             fp32_theta=1e-9))
+    assert st["fp32_checked"] > 0 and st["fp64_fallback"] > 0
+    assert np.linalg.norm(b.ravel() - emat @ to_host(x).ravel()) <= tau
+    x, st = rs.solve(to_dev(b), default_opts(strategy="grt", tol=1e-8, precision=1))
+    assert st["fp32_checked"] > 0 and st["fp64_fallback"] == 0
+    assert np.linalg.norm(b.ravel() - emat @ to_host(x).ravel()) <= 1e-8 * np.linalg.norm(b)
+
+
 @pytest.mark.parametrize("name", ["tiny", "tiny_metal"])
 def test_extra_band_split_matches_plain_and_dense(name):
     """The computed unoccupied bands taken by sum over states (CG on the
