@@ -169,6 +169,128 @@ __global__ __launch_bounds__(NT) void gram_kernel(
   }
 }
 
+// The same partials on the matrix cores: C = conj(W) X as four real 16x16x4
+// MFMA products per 16-row tile (Re += Wr Xr + Wi Xi, Im += Wr Xi - Wi Xr).
+// Wavefront w of the four takes the row tiles w, w + 4, ... over the whole
+// super-chunk, so no reduction across wavefronts is needed (all four stage
+// the chunks).  Chunks of MCH
+// coefficients of W (rows up to 16 * RTMAX) and of the tile's BT bands are
+// staged in LDS ([rows][MCH + 1]); RTM row tiles at most, CHM coefficients
+// per chunk.
+
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+
+template <typename R> struct Mfma;
+template <> struct Mfma<double> {
+  typedef mf64x4 acc;
+  __device__ __forceinline__ static acc mac(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of result value v held by lane l (the column is l % 16)
+  __device__ __forceinline__ static int row(int l, int v) { return 4 * v + (l >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef mf32x4 acc;
+  __device__ __forceinline__ static acc mac(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+template <typename R, int RTM, int CHM>
+__global__ __launch_bounds__(NT) void gram_mfma_kernel(
+    Tiles tl, const int* __restrict__ nb, const int* __restrict__ Mk, int Mmax,
+    const cplx<R>* __restrict__ W, size_t wk_stride, int w_stride,
+    const cplx<R>* __restrict__ X, int x_stride, int nsc, int sc_len,
+    cplx<R>* __restrict__ part, const int* __restrict__ active) {
+  using M = Mfma<R>;
+  constexpr int MCH = CHM, RTMAX = RTM;
+  constexpr int LC = MCH + 1;
+  extern __shared__ __align__(16) unsigned char gm_smem[];
+  cplx<R>* Xs = reinterpret_cast<cplx<R>*>(gm_smem);   // [BT][LC]
+  cplx<R>* Ws = Xs + BT * LC;                          // [16 RT][LC]
+  __shared__ int ss[BT];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nsc * tl.n) return;
+  const int t = item % tl.n, sc = item / tl.n, tid = threadIdx.x;
+  if (!tile_live(tl, t, active)) return;
+  const int k = tl.k[t], nbt = tl.nb[t];
+  const int Mr = Mk[k], n = nb[k];
+  const int RT = (Mr + 15) / 16, nw = blockDim.x >> 6;
+  const int wave = tid >> 6, lane = tid & 63;
+  if (tid < BT) ss[tid] = tid < nbt ? tslot(tl, t, tid) : 0;
+  __syncthreads();
+  const cplx<R>* Wk = W + (size_t)k * wk_stride;
+  const int gbeg = sc * sc_len, gend = min(n, gbeg + sc_len);
+  // row tiles per wavefront (NT / 64 = 4 wavefronts)
+  constexpr int PW = (RTMAX + 3) / 4;
+  typename M::acc cre[PW], cim[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cre[q][v] = cim[q][v] = R(0);
+  // the next chunk is fetched into registers while the current one is used
+  constexpr int XL = BT * MCH / NT, WLM = 16 * RTMAX * MCH / NT;
+  const int wl = 16 * RT * MCH / NT;
+  cplx<R> xr[XL], wr[WLM];
+  auto fetch = [&](int g0) {
+#pragma unroll
+    for (int u = 0; u < XL; ++u) {
+      const int i = tid + u * NT, b = i / MCH, g = g0 + i % MCH;
+      xr[u] = (b < nbt && g < gend) ? X[(size_t)ss[b] * x_stride + g] : mk<R>(0, 0);
+    }
+#pragma unroll
+    for (int u = 0; u < WLM; ++u) {
+      const int i = tid + u * NT, m = i / MCH, g = g0 + i % MCH;
+      if (u < wl) wr[u] = (m < Mr && g < gend) ? Wk[(size_t)m * w_stride + g] : mk<R>(0, 0);
+    }
+  };
+  if (gbeg < gend) fetch(gbeg);
+  for (int g0 = gbeg; g0 < gend; g0 += MCH) {
+#pragma unroll
+    for (int u = 0; u < XL; ++u) {
+      const int i = tid + u * NT;
+      Xs[(i / MCH) * LC + i % MCH] = xr[u];
+    }
+#pragma unroll
+    for (int u = 0; u < WLM; ++u) {
+      const int i = tid + u * NT;
+      if (u < wl) Ws[(i / MCH) * LC + i % MCH] = wr[u];
+    }
+    __syncthreads();
+    if (g0 + MCH < gend) fetch(g0 + MCH);
+#pragma unroll 2
+    for (int ks = 0; ks < MCH / 4; ++ks) {
+      const int e = 4 * ks + (lane >> 4);
+      const cplx<R> xb = Xs[(lane & 15) * LC + e];
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int rt = wave + q * nw;
+        if (rt < RT) {
+          const cplx<R> wa = Ws[(16 * rt + (lane & 15)) * LC + e];
+          cre[q] = M::mac(wa.x, xb.x, cre[q]);
+          cre[q] = M::mac(wa.y, xb.y, cre[q]);
+          cim[q] = M::mac(wa.x, xb.y, cim[q]);
+          cim[q] = M::mac(-wa.y, xb.x, cim[q]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int j = lane & 15;
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    const int rt = wave + q * nw;
+    if (rt >= RT) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = 16 * rt + M::row(lane, v);
+      if (m < Mr) part[(((size_t)t * nsc + sc) * Mmax + m) * BT + j] = mk<R>(cre[q][v], cim[q][v]);
+    }
+  }
+}
+
 // coef[(slot0 + b) * cstride + m] = sum_sc part[...]: one wavefront per
 // output, lanes take super-chunks lane, lane + 64, ... (fixed order), then
 // a fixed shuffle tree.
@@ -540,6 +662,24 @@ int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int
   if (tl.n <= 0) return 0;
   int sc_len;
   const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(tl.n), sc_len);
+  // matrix cores up to 64 rows (faster than the vector kernel on the 48^3
+  // cell; with more rows the accumulators and prefetch registers leave one or
+  // two wavefronts per SIMD, and the vector kernel is faster: 48^2 x 96 cell)
+  if (Mmax <= 64) {
+    const int rt = (Mmax + 15) / 16;
+    const int chm = 64;
+    const size_t lds = (size_t)(BT + 16 * rt) * (chm + 1) * sizeof(cplx<R>);
+    (void)rt;
+    IKR_CHECK(sc_len % chm == 0, 8, "gram: super-chunk not a multiple of the MFMA chunk");
+#define IKR_GRAMM(RTM, CHM)                                                                   \
+  hipLaunchKernelGGL((gram_mfma_kernel<R, RTM, CHM>), dim3(round8(nsc * tl.n)), dim3(NT), lds, \
+                     st, tl, nb, Mk, Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len,   \
+                     part, active)
+    IKR_GRAMM(4, 64);
+#undef IKR_GRAMM
+    IKR_HIP(hipGetLastError());
+    return nsc;
+  }
   // rows per pass: 16, 32 or 48 (the smallest that holds Mmax, else 48)
 #define IKR_GRAM(RB, SBM)                                                              \
   hipLaunchKernelGGL((gram_kernel<R, RB, SBM>), dim3(round8(nsc * tl.n)), dim3(NT), 0, st, \
