@@ -71,6 +71,8 @@ struct CgCompact {
   int nk;
   const int* slot0_k;
   const int* nslot_k;
+  const int* slot_k;   // k of each slot; the slots of k are slot0_k[k] + i, i < nslot_k[k]
+  int J;               // slots
   int* list;
   int* ctk;
   int* cto;
@@ -90,5 +92,11 @@ void cg_finish(const Slots& sl, int nparts, const R* rpart, const R* zpart,
 
 // The compaction (one block).
 void cg_compact(const CgCompact& cp, const int* active, hipStream_t st);
+
+// cg_finish (start = 0) followed by cg_compact; one block does both when
+// the batch has few partials.
+template <typename R>
+void cg_end(const Slots& sl, int nparts, const R* rpart, const R* zpart, const CgScalars<R>& cs,
+            int* active, const CgCompact& cp, hipStream_t st);
 
 }  // namespace ikr

@@ -336,17 +336,46 @@ __global__ __launch_bounds__(NT) void cg_axpy_kernel(Slots s, const int* __restr
 }
 
 // Lists the active slots (k order) and their tiles of up to BT per k, with
-// the whole block; sh holds 3 nk + 1 ints.
+// the whole block: the slots are taken CT at a time in order, a wave ballot
+// and the wave totals place each active slot in the list, LDS atomics count
+// the slots per k, and thread 0 lays out the tiles per k from those counts.
+// sh holds 5 nk + CT / 64 + 2 ints.
 __device__ void compact_block(const CgCompact& cp, const int* active, int* sh) {
-  const int nk = cp.nk, tid = threadIdx.x;
-  int* na = sh;
-  int* lb = sh + nk;
-  int* tb = sh + 2 * nk;
-  for (int k = tid; k < nk; k += blockDim.x) {
-    int c = 0;
-    const int j0 = cp.slot0_k[k], m = cp.nslot_k[k];
-    for (int i = 0; i < m; ++i) c += active[j0 + i] != 0;
-    na[k] = c;
+  constexpr int NWC = CT / 64;
+  const int nk = cp.nk, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int* na = sh;               // [nk] active slots per k
+  int* lb = sh + nk;          // [nk] first list position of k
+  int* tb = sh + 2 * nk;      // [nk + 1] first tile of k
+  int* s0 = sh + 3 * nk + 1;  // [nk] slot0_k
+  int* ns = sh + 4 * nk + 1;  // [nk] nslot_k
+  int* wt = sh + 5 * nk + 1;  // [NWC] wave totals, [NWC] list entries so far
+  for (int k = tid; k < nk; k += CT) {
+    na[k] = 0;
+    s0[k] = cp.slot0_k[k];
+    ns[k] = cp.nslot_k[k];
+  }
+  if (tid == 0) wt[NWC] = 0;
+  for (int j0 = 0; j0 < cp.J; j0 += CT) {
+    const int j = j0 + tid;
+    const bool in = j < cp.J;
+    const int k = in ? cp.slot_k[j] : 0;
+    const int a = in ? active[j] : 0;
+    __syncthreads();   // s0, ns, the counts and wt[NWC] are set
+    const bool f = a != 0 && j - s0[k] < ns[k];
+    const unsigned long long m = __ballot(f);
+    const int below = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wt[wave] = __popcll(m);
+    if (f) atomicAdd(&na[k], 1);
+    __syncthreads();
+    int base = wt[NWC];
+    for (int w = 0; w < wave; ++w) base += wt[w];
+    if (f) cp.list[base + below] = j;
+    __syncthreads();   // every wave has read wt
+    if (tid == 0) {
+      int t = wt[NWC];
+      for (int w = 0; w < NWC; ++w) t += wt[w];
+      wt[NWC] = t;
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -370,11 +399,7 @@ __device__ void compact_block(const CgCompact& cp, const int* active, int* sh) {
     }
   }
   __syncthreads();
-  for (int k = tid; k < nk; k += blockDim.x) {
-    const int j0 = cp.slot0_k[k], m = cp.nslot_k[k];
-    int pos = lb[k];
-    for (int i = 0; i < m; ++i)
-      if (active[j0 + i]) cp.list[pos++] = j0 + i;
+  for (int k = tid; k < nk; k += CT) {
     for (int t = tb[k]; t < tb[k + 1]; ++t) {
       const int o = (t - tb[k]) * BT;
       cp.ctk[t] = k;
@@ -440,6 +465,53 @@ __global__ __launch_bounds__(NT) void cg_finish_kernel(Slots s, int nparts,
 __global__ __launch_bounds__(CT) void cg_compact_kernel(CgCompact cp, const int* active) {
   extern __shared__ int cgk_smem[];
   compact_block(cp, active, cgk_smem);
+}
+
+// The end of an iteration in one block, for batches with few partials: the
+// per-slot sums (FG lanes per listed slot, partials i = sub, sub + FG, ...
+// in order, then the FG lanes pairwise) and finish_slot, then the compaction over the
+// updated flags.  The flags are written and read by this block alone.
+template <typename R>
+__global__ __launch_bounds__(CT) void cg_end_kernel(Slots s, int nparts, const R* __restrict__ rpart,
+                                                    const R* __restrict__ zpart, CgScalars<R> cs,
+                                                    int* active, CgCompact cp) {
+  extern __shared__ int cge_smem[];
+  constexpr int FG = 8, RPP = CT / FG;
+  const int tid = threadIdx.x, sub = tid % FG;
+  const int nrow = s.dn ? min(s.n, *s.dn) : s.n;
+  for (int r0 = 0; r0 < nrow; r0 += RPP) {
+    const int row = r0 + tid / FG;
+    const int slot = row < nrow ? slot_of(s, row) : 0;
+    R rr = 0, rz = 0;
+    if (row < nrow) {
+      const R* rp = rpart + (size_t)slot * nparts;
+      const R* zp = zpart + (size_t)slot * nparts;
+      // UL partials of each kind per lane are loaded before they are added
+      constexpr int UL = 16;
+      for (int i0 = sub; i0 < nparts; i0 += FG * UL) {
+        R a[UL], c[UL];
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+          const int i = i0 + u * FG;
+          a[u] = i < nparts ? rp[i] : R(0);
+          c[u] = i < nparts ? zp[i] : R(0);
+        }
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+          rr += a[u];
+          rz += c[u];
+        }
+      }
+    }
+#pragma unroll
+    for (int o = FG / 2; o > 0; o >>= 1) {
+      rr += __shfl_xor(rr, o, 64);
+      rz += __shfl_xor(rz, o, 64);
+    }
+    if (row < nrow && sub == 0) finish_slot<R>(slot, rr, rz, cs, active, 0);
+  }
+  __syncthreads();
+  compact_block(cp, active, cge_smem);
 }
 
 }  // namespace
@@ -521,7 +593,9 @@ void cg_zero(const Slots& sl, int nb_max, cplx<R>* x, cplx<R>* p, hipStream_t st
   IKR_HIP(hipGetLastError());
 }
 
-static size_t compact_lds(const CgCompact& cp) { return (3 * (size_t)cp.nk + 1) * sizeof(int); }
+static size_t compact_lds(const CgCompact& cp) {
+  return (5 * (size_t)cp.nk + CT / 64 + 2) * sizeof(int);
+}
 
 template <typename R>
 void cg_finish(const Slots& sl, int nparts, const R* rpart, const R* zpart,
@@ -533,10 +607,31 @@ void cg_finish(const Slots& sl, int nparts, const R* rpart, const R* zpart,
 }
 
 void cg_compact(const CgCompact& cp, const int* active, hipStream_t st) {
-  IKR_CHECK(cp.list && cp.cnt && cp.nk > 0, 8, "cg_compact: incomplete arguments");
+  IKR_CHECK(cp.list && cp.cnt && cp.slot_k && cp.nk > 0 && cp.J >= 0, 8,
+            "cg_compact: incomplete arguments");
   const size_t lds = compact_lds(cp);
   IKR_CHECK(lds <= 65536, 1, "cg_compact: too many k-points");
   hipLaunchKernelGGL(cg_compact_kernel, dim3(1), dim3(CT), lds, st, cp, active);
+  IKR_HIP(hipGetLastError());
+}
+
+// Partials per thread up to which the end of an iteration runs as one block.
+constexpr size_t CG_END_FUSED_MAX = 16 * (size_t)CT;
+
+template <typename R>
+void cg_end(const Slots& sl, int nparts, const R* rpart, const R* zpart, const CgScalars<R>& cs,
+            int* active, const CgCompact& cp, hipStream_t st) {
+  if ((size_t)std::max(sl.n, 0) * nparts > CG_END_FUSED_MAX) {
+    cg_finish<R>(sl, nparts, rpart, zpart, cs, active, 0, st);
+    cg_compact(cp, active, st);
+    return;
+  }
+  IKR_CHECK(cp.list && cp.cnt && cp.slot_k && cp.nk > 0 && cp.J >= 0, 8,
+            "cg_end: incomplete arguments");
+  const size_t lds = compact_lds(cp);
+  IKR_CHECK(lds <= 65536, 1, "cg_end: too many k-points");
+  hipLaunchKernelGGL((cg_end_kernel<R>), dim3(1), dim3(CT), lds, st, sl, nparts, rpart, zpart,
+                     cs, active, cp);
   IKR_HIP(hipGetLastError());
 }
 
@@ -556,7 +651,9 @@ void cg_compact(const CgCompact& cp, const int* active, hipStream_t st) {
   template void cg_axpy<R>(const Slots&, const int*, int, R, const cplx<R>*, cplx<R>*,         \
                            hipStream_t);                                                       \
   template void cg_finish<R>(const Slots&, int, const R*, const R*, const CgScalars<R>&, int*,  \
-                             int, hipStream_t);
+                             int, hipStream_t);                                                \
+  template void cg_end<R>(const Slots&, int, const R*, const R*, const CgScalars<R>&, int*,     \
+                          const CgCompact&, hipStream_t);
 IKR_INST(double)
 IKR_INST(float)
 #undef IKR_INST

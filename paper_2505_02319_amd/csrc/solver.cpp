@@ -243,9 +243,9 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
                   min_iter, max_iter};
   const int nvb = vec_nblocks(nbm);
   int* cnt = s.d_cnt.get();
-  CgCompact cp{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_list.get(), s.d_ctk.get(),
-               s.d_cto.get(), s.d_ctn.get(), cnt, s.d_hist.get(), max_iter + 1,
-               s.d_counters.get() + 2};
+  CgCompact cp{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_slot_k.get(), J,
+               s.d_list.get(), s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), cnt,
+               s.d_hist.get(), max_iter + 1, s.d_counters.get() + 2};
   // host bound on the tiles of the member set
   int nct = 0;
   for (int k = 0; k < s.nk; ++k) {
@@ -305,8 +305,7 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
                 w.rpart.get(), w.zpart.get(), st);
     KTimer::end(kid<R>(K_CG_STEP), st, 0.0);
     // beta, convergence, and the active set of the next iteration
-    cg_finish<R>(sl, nvb, w.rpart.get(), w.zpart.get(), cs, s.d_active.get(), 0, st);
-    cg_compact(cp, s.d_active.get(), st);
+    cg_end<R>(sl, nvb, w.rpart.get(), w.zpart.get(), cs, s.d_active.get(), cp, st);
   };
   auto pow2_cap = [](int n, int cap) {
     int p = 1;
@@ -410,8 +409,9 @@ void apply_sternheimer_op(System& s, const std::vector<int>& member, const int* 
   IKR_HIP(hipMemcpyAsync(s.d_active.get(), member.data(), J * sizeof(int), hipMemcpyHostToDevice,
                          st));
   int* cnt = s.d_cnt.get();
-  cg_compact(CgCompact{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_list.get(), s.d_ctk.get(),
-                       s.d_cto.get(), s.d_ctn.get(), cnt, nullptr, 0, s.d_counters.get() + 2},
+  cg_compact(CgCompact{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_slot_k.get(), J,
+                       s.d_list.get(), s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), cnt,
+                       nullptr, 0, s.d_counters.get() + 2},
              s.d_active.get(), st);
   Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
   Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(), cnt + 1};
