@@ -81,6 +81,8 @@ struct CgCompact {
   int* hist;
   int hist_len;
   int* step;
+  int* hcnt = nullptr;   // host-mapped [2][2]: with hist, step s also writes (slots, tiles) to
+                         // hcnt[2 (s & 1)], for the host loop to read without a copy
 };
 
 // start: rz = <r, z>, beta = 0.  Otherwise: iteration count, |r|^2,

@@ -396,6 +396,10 @@ __device__ void compact_block(const CgCompact& cp, const int* active, int* sh) {
         cp.hist[2 * it] = a;
         cp.hist[2 * it + 1] = t;
       }
+      if (cp.hcnt) {
+        cp.hcnt[2 * (it & 1)] = a;
+        cp.hcnt[2 * (it & 1) + 1] = t;
+      }
     }
   }
   __syncthreads();

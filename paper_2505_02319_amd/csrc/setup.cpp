@@ -451,7 +451,9 @@ void finish_setup(System& s) {
     s.d_mcg_all.upload(ma, st);
   }
   s.d_cnt.alloc(2);
-  s.h_cnt.alloc(4);
+  s.h_cnt.alloc(4, hipHostMallocCoherent);
+  for (int i = 0; i < 4; ++i) s.h_cnt.p[i] = -1;
+  IKR_HIP(hipHostGetDevicePointer((void**)&s.d_hcnt, s.h_cnt.p, 0));
   s.d_tol2.alloc(s.J);
   s.d_wa.alloc(s.J);
   s.d_wb.alloc(s.J);

@@ -245,7 +245,7 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   int* cnt = s.d_cnt.get();
   CgCompact cp{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_slot_k.get(), J,
                s.d_list.get(), s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), cnt,
-               s.d_hist.get(), max_iter + 1, s.d_counters.get() + 2};
+               s.d_hist.get(), max_iter + 1, s.d_counters.get() + 2, s.d_hcnt};
   // host bound on the tiles of the member set
   int nct = 0;
   for (int k = 0; k < s.nk; ++k) {
@@ -257,6 +257,7 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   {
     CgCompact c0 = cp;
     c0.hist = nullptr;
+    c0.hcnt = nullptr;
     cg_compact(c0, s.d_active.get(), st);
   }
   // p = 0 (and x = 0 unless it is the initial guess) for the members only:
@@ -317,6 +318,8 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   IKR_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   int iters = 0;
   const bool timing = KTimer::enabled();
+  // no compaction is in flight here (every run ends with a stream sync)
+  for (int i = 0; i < 4; ++i) s.h_cnt.p[i] = -1;
   try {
     for (int it = 0; it < max_iter; ++it) {
       if (use_graph) {
@@ -329,13 +332,20 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
         iteration(nact, nct);
       }
       iters = it + 1;
-      IKR_HIP(hipMemcpyAsync(s.h_cnt.p + 2 * (it & 1), cnt, 2 * sizeof(int),
-                             hipMemcpyDeviceToHost, st));
+      // the compaction of iteration it writes its counts to h_cnt[2 (it & 1)]
       IKR_HIP(hipEventRecord(ev[it & 1], st));
       if (it >= 1) {
         IKR_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
-        nact = s.h_cnt.p[2 * ((it - 1) & 1)];
-        nct = s.h_cnt.p[2 * ((it - 1) & 1) + 1];
+        volatile int* hc = s.h_cnt.p + 2 * ((it - 1) & 1);
+        if (hc[0] < 0 || hc[1] < 0) {
+          // not seen yet: the device counts are as fresh or fresher, so also a bound
+          IKR_HIP(hipMemcpyAsync((void*)hc, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+          IKR_HIP(hipStreamSynchronize(st));
+          ++s.hcnt_copies;
+        }
+        nact = hc[0];
+        nct = hc[1];
+        hc[0] = hc[1] = -1;   // consumed: iteration it + 1 writes this slot next
         if (nact == 0) break;
       }
     }

@@ -68,9 +68,9 @@ template <typename T> struct HBuf {
   HBuf(const HBuf&) = delete;
   HBuf& operator=(const HBuf&) = delete;
   ~HBuf() { if (p) (void)hipHostFree(p); }
-  void alloc(size_t count) {
+  void alloc(size_t count, unsigned flags = hipHostMallocDefault) {
     if (p) { (void)hipHostFree(p); p = nullptr; }
-    if (count) IKR_HIP(hipHostMalloc((void**)&p, count * sizeof(T), hipHostMallocDefault));
+    if (count) IKR_HIP(hipHostMalloc((void**)&p, count * sizeof(T), flags));
   }
 };
 
@@ -185,7 +185,9 @@ struct System {
   int mcg = 0;                     // rows of W_k: natoms + 2 nbands
   DBuf<int> d_mcg_occ, d_mcg_all;  // rows used per k: natoms + 2 nocc_k / + 2 nbands
   DBuf<int> d_cnt, d_hist;         // live counts of the compaction, per-iteration history
-  HBuf<int> h_cnt;                 // [2][2] lagged copies of d_cnt
+  HBuf<int> h_cnt;                 // [2][2] lagged copies of d_cnt (coherent pinned memory)
+  int* d_hcnt = nullptr;           // h_cnt as a device address: the compaction writes it
+  long long hcnt_copies = 0;       // host loop reads that fell back to a copy of d_cnt
   std::vector<double> dvloc;       // [natoms][ng] dV_loc/dA_a, internal layout (lazy)
   DBuf<double> d_tol2;
   std::vector<double> knorm_hist;
