@@ -111,3 +111,26 @@ def test_cfg2_solve_meets_tolerance_mixed_and_fp64(cfg2_system):
     assert stm["n_ham_fp32"] > 0 and st64["n_ham_fp32"] == 0
     assert rel(to_host(xm), to_host(x64)) < 1e-7
     assert rel(to_host(xg), to_host(xm)) < 1e-7
+
+
+def test_cfg3_chi0_properties_two_launch_iteration_end():
+    """chi0 on the 16-atom cell at full size (8 k x 32 bands, spheres of
+    ~74k coefficients): the batch has more per-slot partials than one block
+    of the fused iteration end takes, so every CG iteration ends with the
+    separate finish and compaction launches.  Checked by the properties that
+    hold at any size: symmetry, negativity and charge conservation."""
+    from paper_2505_02319_amd import ResponseSystem
+    spec = config("cfg3")
+    rs = ResponseSystem(spec, ground_state="compute")
+    try:
+        u, v = random_field(spec, 4), random_field(spec, 5)
+        cu, st_u = rs.apply_chi0(to_dev(u), cg_tol=1e-11)
+        cv, st_v = rs.apply_chi0(to_dev(v), cg_tol=1e-11)
+        cu, cv = to_host(cu), to_host(cv)
+        assert st_u["cg_unconverged"] == 0 and st_v["cg_unconverged"] == 0
+        lhs, rhs_ = float(np.sum(u * cv)), float(np.sum(cu * v))
+        assert abs(lhs - rhs_) <= 1e-7 * np.linalg.norm(u) * np.linalg.norm(cv)
+        assert float(np.sum(v * cv)) < 0
+        assert abs(float(np.sum(cv))) <= 1e-9 * float(np.sum(np.abs(cv)))
+    finally:
+        rs.close()
