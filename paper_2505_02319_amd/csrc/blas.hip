@@ -21,10 +21,13 @@ constexpr int CH = 64;        // elements per inner chunk of the gram kernel
 // cells with up to 16 tiles: FP64 fastest near 256, FP32 near 512); with
 // many tiles every block is long anyway, and about 2048 blocks keep the
 // last round of blocks from leaving most CUs idle (60 x 108^2 cell, 135
-// tiles: 270 blocks were 10% slower than 2160)
+// tiles: 270 blocks were 10% slower than 2160).  The matrix-core kernel
+// prefers twice the floor (48^3 cell: FP64 gram 33.5 against 36.4 ms per
+// solve, FP32 11.7 against 12.2).
 constexpr int GRAM_BLOCKS_MAX = 2048;
-template <typename R> int gram_blocks(int ntiles) {
-  return std::max(sizeof(R) == 8 ? 256 : 512, std::min(GRAM_BLOCKS_MAX, 16 * ntiles));
+template <typename R> int gram_blocks(int ntiles, bool mfma) {
+  const int floor = (sizeof(R) == 8 ? 256 : 512) * (mfma ? 2 : 1);
+  return std::max(floor, std::min(GRAM_BLOCKS_MAX, 16 * ntiles));
 }
 constexpr int UPD_BLOCKS = 1024;    // update blocks below which tiles are split
 
@@ -646,8 +649,9 @@ size_t gram_part_elems(int ntiles, int nb_max, int Mmax) {
   size_t most = 0;
   for (int t = 1; t <= ntiles; ++t) {
     int sc_len;
-    most = std::max(most, (size_t)t * nsc_for(nb_max, t, std::max(gram_blocks<double>(t),
-                                                                    gram_blocks<float>(t)),
+    most = std::max(most, (size_t)t * nsc_for(nb_max, t,
+                                                 std::max(gram_blocks<double>(t, true),
+                                                          gram_blocks<float>(t, true)),
                                                  sc_len));
   }
   return most * Mmax * BT;
@@ -661,7 +665,7 @@ int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int
             "gram: null device pointer");
   if (tl.n <= 0) return 0;
   int sc_len;
-  const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(tl.n), sc_len);
+  const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(tl.n, Mmax <= 64), sc_len);
   // matrix cores up to 64 rows (faster than the vector kernel on the 48^3
   // cell; with more rows the accumulators and prefetch registers leave one or
   // two wavefronts per SIMD, and the vector kernel is faster: 48^2 x 96 cell)
