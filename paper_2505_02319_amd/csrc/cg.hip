@@ -264,6 +264,21 @@ __global__ __launch_bounds__(NT) void cg_step2_kernel(
   __shared__ R a_sh;
   if (!row_live(s, blockIdx.y)) return;
   const int slot = slot_of(s, blockIdx.y);
+  const int k = s.k[slot];
+  const int g = blockIdx.x * NT + threadIdx.x;
+  // the vector operands do not depend on alpha: they are requested before
+  // its sum (rows are nb_max long; only g < nb[k] is used)
+  const size_t o = (size_t)slot * nb_max + g;
+  cplx<R> xv = mk<R>(0, 0), rv = xv, pv = xv, wv = xv;
+  R kv = 0;
+  if (g < nb_max) {
+    xv = x[o];
+    rv = r[o];
+    pv = p[o];
+    wv = w[o];
+    kv = R(kin[(size_t)k * nb_max + g]);
+  }
+  const R ps = pshift[slot];
   if (threadIdx.x < 64) {
     R v = 0;
     for (int i = threadIdx.x; i < nup; i += 64) v += dpart[(size_t)slot * nup + i];
@@ -281,21 +296,16 @@ __global__ __launch_bounds__(NT) void cg_step2_kernel(
     }
   }
   __syncthreads();
-  const int k = s.k[slot];
-  const int g = blockIdx.x * NT + threadIdx.x;
   R rr = 0, rz = 0;
   if (g < nb[k]) {
-    const size_t o = (size_t)slot * nb_max + g;
     const R a = a_sh;
-    cplx<R> xv = x[o], rv = r[o];
     if (a != R(0)) {
-      const cplx<R> pv = p[o], wv = w[o];
       xv = mk<R>(xv.x + a * pv.x, xv.y + a * pv.y);
       rv = mk<R>(rv.x - a * wv.x, rv.y - a * wv.y);
       x[o] = xv;
       r[o] = rv;
     }
-    const R m = R(1) / (R(kin[(size_t)k * nb_max + g]) + pshift[slot]);
+    const R m = R(1) / (kv + ps);
     w[o] = cscale<R>(rv, m);
     rr = rv.x * rv.x + rv.y * rv.y;
     rz = m * rr;
