@@ -341,7 +341,6 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
           // not seen yet: the device counts are as fresh or fresher, so also a bound
           IKR_HIP(hipMemcpyAsync((void*)hc, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
           IKR_HIP(hipStreamSynchronize(st));
-          ++s.hcnt_copies;
         }
         nact = hc[0];
         nct = hc[1];

@@ -187,7 +187,6 @@ struct System {
   DBuf<int> d_cnt, d_hist;         // live counts of the compaction, per-iteration history
   HBuf<int> h_cnt;                 // [2][2] lagged copies of d_cnt (coherent pinned memory)
   int* d_hcnt = nullptr;           // h_cnt as a device address: the compaction writes it
-  long long hcnt_copies = 0;       // host loop reads that fell back to a copy of d_cnt
   std::vector<double> dvloc;       // [natoms][ng] dV_loc/dA_a, internal layout (lazy)
   DBuf<double> d_tol2;
   std::vector<double> knorm_hist;
