@@ -169,3 +169,58 @@ def test_gmres_meets_tolerance_on_multi_k_cell(strategy):
     res = inexact_gmres(sys, gs, kern, b, tau, strategy=strategy, m=20)
     true_r = np.linalg.norm(b.ravel() - emat @ res.x.ravel())
     assert true_r <= (tau if strategy != "bal" else 3 * tau)
+
+
+def _lemma_bound(sys, gs, tol, knorm, orb, gap):
+    """The k-point form of Lemma cgtol_E's bound on ||(E - E~) v||:
+    2 w^-1 ||K v|| sum_k w_k sqrt(N_occ,k) ||F_k^-1 Phi_k||_{2,inf}
+    max_n f_nk tau_nk / gap_nk, with w = sqrt(|Omega| / N_g) (eq. fft_ifft).
+    Written from the Lemma, independently of the strategy formulas."""
+    w = np.sqrt(sys.volume / sys.ng)
+    total = 0.0
+    for ik, kb in enumerate(sys.bases):
+        no = gs.nocc_k[ik]
+        f = gs.occ[ik][:no]
+        worst = np.max(f * np.asarray(tol[ik]) / np.asarray(gap[ik]))
+        total += kb.weight * np.sqrt(no) * orb[ik] * worst
+    return 2.0 / w * knorm * total
+
+
+@pytest.mark.parametrize("name", ["tiny_k", "small_metal", "small_rect"])
+def test_strategy_prefactors_against_lemma_bound(name, oracle_case):
+    """Each adaptive strategy spends the error budget of the Lemma exactly as
+    its derivation says (Sec. 3.4 and the k-point supplement):
+      * thm2: the Lemma bound with the real gaps, ||K v|| and the full orbital
+        term equals the common factor c;
+      * bal: with the gap and ||K v|| set to 1 and the orbital term at its
+        lower bound sqrt(N_occ,k / |Omega|) (Prop. FinvPhi_bound) the bound is c
+        (N_occ,k N_mp replaced by the total N_occ splits c over k in
+        proportion to N_occ,k);
+      * grt: with the gap set to 1 and the real-part orbital term, the bound is
+        c sum_k sqrt(N_occ,k / N_occ) (the extra sqrt(N_mp) the paper drops).
+    A dropped w_k, a per-k instead of a total N_occ, or a missing factor 2
+    moves these by N_mp, N_mp or 2."""
+    from oracle.gmres import strategy_prefactors
+    from oracle.response import orbital_row_norm
+    sys, gs = oracle_case(name)
+    nk = len(sys.bases)
+    c, knorm, bnorm = 1e-3, 3.7, 1.0
+    ones = [np.ones(gs.nocc_k[ik]) for ik in range(nk)]
+    lower = [np.sqrt(gs.nocc_k[ik] / sys.volume) for ik in range(nk)]
+    re = [orbital_row_norm(sys, gs, ik) for ik in range(nk)]
+    full = [orbital_row_norm(sys, gs, ik, real_part=False) for ik in range(nk)]
+    for ik in range(nk):   # Prop. FinvPhi_bound brackets the orbital terms
+        assert lower[ik] <= full[ik] * (1 + 1e-12)
+        assert full[ik] <= np.sqrt(sys.ng / sys.volume) * (1 + 1e-12)
+    tol = [p * c for p in strategy_prefactors(sys, gs, "bal", knorm, bnorm)]
+    assert abs(_lemma_bound(sys, gs, tol, 1.0, lower, ones) - c) < 1e-13 * c
+    tol = [p * c for p in strategy_prefactors(sys, gs, "grt", knorm, bnorm, orb_norms=re)]
+    nocc = sum(gs.nocc_k)
+    want = c * sum(np.sqrt(gs.nocc_k[ik] / nocc) for ik in range(nk))
+    assert abs(_lemma_bound(sys, gs, tol, knorm, re, ones) - want) < 1e-13 * want
+    gap = []
+    for ik in range(nk):
+        e, no = gs.eps[ik], gs.nocc_k[ik]
+        gap.append(e[no] - e[:no])
+    tol = [p * c for p in strategy_prefactors(sys, gs, "thm2", knorm, bnorm, orb_full=full)]
+    assert abs(_lemma_bound(sys, gs, tol, knorm, full, gap) - c) < 1e-13 * c

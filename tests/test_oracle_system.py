@@ -110,3 +110,39 @@ def test_kgrid_folding_and_weights():
     kf = np.array([k for k, _ in sys.kpoints])
     assert len(kf) == 8 and set(np.unique(kf)) == {-0.5, 0.0}
     assert abs(sum(w for _, w in sys.kpoints) - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("name,ik", [("cfg1", 0), ("small_k", 0), ("small_k", 1)])
+def test_projector_real_space_centre(name, ik):
+    """F_k^-1 p_a on the grid is the L2-normalised Gaussian
+    (pi s^2)^{-3/4} exp(-|r - R_a - L|^2 / 2 s^2) centred on the atom, summed over
+    lattice vectors L with the Bloch phase e^{-ik.(r - L)} left by F^-1 (the
+    e^{ik.r} factor is dropped, Sec. 4.1.1): the Poisson summation of the
+    projector's Fourier coefficients.  A sign slip in e^{-iq.R} moves every
+    projector to -R, which this fails (the atoms here are not centrosymmetric
+    about the origin: R = (a/4, a/4, a/4) and -R differ by a/2 per axis)."""
+    spec = config(name).with_(ecut=30.0, fft=(40, 40, 40))
+    sys = System(spec)
+    kb = sys.bases[ik]
+    p = sys.projectors(ik)
+    grid = sys.to_grid(ik, p)                      # [natoms, N1, N2, N3]
+    s = spec.sigma_proj
+    r = np.stack(np.meshgrid(*[np.arange(m) / m * a for m, a in zip(sys.n, sys.a)],
+                             indexing="ij"), -1)
+    shifts = [np.array([i, j, k]) * sys.a for i in (-1, 0, 1)
+              for j in (-1, 0, 1) for k in (-1, 0, 1)]
+    for a in range(spec.natoms):
+        ref = np.zeros(sys.n, complex)
+        for L in shifts:
+            d = r - sys.pos[a] - L
+            ref += (np.pi * s * s) ** -0.75 * np.exp(-np.sum(d * d, -1) / (2 * s * s)) * \
+                np.exp(-1j * ((r - L) @ kb.kcart))
+        assert np.max(np.abs(grid[a] - ref)) < 1e-6 * np.max(np.abs(ref))
+        # the mirrored centre is far off: the test is not blind to the sign
+        mir = np.zeros(sys.n, complex)
+        for L in shifts:
+            d = r + sys.pos[a] - L
+            mir += (np.pi * s * s) ** -0.75 * np.exp(-np.sum(d * d, -1) / (2 * s * s)) * \
+                np.exp(-1j * ((r - L) @ kb.kcart))
+        if np.linalg.norm(sys.pos[a]) > 0:
+            assert np.max(np.abs(grid[a] - mir)) > 0.1 * np.max(np.abs(ref))
