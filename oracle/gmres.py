@@ -26,7 +26,7 @@ import numpy as np
 
 from .groundstate import GroundState
 from .response import (Chi0Stats, HxcKernel, apply_dielectric,
-                       apply_dielectric_adjoint, orbital_row_norm)
+                       apply_dielectric_adjoint, kerker_apply, orbital_row_norm)
 from .system import System
 
 STRATEGIES = ("agr", "bal", "grt", "D10", "D100", "D10n", "thm2")
@@ -97,9 +97,16 @@ def inexact_gmres(sys: System, gs: GroundState, kern: HxcKernel,
                   b: np.ndarray, tau: float, strategy: str = "bal",
                   m: int = 20, s0: float = 1.0,
                   x0: Optional[np.ndarray] = None,
-                  max_restarts: int = 50, adjoint: bool = False) -> GmresResult:
+                  max_restarts: int = 50, adjoint: bool = False,
+                  kerker_alpha: Optional[float] = None) -> GmresResult:
     """Algorithm 1 (inexact GMRES(m)) applied to E drho = b, or with
-    ``adjoint`` to E^T lambda = b (same algorithm, transposed operator)."""
+    ``adjoint`` to E^T lambda = b (same algorithm, transposed operator).
+
+    ``kerker_alpha``: Algorithm 1 on the Kerker-preconditioned system
+    T E drho = T b (eq. precond_dyson, T of eq. kerker).  Since ||T|| = 1
+    (Lemma kerker_properties) the strategies' tolerances keep Theorem 2's
+    guarantee, now for the preconditioned residual ||T (b - E x)||; tau stays
+    the caller's (absolute) tolerance."""
     shape = sys.n
     bvec = b.reshape(-1).astype(float)
     bnorm = float(np.linalg.norm(bvec))
@@ -120,16 +127,21 @@ def inexact_gmres(sys: System, gs: GroundState, kern: HxcKernel,
             return [p * common for p in pref]
         op = apply_dielectric_adjoint if adjoint else apply_dielectric
         ev, _ = op(sys, gs, kern, v.reshape(shape), tol_fn, stats=stats)
+        if kerker_alpha is not None:
+            ev = kerker_apply(sys, ev, kerker_alpha)
         return ev.reshape(-1)
+
+    rhs_vec = bvec if kerker_alpha is None else \
+        kerker_apply(sys, bvec, kerker_alpha).reshape(-1)
 
     restarts = 0
     while True:
         # line 1: r0 = b - E~(0) x0 with ||(E - E~(0)) x0|| <= tau/3
         if np.linalg.norm(x0v) == 0.0:
-            r0 = bvec.copy()
+            r0 = rhs_vec.copy()
         else:
             common = tau / 3.0 if adaptive else tau
-            r0 = bvec - eop(x0v, common)
+            r0 = rhs_vec - eop(x0v, common)
         beta = float(np.linalg.norm(r0))
         V = [r0 / beta]
         H = np.zeros((m + 1, m))

@@ -108,6 +108,7 @@ class SumOverStates:
         self.sys = sys
         self.gs = gs
         self.full = []
+        self.vecs = []
         T = sys.spec.temperature
         for ik, kb in enumerate(sys.bases):
             e, v = scipy.linalg.eigh(sys.dense_h(ik))
@@ -122,6 +123,7 @@ class SumOverStates:
                 fp = np.zeros(len(e))
             psi = sys.to_grid(ik, v.T).reshape(len(e), -1)   # [nall, ng]
             self.full.append((e, f, fp, psi))
+            self.vecs.append(np.ascontiguousarray(v.T))
 
     def _dd(self, e, f, fp, n, m):
         de = e[n] - e[m]
@@ -133,7 +135,10 @@ class SumOverStates:
             return float(f_fd_deriv(x) / T)
         return (f[n] - f[m]) / de
 
-    def apply(self, dv: np.ndarray) -> np.ndarray:
+    def apply(self, dv: np.ndarray, dv_nl=None) -> np.ndarray:
+        """chi0 dV; ``dv_nl(ik, coeffs)`` optionally adds a non-multiplicative
+        part of the perturbation (its action on coefficient rows), whose
+        matrix elements join M_mn."""
         sys = self.sys
         dvf = dv.reshape(-1)
         out = np.zeros(sys.ng)
@@ -144,6 +149,9 @@ class SumOverStates:
             nocc = self.gs.nocc_k[ik]
             # M_mn for n occupied, all m
             mm = (psi.conj() * dvf) @ psi[:nocc].T * (sys.volume / sys.ng)  # [nall, nocc]
+            if dv_nl is not None:
+                vecs = self.vecs[ik]                                   # [nall, nb]
+                mm = mm + vecs.conj() @ dv_nl(ik, vecs[:nocc]).T
             acc = np.zeros(sys.ng, complex)
             for n in range(nocc):
                 for m in range(len(e)):
@@ -283,11 +291,15 @@ class Chi0Stats:
 
 def chi0_sternheimer(sys: System, gs: GroundState, dv: np.ndarray,
                      tol, stats: Optional[Chi0Stats] = None,
-                     maxiter: int = 1000) -> np.ndarray:
+                     maxiter: int = 1000, dv_nl=None) -> np.ndarray:
     """chi0 dV through the Sternheimer route (eq. kchi0, eq. delta_phi_P,
     eq. sternheimer_equation, eq. delta_f).
 
     ``tol`` is a scalar or a per-(k, n) list of absolute CG tolerances.
+    ``dv_nl(ik, phi)`` optionally adds a non-multiplicative part of the
+    perturbation: it returns (dV_nl phi_n) as coefficients [nocc, nb], added
+    to t_n = F(dV psi_n) (the Sternheimer right-hand side and every matrix
+    element of the perturbation only use dV phi_n).
     """
     dvg = dv.reshape(sys.n)
     rho1 = np.zeros(sys.n)
@@ -300,6 +312,8 @@ def chi0_sternheimer(sys: System, gs: GroundState, dv: np.ndarray,
         fp = gs.focc_deriv[ik]
         psi = sys.to_grid(ik, phi)                          # [nocc, grid]
         t = sys.to_sphere(ik, dvg * psi)                    # F(dV psi_n)
+        if dv_nl is not None:
+            t = t + dv_nl(ik, phi)
         iters = []
         for n in range(nocc):
             tn = t[n]
@@ -388,3 +402,24 @@ def orbital_row_norm(sys: System, gs: GroundState, ik: int, real_part: bool = Tr
     theta = -0.5 * np.angle(np.sum(psi * psi, axis=1))
     re = (psi * np.exp(1j * theta)[:, None]).real
     return max(float(np.sqrt(np.max(np.sum(re ** 2, axis=0)))), full / np.sqrt(2.0))
+
+
+# ---------------------------------------------------------------- Kerker
+def kerker_symbol(sys: System, alpha: float) -> np.ndarray:
+    """D(G) = |G|^2 / (|G|^2 + alpha^2) on the FFT cube (numpy FFT order,
+    |G| from the signed index) -- the Fourier representation of the
+    discretised Kerker preconditioner (Sec. 3.3)."""
+    g1, g2, g3 = sys.cube_g()
+    gg = g1 ** 2 + g2 ** 2 + g3 ** 2
+    return gg / (gg + alpha * alpha)
+
+
+def kerker_apply(sys: System, v: np.ndarray, alpha: float) -> np.ndarray:
+    """T v with T of eq. (kerker): (1 - 1 1^T / N_g) W^-1 D W + 1 1^T / N_g,
+    the charge-conserving form of W^-1 D W (W the unitary grid DFT of
+    eq. fft_ifft; W^-1 D W is applied through numpy's FFT pair, whose
+    normalisations cancel).  Real grid vectors in, real out."""
+    vg = v.reshape(sys.n)
+    t = sfft.ifftn(kerker_symbol(sys, alpha) * sfft.fftn(vg, workers=WORKERS),
+                   workers=WORKERS).real
+    return t - t.mean() + vg.mean()
