@@ -209,6 +209,20 @@ ikr_status ikr_get_density(ikr_handle h, double* rho_dev);
 ikr_status ikr_apply_hamiltonian(ikr_handle h, int k, int nvec,
                                  const double* x_dev, double* y_dev);
 
+/* y = H_k x exactly as ikr_apply_hamiltonian, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the call allocates nothing.  Its
+ * work space (2 nvec * C * ncol_max complex column buffers plus small tables)
+ * is a fixed 64 MiB device array per GPU, held until the process ends;
+ * nvec beyond what fits returns IKR_E_ARG with the limit in the message
+ * (e.g. about 40 vectors on a 48^3 grid).  All calls on one GPU share that
+ * array, so calls that overlap in time on one GPU race.  On a stream under
+ * graph capture the call only enqueues its work; otherwise it returns after
+ * completion.  Same arguments, layout and ownership as
+ * ikr_apply_hamiltonian. */
+ikr_status ikr_apply_hamiltonian_noalloc(ikr_handle h, int k, int nvec,
+                                         const double* x_dev, double* y_dev);
+
 /* kv = K v, K = K_H + K_xc at the ground-state density (device grid
  * vectors).  Hartree 4 pi/|G|^2 with G = 0 -> 0 (paper Sec. 3.4.3). */
 ikr_status ikr_apply_hxc_kernel(ikr_handle h, const double* v_dev,

@@ -82,6 +82,7 @@ SIGNATURES = {
     "ikr_get_density": (C.c_int, [_VP, _VP]),
     "ikr_get_orbital_norms": (C.c_int, [_VP, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "ikr_apply_hamiltonian": (C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP]),
+    "ikr_apply_hamiltonian_noalloc": (C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "ikr_apply_hxc_kernel": (C.c_int, [_VP, _VP, _VP]),
     "ikr_apply_chi0": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(C.c_double),
                                  C.POINTER(Stats)]),
@@ -304,6 +305,19 @@ class ResponseSystem:
         assert x.shape[-1] == inf.nb_max
         y = torch.empty_like(x)
         _check(lib().ikr_apply_hamiltonian(self.h, k, x.shape[0], _ptr(x), _ptr(y)))
+        return y
+
+    def apply_hamiltonian_noalloc(self, k: int, x, y=None):
+        """y = H_k x through the entry point that allocates no device memory
+        (y may be given, so that the call itself allocates nothing)."""
+        torch = self._torch
+        inf = self.info()
+        assert x.dtype == torch.complex128 and x.is_cuda and x.is_contiguous()
+        assert x.shape[-1] == inf.nb_max
+        if y is None:
+            y = torch.empty_like(x)
+        assert y.shape == x.shape and y.dtype == x.dtype and y.is_contiguous()
+        _check(lib().ikr_apply_hamiltonian_noalloc(self.h, k, x.shape[0], _ptr(x), _ptr(y)))
         return y
 
     def apply_kernel(self, v):

@@ -200,6 +200,18 @@ ikr_status ikr_apply_hamiltonian(ikr_handle h, int k, int nvec, const double* x_
   });
 }
 
+ikr_status ikr_apply_hamiltonian_noalloc(ikr_handle h, int k, int nvec, const double* x_dev,
+                                         double* y_dev) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(k >= 0 && k < s->nk, IKR_E_ARG, "k-point index out of range");
+    IKR_CHECK(nvec >= 1 && nvec <= 4096, IKR_E_ARG, "nvec out of range");
+    IKR_CHECK(x_dev && y_dev && x_dev != y_dev, IKR_E_ARG, "bad vector pointers");
+    ikr::apply_hamiltonian_noalloc(*s, k, nvec, reinterpret_cast<const double2*>(x_dev),
+                                   reinterpret_cast<double2*>(y_dev));
+  });
+}
+
 ikr_status ikr_apply_hxc_kernel(ikr_handle h, const double* v_dev, double* kv_dev) {
   return guarded([&] {
     System* s = sys_of(h);

@@ -51,6 +51,8 @@ System* create_system(const ikr_system_desc* d, hipStream_t st) {
   std::unique_ptr<System> sp(new System());
   System& s = *sp;
   s.stream = st;
+  IKR_HIP(hipGetDevice(&s.device));
+  init_scratch(s.device);
   for (int i = 0; i < 3; ++i) {
     s.a[i] = d->lattice[i];
     s.b[i] = 2.0 * PI / d->lattice[i];

@@ -101,37 +101,67 @@ double small_ls(const std::vector<double>& H, int ld, int i, double beta,
 }  // namespace
 
 // ---------------------------------------------------------------- H psi
+size_t HamWork::bytes(const System& s, int nvec) {
+  const int ntiles = (nvec + BT - 1) / BT;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t tcol = (size_t)nvec * s.L.C * s.ncol_max * sizeof(double2);
+  return al(nvec * sizeof(int)) + 3 * al(ntiles * sizeof(int)) + 2 * al(tcol) +
+         al((size_t)nvec * MAXM * sizeof(double2)) +
+         al(gram_part_elems(ntiles, s.nb_max, std::max(s.natoms, 1)) * sizeof(double2));
+}
+
+void HamWork::carve(const System& s, int nvec, unsigned char* base) {
+  const int ntiles = (nvec + BT - 1) / BT;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t tcol = (size_t)nvec * s.L.C * s.ncol_max * sizeof(double2);
+  unsigned char* p = base;
+  sk = reinterpret_cast<int*>(p); p += al(nvec * sizeof(int));
+  tk = reinterpret_cast<int*>(p); p += al(ntiles * sizeof(int));
+  ts = reinterpret_cast<int*>(p); p += al(ntiles * sizeof(int));
+  tn = reinterpret_cast<int*>(p); p += al(ntiles * sizeof(int));
+  T1 = reinterpret_cast<double2*>(p); p += al(tcol);
+  T2 = reinterpret_cast<double2*>(p); p += al(tcol);
+  coef = reinterpret_cast<double2*>(p); p += al((size_t)nvec * MAXM * sizeof(double2));
+  part = reinterpret_cast<double2*>(p);
+}
+
+// y = H_k x with the work space in w (tables filled by the caller or here).
+void apply_hamiltonian_ws(System& s, int k, int nvec, const double2* x, double2* y,
+                          const HamWork& w) {
+  const hipStream_t st = s.stream;
+  const int ntiles = (nvec + BT - 1) / BT;
+  Tiles tl{ntiles, w.tk, w.ts, w.tn};
+  Slots sl{nvec, w.sk, nullptr};
+  launch_col_inv<double>(s.geom, s.fft, sl, x, s.nb_max, w.T1, nullptr, nullptr, nullptr, st);
+  launch_plane_hv<double>(s.geom, s.fft, sl, w.T1, w.T2, s.d_vloc.get(), 0, st);
+  launch_col_fwd<double>(s.geom, s.fft, sl, w.T2, y, s.nb_max, x, nullptr, 1.0 / s.ng, st);
+  if (s.natoms > 0) {
+    gram<double>(tl, s.d_nb.get(), s.nb_max, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
+                 (size_t)s.natoms * s.nb_max, s.nb_max, x, s.nb_max, w.part, w.coef, MAXM, st);
+    UpdTerm<double> t1{s.d_proj.get(), (size_t)s.natoms * s.nb_max, s.nb_max,
+                       s.d_natoms_k.get(), w.coef, MAXM, s.dnl, s.natoms};
+    update<double>(tl, s.d_nb.get(), s.nb_max, nullptr, y, s.nb_max, 1.0, t1, UpdTerm<double>{},
+                   nullptr, nullptr, st);
+  }
+}
+
 void apply_hamiltonian(System& s, int k, int nvec, const double2* x, double2* y) {
   const hipStream_t st = s.stream;
-  std::vector<int> sk(nvec, k);
-  DBuf<int> dsk, dtk, dts, dtn;
-  dsk.upload(sk, st);
-  std::vector<int> tk, ts, tn;
+  DBuf<unsigned char> ws;
+  ws.alloc(HamWork::bytes(s, nvec));
+  HamWork w;
+  w.carve(s, nvec, ws.get());
+  std::vector<int> sk(nvec, k), tk, ts, tn;
   for (int v0 = 0; v0 < nvec; v0 += BT) {
     tk.push_back(k);
     ts.push_back(v0);
     tn.push_back(std::min(BT, nvec - v0));
   }
-  dtk.upload(tk, st); dts.upload(ts, st); dtn.upload(tn, st);
-  Tiles tl{(int)tk.size(), dtk.get(), dts.get(), dtn.get()};
-  DBuf<double2> T1, T2, coef, part;
-  T1.alloc((size_t)nvec * s.L.C * s.ncol_max);
-  T2.alloc((size_t)nvec * s.L.C * s.ncol_max);
-  Slots sl{nvec, dsk.get(), nullptr};
-  launch_col_inv<double>(s.geom, s.fft, sl, x, s.nb_max, T1.get(), nullptr, nullptr, nullptr, st);
-  launch_plane_hv<double>(s.geom, s.fft, sl, T1.get(), T2.get(), s.d_vloc.get(), 0, st);
-  launch_col_fwd<double>(s.geom, s.fft, sl, T2.get(), y, s.nb_max, x, nullptr, 1.0 / s.ng, st);
-  if (s.natoms > 0) {
-    coef.alloc((size_t)nvec * MAXM);
-    part.alloc(gram_part_elems(tl.n, s.nb_max, s.natoms));
-    gram<double>(tl, s.d_nb.get(), s.nb_max, s.d_natoms_k.get(), s.natoms, s.d_proj.get(),
-                 (size_t)s.natoms * s.nb_max, s.nb_max, x, s.nb_max, part.get(), coef.get(),
-                 MAXM, st);
-    UpdTerm<double> t1{s.d_proj.get(), (size_t)s.natoms * s.nb_max, s.nb_max,
-                       s.d_natoms_k.get(), coef.get(), MAXM, s.dnl, s.natoms};
-    update<double>(tl, s.d_nb.get(), s.nb_max, nullptr, y, s.nb_max, 1.0, t1, UpdTerm<double>{},
-                   nullptr, nullptr, st);
-  }
+  IKR_HIP(hipMemcpyAsync(w.sk, sk.data(), sk.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  IKR_HIP(hipMemcpyAsync(w.tk, tk.data(), tk.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  IKR_HIP(hipMemcpyAsync(w.ts, ts.data(), ts.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  IKR_HIP(hipMemcpyAsync(w.tn, tn.data(), tn.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  apply_hamiltonian_ws(s, k, nvec, x, y, w);
   IKR_HIP(hipStreamSynchronize(st));
 }
 

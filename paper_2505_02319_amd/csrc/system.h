@@ -131,6 +131,7 @@ struct System {
   int kgrid[3];
   int nocc = 0, nextra = 0, nbands = 0, xc = 0;
   hipStream_t stream = nullptr;
+  int device = 0;                  // device current at setup
 
   // layout
   int cax = 0, pax = 1, qax = 2;
@@ -196,6 +197,10 @@ struct System {
   std::string name;
 };
 
+// noalloc.hip: the no-allocation work space (one fixed device array per GPU)
+void init_scratch(int device);
+void apply_hamiltonian_noalloc(System& s, int k, int nvec, const double2* x, double2* y);
+
 // setup.cpp
 System* create_system(const ikr_system_desc* d, hipStream_t st);
 void import_ground_state(System& s, const double* eps, const double* coeffs);
@@ -205,7 +210,20 @@ void finish_setup(System& s);
 void compute_ground_state(System& s);
 
 // solver.cpp
+// Work space of one Hamiltonian application to nvec vectors of one k-point:
+// slot and tile tables, the two column buffers of the pruned FFT, projector
+// coefficients and gram partials, carved from one block of device memory.
+struct HamWork {
+  int *sk = nullptr, *tk = nullptr, *ts = nullptr, *tn = nullptr;
+  double2 *T1 = nullptr, *T2 = nullptr, *coef = nullptr, *part = nullptr;
+  static size_t bytes(const System& s, int nvec);
+  void carve(const System& s, int nvec, unsigned char* base);
+};
 void apply_hamiltonian(System& s, int k, int nvec, const double2* x, double2* y);
+// The same with a caller-provided work space whose tables are already filled;
+// enqueues only (no synchronisation).
+void apply_hamiltonian_ws(System& s, int k, int nvec, const double2* x, double2* y,
+                          const HamWork& w);
 double apply_kernel(System& s, const double* v_int, double* kv_int);
 struct Chi0Result {
   long long n_ham = 0, n_ham32 = 0, n_ham64 = 0;
