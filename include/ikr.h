@@ -126,6 +126,20 @@ typedef struct {
                                reproducible.
                                Kernel profiling (ikr_profile_enable) switches
                                graphs off.  Default 0 */
+  const double* x0;         /* device, nullable: initial guess x0 of Alg. 1 (grid
+                               values, C order, caller-owned, not written).  With
+                               x0 != 0 the first residual b - E~ x0 is formed with
+                               the tolerance tau/3 (Alg. 1, first line), so a solve
+                               can resume from a saved iterate; s0 can carry the
+                               saved estimate s.  Default NULL (x0 = 0) */
+  int kerker;               /* 1: solve the Kerker-preconditioned equation
+                               T E drho = T b (eq. precond_dyson) with T of
+                               eq. kerker; the estimated residual and tau then refer
+                               to T (b - E x), which Theorem 2 still bounds since
+                               ||T|| = 1 (Lemma kerker_properties); true_res stays
+                               ||b - E x||.  Forward solves only.  Default 0 */
+  double kerker_alpha;      /* alpha of the Kerker symbol |G|^2/(|G|^2 + alpha^2),
+                               1/bohr (default 0.8) */
 } ikr_solver_opts;
 
 typedef struct {
@@ -227,6 +241,32 @@ ikr_status ikr_apply_hamiltonian_noalloc(ikr_handle h, int k, int nvec,
  * vectors).  Hartree 4 pi/|G|^2 with G = 0 -> 0 (paper Sec. 3.4.3). */
 ikr_status ikr_apply_hxc_kernel(ikr_handle h, const double* v_dev,
                                 double* kv_dev);
+
+/* out = T v with the Kerker preconditioner of eq. kerker:
+ * T = W^-1 (D + (1 - D_11) e_1 e_1^T) W, D = diag(|G|^2 / (|G|^2 + alpha^2))
+ * over the FFT cube (|G| from the signed index), i.e. the charge-conserving
+ * form that keeps the G = 0 component (Lemma kerker_properties: T Hermitian
+ * positive definite, ||T|| = 1).  v_dev, out_dev: device FP64 grid values
+ * (C order), caller-owned, may alias.  alpha > 0 (1/bohr), else IKR_E_ARG. */
+ikr_status ikr_apply_kerker(ikr_handle h, double alpha, const double* v_dev,
+                            double* out_dev);
+
+/* Right-hand side of the Dyson equation for the displacement of one atom
+ * (Sec. 4.1.2: the perturbing potential dV0 of displaced atomic positions):
+ * b = chi0 dV0 with dV0 = dV_ext / dR_{atom, direction}, the derivative of
+ * both parts of the model potential -- the local Gaussian (whose Fourier
+ * coefficients gain a factor -i G_dir) and the nonlocal projector of that
+ * atom (dV_nl = D (|dp><p| + |p><dp|), dp = -i q_dir p, q = G + k).  The
+ * nonlocal part acts on the orbitals' coefficients, so chi0 is applied with
+ * the Sternheimer right-hand sides dV0 phi_n formed directly.  dv0_dev
+ * (nullable, device, grid values) receives the local part of dV0; b_dev
+ * (device) receives b.  cg_tol: CG tolerance relative to each band's
+ * Sternheimer right-hand side, in (0, 1) (1e-10 gives b to about 1e-9).
+ * Errors: IKR_E_ARG for an atom or direction out of range or a
+ * non-positive tolerance; IKR_E_STATE without a ground state; IKR_E_NOCONV
+ * when a CG hit its cap (b still written). */
+ikr_status ikr_displacement_rhs(ikr_handle h, int atom, int direction, double cg_tol,
+                                double* dv0_dev, double* b_dev, ikr_stats* stats);
 
 /* drho = chi0 dv through the Sternheimer route (eq. kchi0, eq.
  * delta_phi_P, eq. sternheimer_equation, eq. delta_f).  CG tolerances are

@@ -49,7 +49,8 @@ class SolverOpts(C.Structure):
                 ("precision", C.c_int), ("cg_min_iter", C.c_int), ("cg_max_iter", C.c_int),
                 ("fp32_theta", C.c_double), ("b_norm", C.c_double),
                 ("want_true_residual", C.c_int), ("true_res_cg_tol", C.c_double),
-                ("schur", C.c_int), ("batching", C.c_int)]
+                ("schur", C.c_int), ("batching", C.c_int), ("x0", C.c_void_p),
+                ("kerker", C.c_int), ("kerker_alpha", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -84,6 +85,9 @@ SIGNATURES = {
     "ikr_apply_hamiltonian": (C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "ikr_apply_hamiltonian_noalloc": (C.c_int, [_VP, C.c_int, C.c_int, _VP, _VP]),
     "ikr_apply_hxc_kernel": (C.c_int, [_VP, _VP, _VP]),
+    "ikr_apply_kerker": (C.c_int, [_VP, C.c_double, _VP, _VP]),
+    "ikr_displacement_rhs": (C.c_int, [_VP, C.c_int, C.c_int, C.c_double, _VP, _VP,
+                                       C.POINTER(Stats)]),
     "ikr_apply_chi0": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(C.c_double),
                                  C.POINTER(Stats)]),
     "ikr_apply_dielectric": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(SolverOpts),
@@ -129,11 +133,18 @@ def _check(code: int):
 
 
 def default_opts(**kw) -> SolverOpts:
+    """Solver options with the library defaults, overridden by kw.  x0 may be
+    a CUDA float64 grid tensor (it must stay alive while the options are
+    used) or a device address."""
     o = SolverOpts()
     lib().ikr_default_opts(C.byref(o))
     for key, val in kw.items():
         if key == "strategy" and isinstance(val, str):
             val = STRATEGY[val]
+        if key == "x0" and val is not None and hasattr(val, "data_ptr"):
+            assert val.is_cuda and val.is_contiguous()
+            o._x0_keep = val
+            val = val.data_ptr()
         setattr(o, key, val)
     return o
 
@@ -325,6 +336,22 @@ class ResponseSystem:
         _check(lib().ikr_apply_hxc_kernel(self.h, _ptr(v), _ptr(out)))
         return out
 
+    def apply_kerker(self, v, alpha: float = 0.8):
+        """T v with the Kerker preconditioner (eq. kerker)."""
+        out = self._torch.empty_like(self._grid(v))
+        _check(lib().ikr_apply_kerker(self.h, float(alpha), _ptr(v), _ptr(out)))
+        return out
+
+    def displacement_rhs(self, atom: int, direction: int, cg_tol: float = 1e-10):
+        """(b, dV0_local, stats): b = chi0 dV0 for the displacement of one atom."""
+        torch = self._torch
+        b = torch.empty(self.fft, dtype=torch.float64, device="cuda")
+        dv0 = torch.empty_like(b)
+        st = Stats()
+        _check(lib().ikr_displacement_rhs(self.h, int(atom), int(direction), float(cg_tol),
+                                          _ptr(dv0), _ptr(b), C.byref(st)))
+        return b, dv0, st.as_dict()
+
     def apply_chi0(self, dv, cg_tol: float = 1e-10, cg_tol_per_band=None):
         out = self._torch.empty_like(self._grid(dv))
         st = Stats()
@@ -442,3 +469,47 @@ def dyson_solve(b, rs: "ResponseSystem", opts: Optional[SolverOpts] = None,
 
 
 _DYSON = None
+
+
+def _chi0_function():
+    import torch
+
+    class Chi0Apply(torch.autograd.Function):
+        """drho = chi0 dv through the Sternheimer route.  chi0 is symmetric in
+        the grid inner product (it is a response function of a Hermitian
+        Hamiltonian, eq. chi0), so the backward pass applies chi0 itself to
+        the incoming gradient; nothing is stored from the forward pass."""
+
+        @staticmethod
+        def forward(ctx, dv, rs, cg_tol):
+            ctx.rs, ctx.cg_tol = rs, cg_tol
+            return _chi0_scaled(rs, dv, cg_tol)
+
+        @staticmethod
+        def backward(ctx, g):
+            return _chi0_scaled(ctx.rs, g, ctx.cg_tol), None, None
+
+    return Chi0Apply
+
+
+def _chi0_scaled(rs, v, cg_tol):
+    """chi0 v with CG tolerances relative to ||v|| (v normalised first)."""
+    import torch
+    v = v.contiguous()
+    n = float(torch.linalg.norm(v))
+    if n == 0.0:
+        return torch.zeros_like(v)
+    out, _ = rs.apply_chi0(v / n, cg_tol=cg_tol)
+    return out * n
+
+
+def chi0_apply(dv, rs: "ResponseSystem", cg_tol: float = 1e-10):
+    """Differentiable drho = chi0 dv (dv a CUDA float64 grid tensor); the CG
+    tolerance is relative to ||dv|| (and to ||g|| in the backward pass)."""
+    global _CHI0
+    if _CHI0 is None:
+        _CHI0 = _chi0_function()
+    return _CHI0.apply(dv, rs, cg_tol)
+
+
+_CHI0 = None

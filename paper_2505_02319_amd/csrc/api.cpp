@@ -52,6 +52,9 @@ void check_opts(const ikr_solver_opts* o) {
   IKR_CHECK(o->s0 > 0, IKR_E_ARG, "s0 must be positive");
   IKR_CHECK(o->precision == 0 || o->precision == 1, IKR_E_ARG, "precision must be 0 or 1");
   IKR_CHECK(o->batching == 0 || o->batching == 1, IKR_E_ARG, "batching must be 0 or 1");
+  IKR_CHECK(o->kerker == 0 || o->kerker == 1, IKR_E_ARG, "kerker must be 0 or 1");
+  IKR_CHECK(!o->kerker || (o->kerker_alpha > 0 && std::isfinite(o->kerker_alpha)), IKR_E_ARG,
+            "kerker_alpha must be positive");
 }
 
 // The CG launch mode of one call (restored on exit, also on errors).
@@ -82,6 +85,9 @@ void ikr_default_opts(ikr_solver_opts* o) {
   o->want_true_residual = 0;
   o->true_res_cg_tol = 1e-14;
   o->schur = 1;
+  o->x0 = nullptr;
+  o->kerker = 0;
+  o->kerker_alpha = 0.8;
 }
 
 int ikr_supported_fft_size(int n) { return ikr::fft_length_supported(n) ? 1 : 0; }
@@ -224,6 +230,38 @@ ikr_status ikr_apply_hxc_kernel(ikr_handle h, const double* v_dev, double* kv_de
   });
 }
 
+ikr_status ikr_apply_kerker(ikr_handle h, double alpha, const double* v_dev, double* out_dev) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(v_dev && out_dev, IKR_E_ARG, "null vector");
+    IKR_CHECK(alpha > 0 && std::isfinite(alpha), IKR_E_ARG, "alpha must be positive");
+    ikr::apply_kerker_ext(*s, alpha, v_dev, out_dev);
+    IKR_HIP(hipStreamSynchronize(s->stream));
+  });
+}
+
+ikr_status ikr_displacement_rhs(ikr_handle h, int atom, int direction, double cg_tol,
+                                double* dv0_dev, double* b_dev, ikr_stats* stats) {
+  return guarded([&] {
+    System* s = sys_of(h);
+    IKR_CHECK(b_dev, IKR_E_ARG, "null output");
+    IKR_CHECK(atom >= 0 && atom < s->natoms, IKR_E_ARG, "atom index out of range");
+    IKR_CHECK(direction >= 0 && direction < 3, IKR_E_ARG, "direction must be 0, 1 or 2");
+    IKR_CHECK(cg_tol > 0 && cg_tol < 1, IKR_E_ARG, "CG tolerance must be in (0, 1)");
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
+    ikr::Chi0Result r = ikr::displacement_rhs(*s, atom, direction, cg_tol, dv0_dev, b_dev);
+    if (stats) {
+      std::memset(stats, 0, sizeof(*stats));
+      stats->n_ham = r.n_ham;
+      stats->n_ham_fp64 = r.n_ham64;
+      stats->n_ham_fp32 = r.n_ham32;
+      stats->cg_unconverged = r.noconv;
+      stats->true_res = -1;
+    }
+    IKR_CHECK(r.noconv == 0, IKR_E_NOCONV, "a Sternheimer CG hit the iteration cap");
+  });
+}
+
 ikr_status ikr_apply_chi0(ikr_handle h, const double* dv_dev, double* drho_dev, double cg_tol,
                           const double* cg_tol_host, ikr_stats* stats) {
   return guarded([&] {
@@ -313,6 +351,7 @@ ikr_status ikr_solve_response_adjoint(ikr_handle h, const double* g_dev, double*
     check_opts(opts);
     GraphMode mode(s, opts);
     IKR_CHECK(g_dev && lambda_dev && g_dev != lambda_dev, IKR_E_ARG, "bad vector pointers");
+    IKR_CHECK(!opts->kerker, IKR_E_ARG, "Kerker preconditioning is for forward solves only");
     IKR_CHECK(s->have_gs, IKR_E_STATE, "ground state not set up");
     ikr_stats local{};
     local.true_res = -1;

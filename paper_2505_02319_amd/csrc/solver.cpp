@@ -495,8 +495,9 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
 
   // right-hand sides t_j = F(u F^-1 phi_j) into r (or given ones)
   if (ex && ex->rhs_pw) {
-    IKR_HIP(hipMemcpyAsync(w.r.get(), ex->rhs_pw, (size_t)J * nbm * sizeof(double2),
-                           hipMemcpyDeviceToDevice, st));
+    if (ex->rhs_pw != w.r.get())
+      IKR_HIP(hipMemcpyAsync(w.r.get(), ex->rhs_pw, (size_t)J * nbm * sizeof(double2),
+                             hipMemcpyDeviceToDevice, st));
   } else {
     launch_plane_hv<double>(s.geom, s.fft, all, s.d_Tphi.get(), w.T2.get(), u_int, 0, st);
     launch_col_fwd<double>(s.geom, s.fft, all, w.T2.get(), w.r.get(), nbm, nullptr, nullptr,
@@ -818,13 +819,50 @@ void apply_dielectric_adjoint_ext(System& s, const double* v_ext, double* ev_ext
   IKR_HIP(hipStreamSynchronize(st));
 }
 
+// ---------------------------------------------------------------- Kerker
+// T v = W^-1 (D + (1 - D_11) e_1 e_1^T) W v (eq. kerker and the proof of
+// Lemma kerker_properties): the symbol |G|^2 / (|G|^2 + alpha^2) with the
+// G = 0 entry set to 1, applied by the density-grid FFT pair of the Hxc
+// kernel.
+void apply_kerker_ext(System& s, double alpha, const double* v_ext, double* out_ext) {
+  const hipStream_t st = s.stream;
+  if (s.kerker_alpha != alpha || !s.d_kerker.get()) {
+    const int C = s.L.C, P = s.L.P, Q = s.L.Q;
+    std::vector<double> d((size_t)s.ng);
+    for (int c = 0; c < C; ++c)
+      for (int p = 0; p < P; ++p)
+        for (int q = 0; q < Q; ++q) {
+          const int cs = c < C / 2 ? c : c - C, ps = p < P / 2 ? p : p - P,
+                    qs = q < Q / 2 ? q : q - Q;
+          const double gc = cs * s.b[s.cax], gp = ps * s.b[s.pax], gq = qs * s.b[s.qax];
+          const double gg = gc * gc + gp * gp + gq * gq;
+          d[((size_t)c * P + p) * Q + q] = gg > 0 ? gg / (gg + alpha * alpha) : 1.0;
+        }
+    s.d_kerker.upload(d, st);
+    s.kerker_alpha = alpha;
+  }
+  to_internal(s.L, v_ext, s.d_tmpg.get(), st);
+  launch_kernel_apply(s.geom, s.fft, s.d_tmpg.get(), s.d_kerker.get(), nullptr, s.d_u.get(),
+                      s.d_kw1.get(), s.d_kw2.get(), s.d_kpart.get(), st);
+  to_external(s.L, s.d_u.get(), out_ext, 1.0, nullptr, 0.0, st);
+}
+
 // ---------------------------------------------------------------- Alg. 1
 // Inexact GMRES(m) on E (adjoint = false) or on E^T (adjoint = true).
+//
+// With o.kerker the system is T E x = T b (eq. precond_dyson): every operator
+// application is followed by T, and the right-hand side is T b; tau (taken
+// relative to ||b|| when tol_is_relative) then bounds ||T (b - E x)||, which
+// Theorem 2 still controls as ||T|| = 1.  With o.x0 the iteration starts from
+// x0 (Alg. 1, first line, at tolerance tau/3).
 void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_solver_opts& o,
                     ikr_stats* stt, bool adjoint) {
+  const bool kerker = o.kerker != 0;
+  IKR_CHECK(!(kerker && adjoint), 1, "Kerker preconditioning is for forward solves only");
   auto apply_op = [&](const double* v, double* ev, double common, double bn, ikr_stats* sp) {
     if (adjoint) apply_dielectric_adjoint_ext(s, v, ev, common, o, bn, sp);
     else apply_dielectric_ext(s, v, ev, common, o, bn, sp);
+    if (kerker) apply_kerker_ext(s, o.kerker_alpha, ev, ev);
   };
   const auto t0 = std::chrono::steady_clock::now();
   const hipStream_t st = s.stream;
@@ -856,21 +894,39 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
   const double bnorm = std::sqrt(dots(1, b_ext, b_ext)[0]);
   const double tau = o.tol_is_relative ? o.tol * bnorm : o.tol;
   IKR_CHECK(std::isfinite(bnorm), 5, "non-finite right-hand side");
-  IKR_HIP(hipMemsetAsync(x_ext, 0, (size_t)n * sizeof(double), st));
-  double s_est = o.s0;
   bool x0_zero = true;
+  if (o.x0) {
+    const double x0n = std::sqrt(dots(1, o.x0, o.x0)[0]);
+    IKR_CHECK(std::isfinite(x0n), 5, "non-finite initial guess");
+    if (o.x0 != x_ext)
+      IKR_HIP(hipMemcpyAsync(x_ext, o.x0, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice,
+                             st));
+    x0_zero = x0n == 0.0;
+  } else {
+    IKR_HIP(hipMemsetAsync(x_ext, 0, (size_t)n * sizeof(double), st));
+  }
+  // right-hand side of the (preconditioned) system
+  DBuf<double> tb;
+  const double* rhs = b_ext;
+  if (kerker) {
+    tb.alloc(n);
+    apply_kerker_ext(s, o.kerker_alpha, b_ext, tb.get());
+    rhs = tb.get();
+  }
+  double s_est = o.s0;
   int restarts = 0, iters = 0;
   double resid = bnorm;
   std::vector<double> H((size_t)(m + 1) * m);
   bool done = bnorm == 0.0;
+  if (done) IKR_HIP(hipMemsetAsync(x_ext, 0, (size_t)n * sizeof(double), st));   // E^-1 0 = 0
   while (!done) {
     // line 1: r0 = b - E~(0) x0 with tolerance tau/3
     double* v0 = V.get();
     if (x0_zero) {
-      IKR_HIP(hipMemcpyAsync(v0, b_ext, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      IKR_HIP(hipMemcpyAsync(v0, rhs, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {
       apply_op(x_ext, v0, adaptive ? tau / 3.0 : tau, bnorm, stt);
-      axpy(1, b_ext, {1.0}, -1.0, v0);
+      axpy(1, rhs, {1.0}, -1.0, v0);
     }
     const double beta = std::sqrt(dots(1, v0, v0)[0]);
     if (beta == 0.0) break;

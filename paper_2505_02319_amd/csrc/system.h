@@ -171,6 +171,8 @@ struct System {
   // caches
   DBuf<double2> d_Tphi;            // [J][C][ncol_max] column transforms of occupied phi
   DBuf<double> d_rho, d_fx, d_khat;   // internal layout
+  DBuf<double> d_kerker;           // Kerker symbol with G = 0 -> 1 (internal layout)
+  double kerker_alpha = -1;        // alpha d_kerker was built for
   std::vector<double> orbnorm_k;   // ||Re F_k^-1 Phi_k||_{2,inf}
   std::vector<double> orbnorm_full_k;  // ||F_k^-1 Phi_k||_{2,inf}
   double knorm_bound = 0;          // ||K||_2 <= max 4 pi / |G|^2 + max |f_x|
@@ -247,6 +249,11 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
 std::vector<double> grad_amplitudes(System& s, const double* drho_ext, const double* lam_ext,
                                     double cg_tol, ikr_stats* st);
 void ensure_fp32(System& s);   // FP32 work space and operator copies (lazy)
+// out = T v (Kerker, eq. kerker), grid vectors in the external layout (may alias)
+void apply_kerker_ext(System& s, double alpha, const double* v_ext, double* out_ext);
+// b = chi0 dV0 for the displacement of one atom (local and nonlocal parts)
+Chi0Result displacement_rhs(System& s, int atom, int dir, double cg_tol, double* dv0_ext,
+                            double* b_ext);
 void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext,
                           double common, const ikr_solver_opts& o, double bnorm,
                           ikr_stats* st);
