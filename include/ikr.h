@@ -125,7 +125,11 @@ typedef struct {
                                split sums differently); replays are bitwise
                                reproducible.
                                Kernel profiling (ikr_profile_enable) switches
-                               graphs off.  Default 0 */
+                               graphs off.  2: the plain FP64 reference path:
+                               the k-points' Sternheimer CGs one after the
+                               other, the host reading the live count after
+                               every CG iteration, FP64 throughout (precision
+                               ignored).  Default 0 */
   const double* x0;         /* device, nullable: initial guess x0 of Alg. 1 (grid
                                values, C order, caller-owned, not written).  With
                                x0 != 0 the first residual b - E~ x0 is formed with
@@ -328,6 +332,17 @@ ikr_status ikr_solve_response_adjoint(ikr_handle h, const double* g_dev,
 ikr_status ikr_grad_amplitudes(ikr_handle h, const double* drho_dev,
                                const double* lambda_dev, double cg_tol,
                                double* dlda_host, ikr_stats* stats);
+
+/* Kernel-path selection (process-wide; for tests and tuning).  Every path
+ * computes the same quantities; by default (mask 0) each launch picks its
+ * path by size.  Bit 0 forces the vector-FMA projection gram (otherwise the
+ * per-tile matrix-core gram below 65 projection rows, the k-wide matrix-core
+ * gram above), bit 1 the two-launch end of a CG iteration (otherwise one
+ * block while the batch has few partials), bit 2 the k-wide matrix-core gram
+ * (all bands of a k-point per block) at any row count.
+ * Unknown bits: IKR_E_ARG.  ikr_get_kernel_paths returns the current mask. */
+ikr_status ikr_set_kernel_paths(int mask);
+int ikr_get_kernel_paths(void);
 
 /* Opt-in kernel timing (process-wide).  Bit i of kernel_mask brackets every
  * launch of hot kernel i of the Sternheimer CG by HIP events on the launching

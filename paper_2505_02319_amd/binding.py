@@ -99,6 +99,8 @@ SIGNATURES = {
                                              C.POINTER(Stats)]),
     "ikr_grad_amplitudes": (C.c_int, [_VP, _VP, _VP, C.c_double, C.POINTER(C.c_double),
                                       C.POINTER(Stats)]),
+    "ikr_set_kernel_paths": (C.c_int, [C.c_int]),
+    "ikr_get_kernel_paths": (C.c_int, []),
     "ikr_profile_enable": (C.c_int, [C.c_int]),
     "ikr_profile_reset": (C.c_int, []),
     "ikr_profile_kernel_count": (C.c_int, []),
@@ -118,6 +120,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} not built; run paper_2505_02319_amd.build.build()")
+        # torch first: the library then binds to the HIP runtime torch has loaded,
+        # so the process holds one HIP runtime (two in one process do not share
+        # the GPU: whichever initialises second finds no device)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
@@ -147,6 +153,18 @@ def default_opts(**kw) -> SolverOpts:
             val = val.data_ptr()
         setattr(o, key, val)
     return o
+
+
+PATH_VECTOR_GRAM, PATH_SPLIT_END, PATH_KWIDE = 1, 2, 4
+
+
+def set_kernel_paths(mask: int):
+    """Force kernel paths process-wide (0: by size; bits: PATH_*)."""
+    _check(lib().ikr_set_kernel_paths(int(mask)))
+
+
+def kernel_paths() -> int:
+    return int(lib().ikr_get_kernel_paths())
 
 
 def profile_enable(on=True):

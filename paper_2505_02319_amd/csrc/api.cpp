@@ -51,7 +51,7 @@ void check_opts(const ikr_solver_opts* o) {
   IKR_CHECK(o->cg_min_iter >= 0 && o->cg_max_iter >= 1, IKR_E_ARG, "bad CG iteration limits");
   IKR_CHECK(o->s0 > 0, IKR_E_ARG, "s0 must be positive");
   IKR_CHECK(o->precision == 0 || o->precision == 1, IKR_E_ARG, "precision must be 0 or 1");
-  IKR_CHECK(o->batching == 0 || o->batching == 1, IKR_E_ARG, "batching must be 0 or 1");
+  IKR_CHECK(o->batching >= 0 && o->batching <= 2, IKR_E_ARG, "batching must be 0, 1 or 2");
   IKR_CHECK(o->kerker == 0 || o->kerker == 1, IKR_E_ARG, "kerker must be 0 or 1");
   IKR_CHECK(!o->kerker || (o->kerker_alpha > 0 && std::isfinite(o->kerker_alpha)), IKR_E_ARG,
             "kerker_alpha must be positive");
@@ -60,8 +60,11 @@ void check_opts(const ikr_solver_opts* o) {
 // The CG launch mode of one call (restored on exit, also on errors).
 struct GraphMode {
   System* s;
-  GraphMode(System* sys, const ikr_solver_opts* o) : s(sys) { s->cg_graph = o->batching; }
-  ~GraphMode() { s->cg_graph = 0; }
+  GraphMode(System* sys, const ikr_solver_opts* o) : s(sys) {
+    s->cg_graph = o->batching == 1;
+    s->cg_plain = o->batching == 2;
+  }
+  ~GraphMode() { s->cg_graph = 0; s->cg_plain = 0; }
 };
 
 }  // namespace
@@ -379,6 +382,15 @@ ikr_status ikr_grad_amplitudes(ikr_handle h, const double* drho_dev, const doubl
     if (stats) *stats = local;
   });
 }
+
+ikr_status ikr_set_kernel_paths(int mask) {
+  return guarded([&] {
+    IKR_CHECK(mask >= 0 && mask <= 7, IKR_E_ARG, "unknown kernel path bits");
+    ikr::set_kernel_paths(mask);
+  });
+}
+
+int ikr_get_kernel_paths(void) { return ikr::kernel_paths(); }
 
 ikr_status ikr_profile_enable(int kernel_mask) {
   return guarded([&] { ikr::KTimer::enable((unsigned)kernel_mask); });

@@ -53,23 +53,48 @@ struct Layout {
   int st_c, st_p, st_q;    // external strides of the internal axes
 };
 
-size_t gram_part_elems(int ntiles, int nb_max, int Mmax);
+// Process-wide choice of kernel paths, for tests and tuning.  0: by size
+// (the default); each bit forces one path at any size.
+enum KernelPath : int {
+  PATH_VECTOR_GRAM = 1,   // projections by the vector-FMA gram kernel
+  PATH_SPLIT_END = 2,     // CG iteration end as two launches (finish, compaction)
+  PATH_KWIDE = 4,         // k-wide matrix-core gram at any row count
+};
+
+// Tiles grouped by k-point: the tiles of k are t0[k] .. t0[k + 1] - 1 of the
+// tile list (device array of nk + 1 entries, consecutive per k); ktmax bounds
+// the tiles of any one k.  Lets the gram take all bands of a k-point at once.
+struct KTileRange {
+  int nk = 0;
+  const int* t0 = nullptr;
+  int ktmax = 0;
+};
+
+void set_kernel_paths(int mask);
+int kernel_paths();
+
+// Elements of the gram's partial-sum buffer for up to ntiles tiles of Mmax
+// rows (nk: k-points of the tile list, when the k-wide gram may be used).
+size_t gram_part_elems(int ntiles, int nb_max, int Mmax, int nk = 0);
 int update_nblocks(int nb_max);
 int vec_nblocks(int nb_max);
 int multidot_nblocks(int n);
 
+// coef[slot * cstride + m] = <W[k][m], X[slot]> for the slots of the tiles;
+// with kr given (and few enough tiles per k), above 64 rows the k-wide gram.
 template <typename R>
 void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
           const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
           int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st,
-          const int* active = nullptr);
+          const int* active = nullptr, const KTileRange& kr = KTileRange{});
 
 // The first stage of gram alone: partial sums over the super-chunks,
 // part[((t * nsc + sc) * Mmax + m) * BT + b] for rows m < Mk[k]; returns nsc.
 template <typename R>
 int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
                   const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
-                  int x_stride, cplx<R>* part, hipStream_t st, const int* active = nullptr);
+                  int x_stride, cplx<R>* part, hipStream_t st, const int* active = nullptr,
+                  const KTileRange& kr = KTileRange{});
 
 // The second stage: coef[slot * cstride + m] = sum over the nsc super-chunks.
 template <typename R>

@@ -8,8 +8,10 @@
 // two-stage (per-block partials, then a fixed-order sum), so results are
 // bitwise reproducible run to run.
 #include "blas.h"
+#include "mfma.h"
 
 #include <algorithm>
+#include <atomic>
 
 namespace ikr {
 namespace {
@@ -181,25 +183,6 @@ __global__ __launch_bounds__(NT) void gram_kernel(
 // staged in LDS ([rows][MCH + 1]); RTM row tiles at most, CHM coefficients
 // per chunk.
 
-typedef double mf64x4 __attribute__((ext_vector_type(4)));
-typedef float mf32x4 __attribute__((ext_vector_type(4)));
-
-template <typename R> struct Mfma;
-template <> struct Mfma<double> {
-  typedef mf64x4 acc;
-  __device__ __forceinline__ static acc mac(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // row of result value v held by lane l (the column is l % 16)
-  __device__ __forceinline__ static int row(int l, int v) { return 4 * v + (l >> 4); }
-};
-template <> struct Mfma<float> {
-  typedef mf32x4 acc;
-  __device__ __forceinline__ static acc mac(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ __forceinline__ static int row(int l, int v) { return 4 * (l >> 4) + v; }
-};
 
 template <typename R, int RTM, int CHM>
 __global__ __launch_bounds__(NT) void gram_mfma_kernel(
@@ -286,6 +269,129 @@ __global__ __launch_bounds__(NT) void gram_mfma_kernel(
   for (int q = 0; q < PW; ++q) {
     const int rt = wave + q * nw;
     if (rt >= RT) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int m = 16 * rt + M::row(lane, v);
+      if (m < Mr) part[(((size_t)t * nsc + sc) * Mmax + m) * BT + j] = mk<R>(cre[q][v], cim[q][v]);
+    }
+  }
+}
+
+// The same partials for all bands of a k-point at once, on the matrix cores.
+// A block takes one (k, super-chunk) item and the up to KT tiles of k
+// (t0[k] .. t0[k+1]); it stages chunks of KCH coefficients of all Mr rows of
+// W_k and of the k's bands in LDS, so W_k is read once per iteration
+// whatever the number of bands, and its 8 wavefronts deal the (row tile,
+// band tile) pairs of the output round-robin (pair = wave + 8 q).  Each pair
+// is four real 16x16x4 MFMA products per 4 coefficients (Re += Wr Xr + Wi Xi,
+// Im += Wr Xi - Wi Xr).  The next chunk is fetched into registers while the
+// current one is used.
+constexpr int KW_NT = 512;
+
+template <typename R, int KT, int RTM, int KCH>
+__global__ __launch_bounds__(KW_NT) void gram_kw_kernel(
+    Tiles tl, KTileRange kr, const int* __restrict__ nb, const int* __restrict__ Mk, int Mmax,
+    const cplx<R>* __restrict__ W, size_t wk_stride, int w_stride,
+    const cplx<R>* __restrict__ X, int x_stride, int nsc, int sc_len,
+    cplx<R>* __restrict__ part, const int* __restrict__ active) {
+  using M = Mfma<R>;
+  constexpr int LC = KCH + 1;
+  constexpr int NBT = KT * 16;                       // band rows staged
+  constexpr int PW = (KT * RTM + 7) / 8;             // pairs per wavefront
+  __shared__ cplx<R> Xs[NBT * LC];
+  __shared__ cplx<R> Ws[RTM * 16 * LC];
+  __shared__ int ss[NBT];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nsc * kr.nk) return;
+  const int k = item / nsc, sc = item % nsc, tid = threadIdx.x;
+  int t0 = kr.t0[k], nt = kr.t0[k + 1] - t0;
+  if (tl.dn) nt = min(nt, *tl.dn - t0);
+  if (nt <= 0) return;
+  nt = min(nt, KT);
+  const int Mr = Mk[k], n = nb[k];
+  const int RT = (Mr + 15) / 16;
+  const int wave = tid >> 6, lane = tid & 63;
+  if (tid < NBT) {
+    const int t = tid / 16, b = tid % 16;
+    int slot = -1;
+    if (t < nt && b < tl.nb[t0 + t]) {
+      slot = tslot(tl, t0 + t, b);
+      if (active && !active[slot]) slot = -1;
+    }
+    ss[tid] = slot;
+  }
+  __syncthreads();
+  const cplx<R>* Wk = W + (size_t)k * wk_stride;
+  const int gbeg = sc * sc_len, gend = min(n, gbeg + sc_len);
+  const int npair = RT * nt;
+  typename M::acc cre[PW], cim[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cre[q][v] = cim[q][v] = R(0);
+  constexpr int XL = NBT * KCH / KW_NT, WLM = RTM * 16 * KCH / KW_NT;
+  // 16 KCH is a multiple of KW_NT, so whole band and row tiles fill the
+  // fetch registers exactly
+  static_assert(16 * KCH % KW_NT == 0, "k-wide gram staging");
+  const int xl = nt * 16 * KCH / KW_NT, wl = RT * 16 * KCH / KW_NT;
+  cplx<R> xr[XL], wr[WLM];
+  auto fetch = [&](int g0) {
+#pragma unroll
+    for (int u = 0; u < XL; ++u) {
+      if (u < xl) {
+        const int i = tid + u * KW_NT, b = i / KCH, g = g0 + i % KCH;
+        const int slot = b < NBT ? ss[b] : -1;
+        xr[u] = (slot >= 0 && g < gend) ? X[(size_t)slot * x_stride + g] : mk<R>(0, 0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < WLM; ++u) {
+      if (u < wl) {
+        const int i = tid + u * KW_NT, m = i / KCH, g = g0 + i % KCH;
+        wr[u] = (m < Mr && g < gend) ? Wk[(size_t)m * w_stride + g] : mk<R>(0, 0);
+      }
+    }
+  };
+  if (gbeg < gend) fetch(gbeg);
+  for (int g0 = gbeg; g0 < gend; g0 += KCH) {
+#pragma unroll
+    for (int u = 0; u < XL; ++u) {
+      const int i = tid + u * KW_NT;
+      if (i < nt * 16 * KCH) Xs[(i / KCH) * LC + i % KCH] = xr[u];
+    }
+#pragma unroll
+    for (int u = 0; u < WLM; ++u) {
+      const int i = tid + u * KW_NT;
+      if (i < RT * 16 * KCH) Ws[(i / KCH) * LC + i % KCH] = wr[u];
+    }
+    __syncthreads();
+    if (g0 + KCH < gend) fetch(g0 + KCH);
+#pragma unroll 2
+    for (int ks = 0; ks < KCH / 4; ++ks) {
+      const int e = 4 * ks + (lane >> 4);
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int pr = wave + 8 * q;
+        if (pr < npair) {
+          const int rt = pr / nt, bt = pr - rt * nt;
+          const cplx<R> wa = Ws[(16 * rt + (lane & 15)) * LC + e];
+          const cplx<R> xb = Xs[(16 * bt + (lane & 15)) * LC + e];
+          cre[q] = M::mac(wa.x, xb.x, cre[q]);
+          cre[q] = M::mac(wa.y, xb.y, cre[q]);
+          cim[q] = M::mac(wa.x, xb.y, cim[q]);
+          cim[q] = M::mac(-wa.y, xb.x, cim[q]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int j = lane & 15;
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    const int pr = wave + 8 * q;
+    if (pr >= npair) continue;
+    const int rt = pr / nt, bt = pr - rt * nt, t = t0 + bt;
+    if (j >= tl.nb[t]) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int m = 16 * rt + M::row(lane, v);
@@ -633,6 +739,10 @@ __global__ void cscale_kernel(size_t n, cplx<R>* __restrict__ x, R a) {
 }  // namespace
 
 // ------------------------------------------------------------ launchers
+static std::atomic<int> g_kernel_paths{0};
+void set_kernel_paths(int mask) { g_kernel_paths.store(mask); }
+int kernel_paths() { return g_kernel_paths.load(); }
+
 // Super-chunks per tile: about `target` blocks over all tiles, each at
 // least one chunk long.
 static int nsc_for(int nb_max, int ntiles, int target, int& sc_len) {
@@ -645,7 +755,19 @@ static int nsc_for(int nb_max, int ntiles, int target, int& sc_len) {
   return nsc;
 }
 
-size_t gram_part_elems(int ntiles, int nb_max, int Mmax) {
+// Super-chunks per k-point of the k-wide gram: about KW_BLOCKS blocks over
+// the nk k-points (four rounds of one block per CU), each at least one chunk.
+constexpr int KW_BLOCKS = 1024;
+template <typename R> constexpr int kw_chunk() { return sizeof(R) == 8 ? 32 : 64; }
+static int kw_nsc(int nb_max, int nk, int kch, int& sc_len) {
+  const int nch = (nb_max + kch - 1) / kch;
+  int nsc = std::max(1, std::min(nch, KW_BLOCKS / std::max(nk, 1)));
+  const int per = (nch + nsc - 1) / nsc;
+  sc_len = per * kch;
+  return (nb_max + sc_len - 1) / sc_len;
+}
+
+size_t gram_part_elems(int ntiles, int nb_max, int Mmax, int nk) {
   size_t most = 0;
   for (int t = 1; t <= ntiles; ++t) {
     int sc_len;
@@ -654,22 +776,50 @@ size_t gram_part_elems(int ntiles, int nb_max, int Mmax) {
                                                           gram_blocks<float>(t, true)),
                                                  sc_len));
   }
+  if (nk > 0) {
+    int sc_len;
+    const int nsc = std::max(kw_nsc(nb_max, nk, kw_chunk<double>(), sc_len),
+                             kw_nsc(nb_max, nk, kw_chunk<float>(), sc_len));
+    most = std::max(most, (size_t)ntiles * nsc);
+  }
   return most * Mmax * BT;
 }
 
 template <typename R>
 int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
                   const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
-                  int x_stride, cplx<R>* part, hipStream_t st, const int* active) {
+                  int x_stride, cplx<R>* part, hipStream_t st, const int* active,
+                  const KTileRange& kr) {
   IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Mk && W && X && part, 8,
             "gram: null device pointer");
   if (tl.n <= 0) return 0;
+  const int paths = kernel_paths();
+  // k-wide on the matrix cores: above 64 rows (or forced), when every k has
+  // few enough tiles
+  // (instances: up to 6 tiles of 96 rows, or 5 tiles of 176 rows)
+  const bool kw_fits = (kr.ktmax <= 6 && Mmax <= 96) || (kr.ktmax <= 5 && Mmax <= 176);
+  if (kr.t0 && kr.nk > 0 && kw_fits && !(paths & PATH_VECTOR_GRAM) &&
+      (Mmax > 64 || (paths & PATH_KWIDE))) {
+    constexpr int kch = kw_chunk<R>();
+    int sc_len;
+    const int nsc = kw_nsc(nb_max, kr.nk, kch, sc_len);
+    const dim3 grid(round8(nsc * kr.nk));
+#define IKR_GRAMKW(KT, RTM)                                                                   \
+  hipLaunchKernelGGL((gram_kw_kernel<R, KT, RTM, kch>), grid, dim3(KW_NT), 0, st, tl, kr, nb,   \
+                     Mk, Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part, active)
+    if (Mmax <= 96) IKR_GRAMKW(6, 6);
+    else IKR_GRAMKW(5, 11);
+#undef IKR_GRAMKW
+    IKR_HIP(hipGetLastError());
+    return nsc;
+  }
   int sc_len;
-  const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(tl.n, Mmax <= 64), sc_len);
+  const bool mfma = Mmax <= 64 && !(paths & PATH_VECTOR_GRAM);
+  const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(tl.n, mfma), sc_len);
   // matrix cores up to 64 rows (faster than the vector kernel on the 48^3
   // cell; with more rows the accumulators and prefetch registers leave one or
   // two wavefronts per SIMD, and the vector kernel is faster: 48^2 x 96 cell)
-  if (Mmax <= 64) {
+  if (Mmax <= 64 && !(paths & PATH_VECTOR_GRAM)) {
     const int rt = (Mmax + 15) / 16;
     const int chm = 64;
     const size_t lds = (size_t)(BT + 16 * rt) * (chm + 1) * sizeof(cplx<R>);
@@ -702,11 +852,11 @@ template <typename R>
 void gram(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
           const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
           int x_stride, cplx<R>* part, cplx<R>* coef, int cstride, hipStream_t st,
-          const int* active) {
+          const int* active, const KTileRange& kr) {
   IKR_CHECK(coef, 8, "gram: null device pointer");
   IKR_CHECK(Mmax <= cstride, 1, "gram: coefficient stride below the row count");
   const int nsc = gram_partials<R>(tl, nb, nb_max, Mk, Mmax, W, wk_stride, w_stride, X,
-                                   x_stride, part, st, active);
+                                   x_stride, part, st, active, kr);
   gram_reduce<R>(tl, Mk, Mmax, nsc, part, coef, cstride, st, active);
 }
 
@@ -872,10 +1022,10 @@ void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st) {
 #define IKR_INST(R)                                                                       \
   template void gram<R>(const Tiles&, const int*, int, const int*, int, const cplx<R>*,   \
                         size_t, int, const cplx<R>*, int, cplx<R>*, cplx<R>*, int,        \
-                        hipStream_t, const int*);                                         \
+                        hipStream_t, const int*, const KTileRange&);                      \
   template int gram_partials<R>(const Tiles&, const int*, int, const int*, int,           \
                                 const cplx<R>*, size_t, int, const cplx<R>*, int,         \
-                                cplx<R>*, hipStream_t, const int*);                       \
+                                cplx<R>*, hipStream_t, const int*, const KTileRange&);    \
   template void gram_reduce<R>(const Tiles&, const int*, int, int, const cplx<R>*,        \
                                cplx<R>*, int, hipStream_t, const int*);                   \
   template void update<R>(const Tiles&, const int*, int, const int*, cplx<R>*, int, R,    \

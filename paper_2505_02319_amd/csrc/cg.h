@@ -37,20 +37,26 @@ void cg_combine(const Slots& sl, int Na, const int* Mq, int Mq_max, const cplx<R
                 R dnl, cplx<R>* gam, hipStream_t st);
 
 // Ap = w~ + sum_r W[r] gam[r] (in place in Wv), p = p~ - sum_m phi_m a_m (in
-// place in P), partial <p, Ap> -> dpart[slot * update_nblocks(nb_max) + gb].
+// place in P), partial <p, Ap> -> dpart[slot * nparts + gb] with nparts =
+// cg_update_parts(...).  With kr given, above 64 rows (or forced) all bands of
+// a k-point are updated per block on the matrix cores.
 template <typename R>
 void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, size_t wk,
                int Na, const int* Mq, int Mq_max, const cplx<R>* gam, int cstride,
-               cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st);
+               cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st,
+               const KTileRange& kr = KTileRange{});
+bool cg_update_kwide(int Mrows, const KTileRange& kr);
+int cg_update_parts(int nb_max, int Mrows, const KTileRange& kr);
 
-// alpha = rz / <p, Ap> per listed slot (from dpart); on a breakdown (<p, Ap>
+// alpha = rz / <p, Ap> per listed slot (from the nup partials per slot in
+// dpart); on a breakdown (<p, Ap>
 // <= 0 or a non-finite alpha) alpha = 0 and the slot leaves the active set.
 // Then x += alpha p ; r -= alpha Ap ; z = M^-1 r (into w) ; partials |r|^2
 // and <r, z> (rpart must not alias dpart).
 template <typename R>
 void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, const R* dpart,
-              const R* rz, R* alpha, int* active, const R* pshift, cplx<R>* x, cplx<R>* r,
-              const cplx<R>* p, cplx<R>* w, R* rpart, R* zpart, hipStream_t st);
+              int nup, const R* rz, R* alpha, int* active, const R* pshift, cplx<R>* x,
+              cplx<R>* r, const cplx<R>* p, cplx<R>* w, R* rpart, R* zpart, hipStream_t st);
 
 // x = p = 0 on the whole rows of the listed slots (the CG's start; x may be
 // null: p only).
@@ -83,6 +89,7 @@ struct CgCompact {
   int* step;
   int* hcnt = nullptr;   // host-mapped [2][2]: with hist, step s also writes (slots, tiles) to
                          // hcnt[2 (s & 1)], for the host loop to read without a copy
+  int* ktb = nullptr;    // [nk + 1]: first compact tile of each k (nullable)
 };
 
 // start: rz = <r, z>, beta = 0.  Otherwise: iteration count, |r|^2,

@@ -4,6 +4,7 @@
 // iteration).  Reductions are two-stage with fixed orders, so results are
 // bitwise reproducible run to run.
 #include "cg.h"
+#include "mfma.h"
 
 namespace ikr {
 namespace {
@@ -246,6 +247,158 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(
   }
 }
 
+// The same update for all bands of a k-point at once, on the matrix cores:
+//   Ap[b][g] = w~[b][g] + sum_r gam[b][r] W[r][g]          (all Mr rows)
+//   p[b][g]  = p~[b][g] + sum_m gam[b][Na + 2m + 1] W[Na + 2m][g]   (phi rows)
+// A block takes one (k, chunk of GB coefficients) item and every band of k
+// (up to KT tiles: t0[k] .. t0[k+1] of the compact tiles), so W_k is read once
+// per iteration.  The rows go through LDS 16 at a time with the coefficients
+// of those rows (and the -a_m of the phi rows among them); the (g tile, band
+// tile) pairs of the output are dealt to the 8 wavefronts round-robin.  Each
+// pair holds two accumulators (Ap and p), each four real 16x16x4 products per
+// 4 rows (Re = Gr Wr - Gi Wi, Im = Gr Wi + Gi Wr): A = coefficients
+// [band][row], B = W [row][g], so a lane's results lie along g.  The
+// <p, Ap> partial of each band goes to dpart[slot * nparts + chunk].
+constexpr int UKW_NT = 512;
+constexpr int UKW_RC = 16;     // rows per LDS stage
+
+template <typename R, int KT, int GB>
+__global__ __launch_bounds__(UKW_NT) void cg_update_kw_kernel(
+    Tiles tl, KTileRange kr, const int* __restrict__ nb, int nb_max,
+    const cplx<R>* __restrict__ Wcg, size_t wk, int Na, const int* __restrict__ Mq, int Mq_max,
+    const cplx<R>* __restrict__ gam, int cstride, cplx<R>* __restrict__ Wv,
+    cplx<R>* __restrict__ P, R* __restrict__ dpart, int nparts) {
+  using M = Mfma<R>;
+  constexpr int NBT = KT * 16, GT = GB / 16, NPAIR = KT * GT;
+  constexpr int PW = (NPAIR + 7) / 8;
+  constexpr int LW = GB + 1, LG = UKW_RC + 1, LA = UKW_RC / 2 + 1;
+  __shared__ cplx<R> Ws[UKW_RC * LW];     // W rows [r][g]
+  __shared__ cplx<R> Gs[NBT * LG];        // gam [band][r]
+  __shared__ cplx<R> As[NBT * LA];        // -a of the chunk's phi rows [band][m]
+  __shared__ int ss[NBT];
+  __shared__ R red[GT * NBT];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nparts * kr.nk) return;
+  const int k = item / nparts, gc = item % nparts, tid = threadIdx.x;
+  int t0 = kr.t0[k], nt = kr.t0[k + 1] - t0;
+  if (tl.dn) nt = min(nt, *tl.dn - t0);
+  if (nt <= 0) return;
+  nt = min(nt, KT);
+  const int n = nb[k], g0 = gc * GB;
+  if (g0 >= n) {   // past this k's sphere: zero partials (the vector step sums all nparts)
+    if (tid < NBT) {
+      const int t = tid / 16, b = tid % 16;
+      if (t < nt && b < tl.nb[t0 + t]) dpart[(size_t)tslot(tl, t0 + t, b) * nparts + gc] = R(0);
+    }
+    return;
+  }
+  const int Mm = min(Mq[k], Mq_max), Mr = Na + 2 * Mm;
+  const int wave = tid >> 6, lane = tid & 63;
+  if (tid < NBT) {
+    const int t = tid / 16, b = tid % 16;
+    ss[tid] = (t < nt && b < tl.nb[t0 + t]) ? tslot(tl, t0 + t, b) : -1;
+  }
+  for (int i = tid; i < GT * NBT; i += UKW_NT) red[i] = R(0);
+  __syncthreads();
+  const int npair = GT * nt;
+  typename M::acc c1r[PW], c1i[PW], c2r[PW], c2i[PW];
+#pragma unroll
+  for (int q = 0; q < PW; ++q)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c1r[q][v] = c1i[q][v] = c2r[q][v] = c2i[q][v] = R(0);
+  const cplx<R>* Wk = Wcg + (size_t)k * wk;
+  for (int r0 = 0; r0 < Mr; r0 += UKW_RC) {
+    // phi rows Na + 2m of this stage: m in [mlo, mhi)
+    const int mlo = r0 <= Na ? 0 : (r0 - Na + 1) / 2;
+    const int mhi = min(Mm, r0 + UKW_RC <= Na ? 0 : (r0 + UKW_RC - Na + 1) / 2);
+    for (int i = tid; i < UKW_RC * GB; i += UKW_NT) {
+      const int rr = i / GB, gg = i % GB, r = r0 + rr, g = g0 + gg;
+      Ws[rr * LW + gg] = (r < Mr && g < n) ? Wk[(size_t)r * nb_max + g] : mk<R>(0, 0);
+    }
+    for (int i = tid; i < NBT * UKW_RC; i += UKW_NT) {
+      const int b = i / UKW_RC, rr = i % UKW_RC, r = r0 + rr, slot = ss[b];
+      Gs[b * LG + rr] = (slot >= 0 && r < Mr) ? gam[(size_t)slot * cstride + r] : mk<R>(0, 0);
+    }
+    for (int i = tid; i < NBT * (UKW_RC / 2); i += UKW_NT) {
+      const int b = i / (UKW_RC / 2), mm = i % (UKW_RC / 2), m = mlo + mm, slot = ss[b];
+      As[b * LA + mm] = (slot >= 0 && m < mhi) ? gam[(size_t)slot * cstride + Na + 2 * m + 1]
+                                               : mk<R>(0, 0);
+    }
+    __syncthreads();
+    // Ap: the 16 rows of the stage, 4 per product
+#pragma unroll 1
+    for (int j = 0; j < UKW_RC / 4; ++j) {
+      const int rr = 4 * j + (lane >> 4);
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int pr = wave + 8 * q;
+        if (pr < npair) {
+          const int bt = pr / GT, gt = pr - bt * GT;
+          const cplx<R> ga = Gs[(16 * bt + (lane & 15)) * LG + rr];
+          const cplx<R> wb = Ws[rr * LW + 16 * gt + (lane & 15)];
+          c1r[q] = M::mac(ga.x, wb.x, c1r[q]);
+          c1r[q] = M::mac(-ga.y, wb.y, c1r[q]);
+          c1i[q] = M::mac(ga.x, wb.y, c1i[q]);
+          c1i[q] = M::mac(ga.y, wb.x, c1i[q]);
+        }
+      }
+    }
+    // p: the phi rows of the stage (at most 8), 4 per product
+    for (int mb = mlo; mb < mhi; mb += 4) {
+      const int m = mb + (lane >> 4);
+      const bool ok = m < mhi;
+      const int rr = Na + 2 * m - r0;
+#pragma unroll
+      for (int q = 0; q < PW; ++q) {
+        const int pr = wave + 8 * q;
+        if (pr < npair) {
+          const int bt = pr / GT, gt = pr - bt * GT;
+          const cplx<R> aa = ok ? As[(16 * bt + (lane & 15)) * LA + (m - mlo)] : mk<R>(0, 0);
+          const cplx<R> wb = ok ? Ws[rr * LW + 16 * gt + (lane & 15)] : mk<R>(0, 0);
+          c2r[q] = M::mac(aa.x, wb.x, c2r[q]);
+          c2r[q] = M::mac(-aa.y, wb.y, c2r[q]);
+          c2i[q] = M::mac(aa.x, wb.y, c2i[q]);
+          c2i[q] = M::mac(aa.y, wb.x, c2i[q]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // Ap = w~ + ..., p = p~ + ..., and <p, Ap> summed over the 16 lanes of each
+  // band row, then over the g tiles
+#pragma unroll
+  for (int q = 0; q < PW; ++q) {
+    const int pr = wave + 8 * q;
+    if (pr >= npair) continue;
+    const int bt = pr / GT, gt = pr - bt * GT;
+    const int g = g0 + 16 * gt + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = 16 * bt + M::row(lane, v);
+      const int slot = ss[b];
+      R d = 0;
+      if (slot >= 0 && g < n) {
+        const size_t o = (size_t)slot * nb_max + g;
+        const cplx<R> ap = cadd<R>(Wv[o], mk<R>(c1r[q][v], c1i[q][v]));
+        const cplx<R> pn = cadd<R>(P[o], mk<R>(c2r[q][v], c2i[q][v]));
+        Wv[o] = ap;
+        P[o] = pn;
+        d = pn.x * ap.x + pn.y * ap.y;
+      }
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) d += __shfl_xor(d, o, 64);
+      if ((lane & 15) == 0) red[gt * NBT + b] = d;
+    }
+  }
+  __syncthreads();
+  if (tid < NBT && ss[tid] >= 0) {
+    R v = red[tid];
+#pragma unroll
+    for (int gt = 1; gt < GT; ++gt) v += red[gt * NBT + tid];
+    dpart[(size_t)ss[tid] * nparts + gc] = v;
+  }
+}
+
 // alpha = rz / <p, Ap> from the update's partials (every block of a slot
 // forms the same sum in the same order; block 0 records alpha and, on a
 // breakdown, takes the slot out of the active set), then
@@ -397,6 +550,7 @@ __device__ void compact_block(const CgCompact& cp, const int* active, int* sh) {
       t += (na[k] + BT - 1) / BT;
     }
     tb[nk] = t;
+    if (cp.ktb) cp.ktb[nk] = t;
     cp.cnt[0] = a;
     cp.cnt[1] = t;
     if (cp.hist) {
@@ -414,6 +568,7 @@ __device__ void compact_block(const CgCompact& cp, const int* active, int* sh) {
   }
   __syncthreads();
   for (int k = tid; k < nk; k += CT) {
+    if (cp.ktb) cp.ktb[k] = tb[k];
     for (int t = tb[k]; t < tb[k + 1]; ++t) {
       const int o = (t - tb[k]) * BT;
       cp.ctk[t] = k;
@@ -554,12 +709,31 @@ void cg_combine(const Slots& sl, int Na, const int* Mq, int Mq_max, const cplx<R
   IKR_HIP(hipGetLastError());
 }
 
+constexpr int UKW_GB = 64;     // coefficients per block of the k-wide update
+
+bool cg_update_kwide(int Mrows, const KTileRange& kr) {
+  return kr.t0 && kr.nk > 0 && kr.ktmax <= 5 && !(kernel_paths() & PATH_VECTOR_GRAM) &&
+         (Mrows > 64 || (kernel_paths() & PATH_KWIDE));
+}
+
+int cg_update_parts(int nb_max, int Mrows, const KTileRange& kr) {
+  return cg_update_kwide(Mrows, kr) ? (nb_max + UKW_GB - 1) / UKW_GB : update_nblocks(nb_max);
+}
+
 template <typename R>
 void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, size_t wk,
                int Na, const int* Mq, int Mq_max, const cplx<R>* gam, int cstride,
-               cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st) {
+               cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st, const KTileRange& kr) {
   if (tl.n <= 0) return;
   IKR_CHECK(Na + 2 * Mq_max <= cstride, 1, "cg_update: row count");
+  if (cg_update_kwide(Na + 2 * Mq_max, kr)) {
+    const int nparts = (nb_max + UKW_GB - 1) / UKW_GB;
+    hipLaunchKernelGGL((cg_update_kw_kernel<R, 5, UKW_GB>), dim3(round8(nparts * kr.nk)),
+                       dim3(UKW_NT), 0, st, tl, kr, nb, nb_max, Wcg, wk, Na, Mq, Mq_max, gam,
+                       cstride, Wv, P, dpart, nparts);
+    IKR_HIP(hipGetLastError());
+    return;
+  }
   const int ngb = update_nblocks(nb_max);
   const int blocks = ngb * tl.n;
   // FP64 caps the band group at 8 (16 would leave one wavefront per SIMD)
@@ -580,12 +754,12 @@ void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, s
 
 template <typename R>
 void cg_step2(const Slots& sl, const int* nb, const double* kin, int nb_max, const R* dpart,
-              const R* rz, R* alpha, int* active, const R* pshift, cplx<R>* x, cplx<R>* r,
-              const cplx<R>* p, cplx<R>* w, R* rpart, R* zpart, hipStream_t st) {
+              int nup, const R* rz, R* alpha, int* active, const R* pshift, cplx<R>* x,
+              cplx<R>* r, const cplx<R>* p, cplx<R>* w, R* rpart, R* zpart, hipStream_t st) {
   if (sl.n <= 0) return;
   IKR_CHECK(rpart != dpart, 1, "cg_step2: the residual partials must not overwrite <p, Ap>");
   hipLaunchKernelGGL((cg_step2_kernel<R>), dim3(cg_vec_blocks(nb_max), sl.n), dim3(NT), 0, st,
-                     sl, nb, kin, nb_max, update_nblocks(nb_max), dpart, rz, alpha, active,
+                     sl, nb, kin, nb_max, nup, dpart, rz, alpha, active,
                      pshift, x, r, p, w, rpart, zpart);
   IKR_HIP(hipGetLastError());
 }
@@ -635,7 +809,8 @@ constexpr size_t CG_END_FUSED_MAX = 16 * (size_t)CT;
 template <typename R>
 void cg_end(const Slots& sl, int nparts, const R* rpart, const R* zpart, const CgScalars<R>& cs,
             int* active, const CgCompact& cp, hipStream_t st) {
-  if ((size_t)std::max(sl.n, 0) * nparts > CG_END_FUSED_MAX) {
+  if ((size_t)std::max(sl.n, 0) * nparts > CG_END_FUSED_MAX ||
+      (kernel_paths() & PATH_SPLIT_END)) {
     cg_finish<R>(sl, nparts, rpart, zpart, cs, active, 0, st);
     cg_compact(cp, active, st);
     return;
@@ -657,10 +832,10 @@ void cg_end(const Slots& sl, int nparts, const R* rpart, const R* zpart, const C
                               hipStream_t);                                                    \
   template void cg_update<R>(const Tiles&, const int*, int, const cplx<R>*, size_t, int,       \
                              const int*, int, const cplx<R>*, int, cplx<R>*, cplx<R>*, R*,     \
-                             hipStream_t);                                                     \
-  template void cg_step2<R>(const Slots&, const int*, const double*, int, const R*, const R*,  \
-                            R*, int*, const R*, cplx<R>*, cplx<R>*, const cplx<R>*, cplx<R>*,  \
-                            R*, R*, hipStream_t);                                              \
+                             hipStream_t, const KTileRange&);                                  \
+  template void cg_step2<R>(const Slots&, const int*, const double*, int, const R*, int,       \
+                            const R*, R*, int*, const R*, cplx<R>*, cplx<R>*, const cplx<R>*,  \
+                            cplx<R>*, R*, R*, hipStream_t);                                    \
   template void cg_zero<R>(const Slots&, int, cplx<R>*, cplx<R>*, hipStream_t);               \
   template void cg_axpy<R>(const Slots&, const int*, int, R, const cplx<R>*, cplx<R>*,         \
                            hipStream_t);                                                       \

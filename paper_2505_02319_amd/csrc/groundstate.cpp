@@ -137,7 +137,7 @@ void compute_ground_state(System& s) {
   const int nblk = std::min(MAXM - 1, nbn + std::max(8, nbn / 2));
   const int ns = nk * nblk;
   const double tol = 1e-11;
-  const int degree = 14, max_outer = 400;
+  const int degree = 24, max_outer = 400;
   const bool verbose = std::getenv("IKR_VERBOSE") != nullptr;
 
   // slots (k, i) and tiles of <= BT per k
@@ -150,10 +150,17 @@ void compute_ground_state(System& s) {
       ts.push_back(k * nblk + i0);
       tn.push_back(std::min(BT, nblk - i0));
     }
-  DBuf<int> dsk, dtk, dts, dtn, dM;
+  DBuf<int> dsk, dtk, dts, dtn, dM, dkt0;
   dsk.upload(sk, st); dtk.upload(tk, st); dts.upload(ts, st); dtn.upload(tn, st);
   dM.upload(std::vector<int>(nk, nblk), st);
   Tiles tl{(int)tk.size(), dtk.get(), dts.get(), dtn.get()};
+  const int tpk = (nblk + BT - 1) / BT;   // tiles per k
+  {
+    std::vector<int> kt0(nk + 1);
+    for (int k = 0; k <= nk; ++k) kt0[k] = k * tpk;
+    dkt0.upload(kt0, st);
+  }
+  const KTileRange kr{nk, dkt0.get(), tpk};
   Slots sl{ns, dsk.get(), nullptr};
 
   const size_t vec = (size_t)ns * nbm;
@@ -165,7 +172,7 @@ void compute_ground_state(System& s) {
   T2.alloc((size_t)ns * s.L.C * s.ncol_max);
   coef.alloc((size_t)ns * MAXM);
   pcoef.alloc((size_t)ns * MAXM);
-  part.alloc(gram_part_elems(tl.n, nbm, std::max(nblk, s.natoms)));
+  part.alloc(gram_part_elems(tl.n, nbm, std::max(nblk, s.natoms), nk));
   DBuf<double> dshift, dal, dbe, dlam, rpart;
   dshift.alloc(ns); dal.alloc(ns); dbe.alloc(ns); dlam.alloc(ns);
   const int nrb = vec_nblocks(nbm);
@@ -189,7 +196,7 @@ void compute_ground_state(System& s) {
   // G[k][m][j] = <Y_m, X_j> per k (host, nblk x nblk per k)
   auto gram_host = [&](const cd* Yw, const cd* Xs) {
     gram<double>(tl, s.d_nb.get(), nbm, dM.get(), nblk, Yw, wk, nbm, Xs, nbm, part.get(),
-                 coef.get(), MAXM, st);
+                 coef.get(), MAXM, st, nullptr, kr);
     std::vector<cd> c((size_t)ns * MAXM);
     IKR_HIP(hipMemcpyAsync(c.data(), coef.get(), c.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
     IKR_HIP(hipStreamSynchronize(st));
@@ -239,7 +246,11 @@ void compute_ground_state(System& s) {
     IKR_HIP(hipMemcpyAsync(A.get(), h.data(), vec * sizeof(cd), hipMemcpyHostToDevice, st));
     IKR_HIP(hipStreamSynchronize(st));
   }
-  // Upper bound of the spectrum of every H_k: max kinetic + max|V| + D sum |p|^2.
+  // Upper bound of the spectrum of every H_k (Weyl): max kinetic + max V +
+  // D ||P_k^H P_k|| (D > 0), the last bounded by the largest Gershgorin row
+  // sum of the projectors' Gram matrix (natoms x natoms, nearly the identity
+  // for well-separated atoms) or its trace.  A tight bound makes the filter
+  // sharper.
   double bup = 0;
   {
     std::vector<double> v((size_t)s.ng);
@@ -248,14 +259,38 @@ void compute_ground_state(System& s) {
     if (s.natoms)
       IKR_HIP(hipMemcpyAsync(pr.data(), s.d_proj.get(), pr.size() * sizeof(cd), hipMemcpyDeviceToHost, st));
     IKR_HIP(hipStreamSynchronize(st));
-    double vmax = 0;
-    for (double x : v) vmax = std::max(vmax, std::fabs(x));
+    double vmax = -1e300;
+    for (double x : v) vmax = std::max(vmax, x);
+    const int na = s.natoms;
     for (int k = 0; k < nk; ++k) {
-      double kmax = 0, pn = 0;
+      double kmax = 0;
       for (double x : s.kp[k].kin) kmax = std::max(kmax, x);
-      for (size_t i = (size_t)k * s.natoms * nbm; i < (size_t)(k + 1) * s.natoms * nbm; ++i)
-        pn += pr[i].x * pr[i].x + pr[i].y * pr[i].y;
-      bup = std::max(bup, kmax + vmax + std::fabs(s.dnl) * pn);
+      double nl = 0;
+      if (na > 0 && s.dnl > 0) {
+        std::vector<cd> G((size_t)na * na, mk<double>(0, 0));
+        const cd* P = pr.data() + (size_t)k * na * nbm;
+        double tr = 0;
+        for (int a = 0; a < na; ++a)
+          for (int b = 0; b < na; ++b) {
+            double re = 0, im = 0;
+            for (int g = 0; g < s.kp[k].nb; ++g) {
+              const cd x = P[(size_t)a * nbm + g], y = P[(size_t)b * nbm + g];
+              re += x.x * y.x + x.y * y.y;
+              im += x.x * y.y - x.y * y.x;
+            }
+            G[(size_t)a * na + b] = mk<double>(re, im);
+            if (a == b) tr += re;
+          }
+        double gersh = 0;   // largest eigenvalue <= max row sum of |G| (Gershgorin)
+        for (int a = 0; a < na; ++a) {
+          double row = 0;
+          for (int b = 0; b < na; ++b)
+            row += std::hypot(G[(size_t)a * na + b].x, G[(size_t)a * na + b].y);
+          gersh = std::max(gersh, row);
+        }
+        nl = s.dnl * std::min(gersh, tr);
+      }
+      bup = std::max(bup, kmax + std::max(vmax, 0.0) + nl);
     }
     bup *= 1.01;
   }

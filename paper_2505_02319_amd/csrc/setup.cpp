@@ -420,6 +420,17 @@ void finish_setup(System& s) {
   s.d_tile_nb.upload(s.tile_nb, st);
   s.tiles = Tiles{(int)s.tile_k.size(), s.d_tile_k.get(), s.d_tile_slot0.get(),
                   s.d_tile_nb.get()};
+  {
+    std::vector<int> kt0(nk + 1, 0);
+    s.ktmax = 0;
+    for (int k = 0; k < nk; ++k) {
+      const int nt = (s.nocc_k[k] + BT - 1) / BT;
+      kt0[k + 1] = kt0[k] + nt;
+      s.ktmax = std::max(s.ktmax, nt);
+    }
+    s.d_kt0.upload(kt0, st);
+    s.d_ktb.alloc(nk + 1);
+  }
 
   // -- work space (FP64 CG)
   const size_t vec = (size_t)s.J * s.nb_max;
@@ -430,13 +441,14 @@ void finish_setup(System& s) {
   const int mrows = std::max(s.nocc_max, s.natoms) + 1;
   w.coefA.alloc((size_t)s.J * MAXM);
   w.coefB.alloc((size_t)s.J * MAXM);
-  w.part.alloc(gram_part_elems(s.tiles.n, s.nb_max, std::max({mrows, s.nbands, s.mcg})));
+  w.part.alloc(gram_part_elems(s.tiles.n, s.nb_max, std::max({mrows, s.nbands, s.mcg}), nk));
   w.craw.alloc((size_t)s.J * s.mcg);
   w.gam.alloc((size_t)s.J * s.mcg);
   w.rpart.alloc((size_t)s.J * vec_nblocks(s.nb_max));
   w.zpart.alloc((size_t)s.J * vec_nblocks(s.nb_max));
   w.rz.alloc(s.J); w.alpha.alloc(s.J); w.beta.alloc(s.J); w.rnorm2.alloc(s.J);
-  w.dpart.alloc((size_t)s.J * std::max(update_nblocks(s.nb_max), vec_nblocks(s.nb_max)));
+  w.dpart.alloc((size_t)s.J * std::max({update_nblocks(s.nb_max), vec_nblocks(s.nb_max),
+                                         (s.nb_max + 63) / 64}));
   w.pshift.alloc(s.J); w.shift.alloc(s.J);
   s.d_active.alloc(s.J);
   s.d_list.alloc(s.J);

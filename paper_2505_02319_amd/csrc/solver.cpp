@@ -272,10 +272,12 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
                   s.d_iters.get(), s.d_counters.get(), s.d_counters.get() + 1,
                   min_iter, max_iter};
   const int nvb = vec_nblocks(nbm);
+  const int nup = cg_update_parts(nbm, Mrows, s.krange_compact());
   int* cnt = s.d_cnt.get();
   CgCompact cp{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_slot_k.get(), J,
                s.d_list.get(), s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), cnt,
-               s.d_hist.get(), max_iter + 1, s.d_counters.get() + 2, s.d_hcnt};
+               s.d_hist.get(), max_iter + 1, s.d_counters.get() + 2, s.d_hcnt,
+               s.d_ktb.get()};
   // host bound on the tiles of the member set
   int nct = 0;
   for (int k = 0; k < s.nk; ++k) {
@@ -320,18 +322,19 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
     // q, a, h = W_k^H p~ ; update coefficients ; Ap and p = Q p~ ; <p, Ap>
     KTimer::begin(kid<R>(K_GRAM), st);
     const int nsc = gram_partials<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm,
-                                     w.p.get(), nbm, w.part.get(), st);
+                                     w.p.get(), nbm, w.part.get(), st, nullptr,
+                                     s.krange_compact());
     KTimer::end(kid<R>(K_GRAM), st, 0.0);
     gram_reduce<R>(ctl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
     cg_combine<R>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
                   w.sT.get(), nbn, R(s.dnl), w.gam.get(), st);
     KTimer::begin(kid<R>(K_UPDATE), st);
     cg_update<R>(ctl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), s.mcg,
-                 w.w.get(), w.p.get(), w.dpart.get(), st);
+                 w.w.get(), w.p.get(), w.dpart.get(), st, s.krange_compact());
     KTimer::end(kid<R>(K_UPDATE), st, 0.0);
     // alpha ; x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, <r, z>
     KTimer::begin(kid<R>(K_CG_STEP), st);
-    cg_step2<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.dpart.get(), w.rz.get(), w.alpha.get(),
+    cg_step2<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.dpart.get(), nup, w.rz.get(), w.alpha.get(),
                 s.d_active.get(), w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(),
                 w.rpart.get(), w.zpart.get(), st);
     KTimer::end(kid<R>(K_CG_STEP), st, 0.0);
@@ -355,13 +358,22 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
       if (use_graph) {
         const int na = pow2_cap(nact, J), nt = pow2_cap(nct, s.tiles.n);
         const CgGraphs::Key key{(long long)sizeof(R), na, nt, (long long)(intptr_t)dMq,
-                                min_iter, max_iter};
+                                min_iter, max_iter, kernel_paths()};
         const hipGraphExec_t ge = s.graphs.get(key, st, [&] { iteration(na, nt); });
         IKR_HIP(hipGraphLaunch(ge, st));
       } else {
         iteration(nact, nct);
       }
       iters = it + 1;
+      if (s.cg_plain) {   // reference loop: the host waits for every iteration's count
+        IKR_HIP(hipMemcpyAsync(s.h_cnt.p, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+        IKR_HIP(hipStreamSynchronize(st));
+        nact = s.h_cnt.p[0];
+        nct = s.h_cnt.p[1];
+        s.h_cnt.p[0] = s.h_cnt.p[1] = -1;
+        if (nact == 0) break;
+        continue;
+      }
       // the compaction of iteration it writes its counts to h_cnt[2 (it & 1)]
       IKR_HIP(hipEventRecord(ev[it & 1], st));
       if (it >= 1) {
@@ -450,7 +462,7 @@ void apply_sternheimer_op(System& s, const std::vector<int>& member, const int* 
   int* cnt = s.d_cnt.get();
   cg_compact(CgCompact{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_slot_k.get(), J,
                        s.d_list.get(), s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), cnt,
-                       nullptr, 0, s.d_counters.get() + 2},
+                       nullptr, 0, s.d_counters.get() + 2, nullptr, s.d_ktb.get()},
              s.d_active.get(), st);
   Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
   Tiles ctl{nct, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(), cnt + 1};
@@ -462,12 +474,13 @@ void apply_sternheimer_op(System& s, const std::vector<int>& member, const int* 
   launch_col_fwd<double>(s.geom, s.fft, sl, w.T2.get(), w.w.get(), nbm, w.p.get(), w.shift.get(),
                          1.0 / s.ng, st);
   const int nsc = gram_partials<double>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, w.wcg.get(), wk,
-                                        nbm, w.p.get(), nbm, w.part.get(), st);
+                                        nbm, w.p.get(), nbm, w.part.get(), st, nullptr,
+                                        s.krange_compact());
   gram_reduce<double>(ctl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
   cg_combine<double>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
                      w.sT.get(), nbn, s.dnl, w.gam.get(), st);
   cg_update<double>(ctl, s.d_nb.get(), nbm, w.wcg.get(), wk, Na, dMq, Mq_max, w.gam.get(),
-                    s.mcg, w.w.get(), w.p.get(), w.dpart.get(), st);
+                    s.mcg, w.w.get(), w.p.get(), w.dpart.get(), st, s.krange_compact());
 }
 
 }  // namespace
@@ -505,7 +518,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
   }
   // M[j][m] = <phi_m, t_j>
   gram<double>(s.tiles, s.d_nb.get(), nbm, dMq, Mq_max, s.d_phi.get(), phik,
-               nbm, w.r.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+               nbm, w.r.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st, nullptr, s.krange());
   const std::vector<double2> M = download(w.coefA.get(), (size_t)J * MAXM, st);
   if (ex && ex->m_out) *ex->m_out = M;
 
@@ -566,12 +579,25 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
       if (ex && ex->tol_relative) tol_slot[j] *= bn[j];
       tol_slot[j] = std::max(tol_slot[j], TOL_FLOOR * bn[j]);
     }
-    if (precision == 1)
+    if (precision == 1 && !s.cg_plain)
       for (int j = 0; j < J; ++j)
         if (tol_slot[j] >= theta * bn[j]) { m32[j] = 1; m64[j] = 0; ++n32; }
   }
-  const CgOut o64 = run_cg<double>(s, s.w64, w.r.get(), m64, tol_slot, min_iter, max_iter,
-                                   dMq, Mq_max, dMcg);
+  CgOut o64;
+  if (s.cg_plain) {
+    // plain FP64 reference: the k-points one after the other
+    for (int k = 0; k < s.nk; ++k) {
+      std::vector<int> mk_(J, 0);
+      for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) mk_[j] = 1;
+      const CgOut ok = run_cg<double>(s, s.w64, w.r.get(), mk_, tol_slot, min_iter, max_iter,
+                                      dMq, Mq_max, dMcg);
+      o64.n_ham += ok.n_ham;
+      o64.noconv += ok.noconv;
+    }
+  } else {
+    o64 = run_cg<double>(s, s.w64, w.r.get(), m64, tol_slot, min_iter, max_iter, dMq, Mq_max,
+                         dMcg);
+  }
   res.n_ham64 = o64.n_ham;
   res.noconv = o64.noconv;
   if (n32 > 0) {
@@ -648,7 +674,7 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
 
   // final projection and occupied part: dphi = x - Phi Phi^H x + Phi dP
   gram<double>(s.tiles, s.d_nb.get(), nbm, dMq, Mq_max, s.d_phi.get(), phik,
-               nbm, w.x.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st);
+               nbm, w.x.get(), nbm, w.part.get(), w.coefA.get(), MAXM, st, nullptr, s.krange());
   IKR_HIP(hipMemcpyAsync(w.coefB.get(), dp.data(), dp.size() * sizeof(double2),
                          hipMemcpyHostToDevice, st));
   UpdTerm<double> phiB{s.d_phi.get(), phik, nbm, dMq, w.coefB.get(), MAXM, 1.0, Mq_max};

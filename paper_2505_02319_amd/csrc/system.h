@@ -78,7 +78,7 @@ template <typename T> struct HBuf {
 // and grid bounds, and the private stream they are captured and replayed on
 // (a caller's stream may be the legacy default stream, which cannot capture).
 struct CgGraphs {
-  using Key = std::array<long long, 6>;
+  using Key = std::array<long long, 7>;
   hipStream_t stream = nullptr;
   std::map<Key, hipGraphExec_t> exec;
   long long captures = 0;
@@ -167,6 +167,11 @@ struct System {
   DBuf<int> d_tile_k, d_tile_slot0, d_tile_nb;
   Tiles tiles{};
   int nocc_max = 0;
+  DBuf<int> d_kt0;                 // [nk + 1] first tile of each k in `tiles`
+  DBuf<int> d_ktb;                 // [nk + 1] the same for the compacted active tiles
+  int ktmax = 0;                   // most tiles of one k
+  KTileRange krange() const { return KTileRange{nk, d_kt0.get(), ktmax}; }
+  KTileRange krange_compact() const { return KTileRange{nk, d_ktb.get(), ktmax}; }
 
   // caches
   DBuf<double2> d_Tphi;            // [J][C][ncol_max] column transforms of occupied phi
@@ -194,6 +199,8 @@ struct System {
   DBuf<double> d_tol2;
   std::vector<double> knorm_hist;
   int cg_graph = 0;                // 1: CG iterations replayed from captured graphs
+  int cg_plain = 0;                // 1: plain FP64 reference: one k-point per CG run,
+                                   //    the host reads the live count every iteration
   CgGraphs graphs;
 
   std::string name;

@@ -141,6 +141,12 @@ def _make_configs() -> Dict[str, SystemSpec]:
                            [0.5, 0.5, 0.5], [0.75, 0.75, 0.625]]),
         amp=np.full(4, 4.0), ecut=5.0, fft=(20, 20, 36), kgrid=(1, 1, 2),
         nocc=8, nextra=4, temperature=0.0, xc=1)
+    # More than 64 projection rows on a small grid (natoms + 2 N_occ = 68, or
+    # 80 with the extra bands): closed free-electron shells at 33 bands.
+    c["wide"] = c["cfg1"].with_(name="wide", nocc=33, nextra=6)
+    c["wide_k"] = c["wide"].with_(name="wide_k", kgrid=(1, 1, 2))
+    # 116 rows (57 occupied bands, the next closed shell; 128 with the extras)
+    c["wider"] = c["cfg1"].with_(name="wider", nocc=57, nextra=6)
     # Tiny cells (N_g = 12^3) on which chi0 and E are formed as dense
     # matrices by the oracle.
     c["tiny"] = c["cfg1"].with_(name="tiny", ecut=3.0, fft=(12, 12, 12))
