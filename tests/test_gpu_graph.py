@@ -69,4 +69,4 @@ def test_batching_option_is_validated():
     rs, osys, ogs, perms = gpu_system("tiny")
     b = to_dev(random_field(osys.spec, 2))
     with pytest.raises(IkrError):
-        rs.solve(b, default_opts(batching=2))
+        rs.solve(b, default_opts(batching=3))
