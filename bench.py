@@ -1,13 +1,23 @@
 #!/usr/bin/env python3
 """Throughput of the inexact-GMRES Dyson solve on one MI355X.
 
-One step = one full solve of E drho = b (Alg. 1, grt strategy, tau = 1e-8 ||b||,
-m = 20, s0 = 1, x0 = 0; computed unoccupied bands by sum over states; FP32
-Sternheimer CG where the band's tolerance allows) on the 8-atom cubic cell (a = 20.52 bohr, Ecut = 15 Ha,
+One step = one full solve of E drho = b (Alg. 1 on the Kerker-preconditioned
+equation T E drho = T b, grt strategy, tau = 1e-8 ||b||, m = 20, s0 = 1,
+x0 = 0; computed unoccupied bands by sum over states; FP32 Sternheimer CG
+where the band's tolerance allows; the true residual ||b - E drho|| of the
+same solve is reported) on the 8-atom cubic cell (a = 20.52 bohr, Ecut = 15 Ha,
 FFT 48^3, 2x2x2 k-points, 16 occupied + 4 extra bands, Hartree + Slater
 kernel), with b the seeded smooth random field.  Inputs and the ground state
 (computed by the library's own GPU eigensolver during setup) are resident in
 HBM before the timed region.  Prints one JSON line.
+
+Beside the headline (untimed by the step clock, reported in the same line):
+the plain FP64 reference path (k-points one after the other, a host read per
+CG iteration) and the speed-up over it, the true residuals and the paper's
+efficiency eta = -log10(||r_end|| / ||b||) / N_ham of several strategies with
+and without the Kerker preconditioner, eta_rel against D10, and one timed
+solve on the 32-atom smeared cell (60 x 108^2, 27 k-points, 64 + 8 bands) with
+its setup time, per-kernel times and true residual.
 """
 import argparse
 import json
@@ -75,6 +85,8 @@ def main():
     ap.add_argument("--strategy", default="grt")
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--schur", type=int, default=1)
+    ap.add_argument("--kerker", type=int, default=1,
+                    help="1: Kerker-preconditioned GMRES (the paper's P-strategies)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-checks", action="store_true",
                     help="skip the untimed accuracy and FP64 comparison solves")
@@ -87,10 +99,29 @@ def main():
     ap.add_argument("--gradient", action="store_true",
                     help="time the forward solve and the adjoint backward (dL/db, dL/dA) "
                          "and check them against central differences")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="only summarise a rocprofv3 kernel-trace CSV: durations of the last "
+                         "--trace-last dispatches whose name contains --trace-kernel")
+    ap.add_argument("--pmc-summary", metavar="CSV",
+                    help="only summarise a rocprofv3 --pmc counter-collection CSV: the mean "
+                         "per-dispatch counter value over the last --trace-last dispatches "
+                         "whose name contains --trace-kernel")
+    ap.add_argument("--trace-kernel", default="plane_hv_kernel<double")
+    ap.add_argument("--trace-last", type=int, default=0)
+    ap.add_argument("--large-cell", default="cfg4",
+                    help="workload of the one-solve large-cell leg ('none' to skip)")
+    ap.add_argument("--large-strategy", default="grt")
+    ap.add_argument("--large-kerker", type=int, default=1)
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary, args.trace_kernel, args.trace_last)
+        return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary, args.trace_kernel, args.trace_last)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the response path here is single-GPU "
-              "(k-point sharding is described in DESIGN.md); use --gpus 1", file=sys.stderr)
+              "(k-point sharding across GPUs is not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     # setup and eigensolver progress on stderr (large cells take minutes)
@@ -118,7 +149,7 @@ def main():
         f"residual {info['gs_residual']:.1e}, min gap {min(info['gaps']):.2e}")
     b = torch.from_numpy(random_field(spec, B_SEED)).cuda()
     opts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
-                        precision=args.precision, schur=args.schur)
+                        precision=args.precision, schur=args.schur, kerker=args.kerker)
 
     # warmup; the last warmup step times every hot kernel to find the dominant
     # one, whose launches alone are then timed live inside the timed region
@@ -156,7 +187,8 @@ def main():
     graph = None
     if args.graph_steps > 0:
         gopts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
-                             precision=args.precision, schur=args.schur, batching=1)
+                             precision=args.precision, schur=args.schur, batching=1,
+                             kerker=args.kerker)
         rs.solve(b, gopts)                       # captures the graphs
         torch.cuda.synchronize()
         t_g = time.perf_counter()
@@ -169,9 +201,11 @@ def main():
         log(f"graph replay: {sec:.3f} s per solve, N_ham {stg['n_ham']}")
 
     bnorm = float(torch.linalg.norm(b))
-    true_rel, fp64, n32, other = None, None, None, None
+    true_rel, fp64, n32, other, plain, strategies = None, None, None, None, None, None
     if not args.no_checks:
         true_rel, fp64, n32, other = accuracy_checks(rs, b, bnorm, args, default_opts)
+        plain = plain_fp64_leg(rs, b, bnorm, args, default_opts)
+        strategies = strategy_legs(rs, b, bnorm, args, default_opts)
 
     launches, ms, by = prof[dom]
     achieved = by / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -194,7 +228,6 @@ def main():
         "dtype": "f64" if args.precision == 0 else "f32/f64",
         "fp64_cg_solve": fp64,
         "graph_replay_solve": graph,
-        "balanced_strategy_solve": other,
         "n_ham_fp32_per_solve": n32,
         "data": "synthetic",
         "config": {"workload": describe(spec, args), "global_batch": 1,
@@ -203,19 +236,24 @@ def main():
         "n_ham_per_solve": n_ham / args.steps,
         "gmres_iters_per_solve": gm / args.steps,
         "true_rel_residual": true_rel,
+        "plain_fp64_solve": plain,
+        "speedup_vs_plain_fp64": (plain["seconds"] / (elapsed / args.steps)) if plain else None,
+        "strategies": strategies,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(spec.name, dom),
-                     "avg_launch_us": 1e3 * ms / max(launches, 1),
+                     "avg_launch_us": 1e3 * ms / max(launches, 1), "launches": launches,
                      "bytes_per_launch": bytes_per_launch},
         "kernels_warmup_step": kernels,
         "setup_seconds": t_setup,
     }
+    rs.close()
+    if args.large_cell != "none":
+        out["large_cell_solve"] = large_cell_leg(torch, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(spec, n_ham / args.steps, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    rs.close()
 
 
 def gradient_bench(torch, spec, args):
@@ -283,7 +321,8 @@ def accuracy_checks(rs, b, bnorm, args, default_opts):
     same solve with the Sternheimer CG in FP64 throughout."""
     import torch
     vopts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
-                         precision=args.precision, schur=args.schur, want_true_residual=1)
+                         precision=args.precision, schur=args.schur, kerker=args.kerker,
+                         want_true_residual=1)
     xv, vst = rs.solve(b, vopts)
     bnorm = float(torch.linalg.norm(b))
     true_rel = vst["true_res"] / bnorm
@@ -291,27 +330,150 @@ def accuracy_checks(rs, b, bnorm, args, default_opts):
     # the same solve with the Sternheimer CG in FP64 throughout (untimed
     # reference for the mixed-precision error and speed-up)
     popts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1, precision=0,
-                         schur=args.schur, want_true_residual=1)
+                         schur=args.schur, kerker=args.kerker, want_true_residual=1)
     xp, pst = rs.solve(b, popts)
     fp64 = {"seconds": pst["seconds"], "n_ham": pst["n_ham"],
             "true_rel_residual": pst["true_res"] / bnorm,
             "rel_diff_vs_mixed": float(torch.linalg.norm(xv - xp) / torch.linalg.norm(xp))}
     log(f"fp64 CG: {pst['seconds']:.3f} s, true rel. residual {fp64['true_rel_residual']:.2e}")
-    # the paper's balanced strategy on the same solve (no accuracy guarantee,
-    # hence not the headline): its time and the true residual it reaches
     other = None
-    if args.strategy != "bal":
-        bopts = default_opts(strategy="bal", tol=1e-8, tol_is_relative=1,
-                             precision=args.precision, schur=args.schur)
-        rs.solve(b, bopts)
-        _, bst = rs.solve(b, bopts)
-        bopts.want_true_residual = 1
-        _, bst2 = rs.solve(b, bopts)
-        other = {"strategy": "bal", "seconds": bst["seconds"], "n_ham": bst["n_ham"],
-                 "true_rel_residual": bst2["true_res"] / bnorm}
-        log(f"bal: {bst['seconds']:.3f} s, N_ham {bst['n_ham']}, "
-            f"true rel. residual {other['true_rel_residual']:.2e}")
     return true_rel, fp64, vst["n_ham_fp32"], other
+
+
+def trace_summary(path, kernel, last):
+    """Durations of the last `last` dispatches (all if 0) of the kernels whose
+    name contains `kernel`, from a rocprofv3 --kernel-trace CSV; with the
+    bench run under the profiler and nothing launched after its timed steps,
+    these are the launches its HIP events timed."""
+    import csv
+    with open(path) as fh:
+        rows = list(csv.DictReader(fh))
+    cols = {c.lower(): c for c in rows[0]} if rows else {}
+    kn, ks, ke = cols["kernel_name"], cols["start_timestamp"], cols["end_timestamp"]
+    sel = sorted((r for r in rows if kernel in r[kn]), key=lambda r: int(r[ks]))
+    if last > 0:
+        sel = sel[-last:]
+    us = [(int(r[ke]) - int(r[ks])) * 1e-3 for r in sel]
+    print(json.dumps({"trace": os.path.basename(path), "kernel": kernel, "dispatches": len(us),
+                      "avg_us": sum(us) / max(len(us), 1), "min_us": min(us) if us else None,
+                      "max_us": max(us) if us else None,
+                      "names": sorted({r[kn] for r in sel})}), flush=True)
+
+
+def pmc_summary(path, kernel, last):
+    """Mean per-dispatch value of each counter in a rocprofv3 --pmc CSV over
+    the last `last` dispatches (all if 0) of the kernels whose name contains
+    `kernel` (values of one dispatch summed over their rows)."""
+    import csv
+    with open(path) as fh:
+        rows = list(csv.DictReader(fh))
+    cols = {c.lower(): c for c in rows[0]} if rows else {}
+    kn, dk = cols["kernel_name"], cols["dispatch_id"]
+    cn, cv = cols["counter_name"], cols["counter_value"]
+    per = {}
+    for r in rows:
+        if kernel in r[kn]:
+            per.setdefault(int(r[dk]), {}).setdefault(r[cn], 0.0)
+            per[int(r[dk])][r[cn]] += float(r[cv])
+    ids = sorted(per)
+    if last > 0:
+        ids = ids[-last:]
+    names = sorted({c for i in ids for c in per[i]})
+    mean = {c: sum(per[i].get(c, 0.0) for i in ids) / max(len(ids), 1) for c in names}
+    print(json.dumps({"pmc": os.path.basename(path), "kernel": kernel, "dispatches": len(ids),
+                      "mean_per_dispatch": mean}), flush=True)
+
+
+def plain_fp64_leg(rs, b, bnorm, args, default_opts):
+    """The plain FP64 reference path on the same solve: the Sternheimer CGs of
+    the k-points one after the other, the host reading the live count after
+    every CG iteration, FP64 throughout (solver option batching = 2)."""
+    import torch
+    popts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1, precision=0,
+                         schur=args.schur, kerker=args.kerker, batching=2)
+    rs.solve(b, popts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = rs.solve(b, popts)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    log(f"plain fp64 path: {sec:.3f} s, N_ham {st['n_ham']}")
+    return {"seconds": sec, "n_ham": st["n_ham"], "gmres_iters": st["gmres_iters"]}
+
+
+def strategy_legs(rs, b, bnorm, args, default_opts):
+    """N_ham, seconds, true residual and the paper's efficiency
+    eta = -log10(||r_end|| / ||r_0||) / N_ham (r_0 = b, x0 = 0; Sec. 4.1.3) of
+    the strategies with and without the Kerker preconditioner (Sec. 3.3), and
+    eta_rel against D10, all in the headline's precision."""
+    import math
+    out = {}
+    for name, strat, kerk in [("grt", "grt", 0), ("bal", "bal", 0), ("D10", "D10", 0),
+                              ("Pgrt", "grt", 1), ("Pbal", "bal", 1), ("PD10", "D10", 1)]:
+        o = default_opts(strategy=strat, tol=1e-8, tol_is_relative=1, precision=args.precision,
+                         schur=args.schur, kerker=kerk, want_true_residual=1)
+        _, st = rs.solve(b, o)
+        tr = st["true_res"] / bnorm
+        eta = -math.log10(tr) / st["n_ham"] if tr > 0 else None
+        out[name] = {"n_ham": st["n_ham"], "seconds": st["seconds"],
+                     "gmres_iters": st["gmres_iters"], "true_rel_residual": tr, "eta": eta}
+    ref = out["D10"]["eta"]
+    for v in out.values():
+        v["eta_rel_vs_D10"] = v["eta"] / ref if (v["eta"] and ref) else None
+    log("strategies: " + ", ".join(f"{k} N_ham {v['n_ham']} res {v['true_rel_residual']:.1e}"
+                                   for k, v in out.items()))
+    return out
+
+
+def large_cell_leg(torch, args):
+    """One timed solve on the large smeared cell (setup by the library's GPU
+    eigensolver, timed apart), with per-kernel times and its true residual."""
+    from paper_2505_02319_amd import (ResponseSystem, default_opts, profile_enable,
+                                      profile_query, profile_reset)
+    from workloads import B_SEED, config, random_field
+    spec = config(args.large_cell)
+    t0 = time.perf_counter()
+    rs = ResponseSystem(spec, ground_state="compute")
+    info = rs.setup_info()
+    t_setup = time.perf_counter() - t0
+    log(f"large cell {spec.name}: setup {t_setup:.1f} s, eigensolver steps {info['gs_iters']}")
+    b = torch.from_numpy(random_field(spec, B_SEED)).cuda()
+    bnorm = float(torch.linalg.norm(b))
+    o = default_opts(strategy=args.large_strategy, tol=1e-8, tol_is_relative=1, precision=1,
+                     schur=1, kerker=args.large_kerker)
+    profile_reset()
+    profile_enable(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    x, st = rs.solve(b, o)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t1
+    profile_enable(False)
+    prof = profile_query()
+    log(f"large cell solve: {sec:.2f} s, N_ham {st['n_ham']}, GMRES {st['gmres_iters']}")
+    # true residual ||b - E x|| with every Sternheimer CG at 1e-14 (Sec. 4.1.3)
+    ex, _ = rs.apply_dielectric(x, 1e-14, default_opts(strategy="fixed", precision=0))
+    true_rel = float(torch.linalg.norm(b - ex)) / bnorm
+    log(f"large cell true relative residual {true_rel:.2e}")
+    rs.close()
+    kernels = {k: {"launches": v[0], "ms": round(v[1], 1),
+                   "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
+               for k, v in prof.items() if v[0]}
+    return {"workload": describe_large(spec, args), "setup_seconds": t_setup,
+            "eigensolver_steps": info["gs_iters"], "seconds": sec, "solves_per_s": 1.0 / sec,
+            "n_ham": st["n_ham"], "n_ham_fp32": st["n_ham_fp32"], "gmres_iters": st["gmres_iters"],
+            "true_rel_residual": true_rel,
+            "note": "kernel times from HIP events on every hot launch of the timed solve",
+            "kernels": kernels}
+
+
+def describe_large(spec, args):
+    L = spec.lattice
+    return (f"{spec.name}: {len(spec.frac_pos)}-atom cell {L[0]:g}x{L[1]:g}x{L[2]:g} bohr, "
+            f"Ecut {spec.ecut:g} Ha, FFT {spec.fft[0]}x{spec.fft[1]}x{spec.fft[2]}, "
+            f"{spec.kgrid[0]}x{spec.kgrid[1]}x{spec.kgrid[2]} k, {spec.nocc}+{spec.nextra} bands, "
+            f"T {spec.temperature:g}, strategy {'P' if args.large_kerker else ''}"
+            f"{args.large_strategy}, mixed precision, tau 1e-8||b||")
 
 
 def describe(spec, args):
@@ -320,7 +482,9 @@ def describe(spec, args):
             f"Ecut {spec.ecut:g} Ha, FFT {spec.fft[0]}x{spec.fft[1]}x{spec.fft[2]}, "
             f"{spec.kgrid[0]}x{spec.kgrid[1]}x{spec.kgrid[2]} k, {spec.nocc}+{spec.nextra} bands, "
             f"T {spec.temperature:g}, K_H{' + Slater' if spec.xc else ''}, "
-            f"strategy {args.strategy}, extra bands by sum over states "
+            f"strategy {'P' if args.kerker else ''}{args.strategy} "
+            f"({'Kerker-preconditioned' if args.kerker else 'unpreconditioned'} GMRES), "
+            f"extra bands by sum over states "
             f"{'on' if args.schur else 'off'}, CG precision "
             f"{'mixed' if args.precision else 'fp64'}, m 20, tau 1e-8||b||")
 

@@ -711,9 +711,14 @@ void cg_combine(const Slots& sl, int Na, const int* Mq, int Mq_max, const cplx<R
 
 constexpr int UKW_GB = 64;     // coefficients per block of the k-wide update
 
+// The k-wide update only when forced: on the 60 x 108^2 cell, where the CG
+// batch keeps about 13 live bands per k-point on average, it took 12.2 ms per
+// FP64 launch against 7.3 ms for the tiled update (its 16-row stages wait on
+// their loads; the tiled kernel streams W with four rows in flight).
 bool cg_update_kwide(int Mrows, const KTileRange& kr) {
-  return kr.t0 && kr.nk > 0 && kr.ktmax <= 5 && !(kernel_paths() & PATH_VECTOR_GRAM) &&
-         (Mrows > 64 || (kernel_paths() & PATH_KWIDE));
+  (void)Mrows;
+  return kr.t0 && kr.nk > 0 && kr.ktmax <= 5 && (kernel_paths() & PATH_KWIDE) &&
+         !(kernel_paths() & PATH_VECTOR_GRAM);
 }
 
 int cg_update_parts(int nb_max, int Mrows, const KTileRange& kr) {

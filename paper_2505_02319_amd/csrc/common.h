@@ -70,6 +70,8 @@ struct Geom {
   const int* col_pq;     // [nk][ncol_max] plane index p*Q + q of the column
   const int* col_clo;    // [nk][ncol_max] first (signed) c index of the column
   const double* kin;     // [nk][nb_max] |G+k|^2/2, 0 beyond nb
+  const int* prow = nullptr;   // [nk][P] rows p of the plane that hold columns, ascending
+  const int* nprow = nullptr;  // [nk] their number
 };
 
 // Per-slot (band of the batch) metadata for batched kernels.  A launch

@@ -177,17 +177,30 @@ __global__ __launch_bounds__(NT) void col_kernel(
 }
 
 // ---------------------------------------------------------------- planes
+// rows (nullable): the nrows rows p that hold sphere columns.  The inverse
+// transform along q then skips the other rows (zero on input) and the
+// forward one along q skips them too (not read afterwards).
 template <typename R, int P, int Q, bool INV>
 __device__ __forceinline__ void fft2d(cplx<R>* pl, const cplx<R>* twP,
-                                      const cplx<R>* twQ) {
+                                      const cplx<R>* twQ, const int* rows = nullptr,
+                                      int nrows = P) {
   constexpr int LQ = Q + 1;
   if (INV) {
-    lds_fft<R, Q, NT, P, true>(pl, P, LQ, 1, twQ);
+    lds_fft<R, Q, NT, P, true>(pl, rows ? nrows : P, LQ, 1, twQ, rows);
     lds_fft<R, P, NT, Q, true>(pl, Q, 1, LQ, twP);
   } else {
     lds_fft<R, P, NT, Q, false>(pl, Q, 1, LQ, twP);
-    lds_fft<R, Q, NT, P, false>(pl, P, LQ, 1, twQ);
+    lds_fft<R, Q, NT, P, false>(pl, rows ? nrows : P, LQ, 1, twQ, rows);
   }
+}
+
+// The footprint rows of k-point k in LDS (rows[P]); returns their number,
+// or P (all rows) when the geometry has no row lists.
+template <int P>
+__device__ __forceinline__ int load_rows(const Geom& g, int k, int* rows) {
+  if (!g.prow) return P;
+  for (int i = threadIdx.x; i < P; i += NT) rows[i] = g.prow[(size_t)k * P + i];
+  return g.nprow[k];
 }
 
 // H psi local part: T -> inverse 2D -> * V -> forward 2D -> T.
@@ -199,6 +212,7 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
   constexpr int LQ = Q + 1;
   __shared__ cplx<R> pl[P * LQ];
   __shared__ cplx<R> sP[P], sQ[Q];
+  __shared__ int rows[P];
   load_tw<R, P>(sP, twP);
   load_tw<R, Q>(sQ, twQ);
   if (!row_live(s, blockIdx.y)) return;
@@ -208,6 +222,7 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
   const int k = s.k[slot];
   const int ncol = g.ncol[k];
   const int tid = threadIdx.x;
+  const int nrows = load_rows<P>(g, k, rows);
   for (int i = tid; i < P * LQ; i += NT) pl[i] = mk<R>(0, 0);
   __syncthreads();
   const int* pq = g.col_pq + (size_t)k * g.ncol_max;
@@ -228,7 +243,7 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
       if (pv[u] >= 0) pl[(pv[u] / Q) * LQ + (pv[u] % Q)] = tv[u];
   }
   __syncthreads();
-  fft2d<R, P, Q, true>(pl, sP, sQ);
+  fft2d<R, P, Q, true>(pl, sP, sQ, rows, nrows);
   const R* vp = V + (v_per_slot ? (size_t)slot * g.C * P * Q : 0) + (size_t)c * P * Q;
   constexpr int NV = (P * Q + NT - 1) / NT;
   R vv[NV];
@@ -246,7 +261,7 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
     }
   }
   __syncthreads();
-  fft2d<R, P, Q, false>(pl, sP, sQ);
+  fft2d<R, P, Q, false>(pl, sP, sQ, rows, nrows);
   for (int col = tid; col < ncol; col += NT) {
     const int v = pq[col];
     Tout[tb + col] = pl[(v / Q) * LQ + (v % Q)];

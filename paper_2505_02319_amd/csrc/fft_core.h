@@ -182,11 +182,13 @@ template <typename R, bool INV> struct Dft<R, 16, INV> : DftComp<R, 4, 4, INV> {
 // ceil(MAXL * NB / NT) butterflies, neighbouring lanes take the same
 // butterfly of neighbouring lines (an LDS stride of lstride, which is 1 or
 // an odd pitch: no bank conflicts) and read the same twiddle (a broadcast).
+// With lmap, line l is the buffer line lmap[l] (a subset of the lines).
 template <typename R, int N, int NT, int MAXL, bool INV, int STAGE, int NS>
 struct Stages {
   __device__ __forceinline__ static void run(cplx<R>* buf, int nlines,
                                              int lstride, int estride,
-                                             const cplx<R>* __restrict__ tw) {
+                                             const cplx<R>* __restrict__ tw,
+                                             const int* lmap = nullptr) {
     constexpr int RAD = Rad<N>::r[STAGE];
     constexpr int NB = N / RAD;                   // butterflies per line
     constexpr int NV = (MAXL * NB + NT - 1) / NT; // butterflies per thread
@@ -198,7 +200,7 @@ struct Stages {
       const int i = tid + NT * vi;
       const int l = i % MAXL, b = i / MAXL;
       if (i < tot && l < nlines) {
-        cplx<R>* line = buf + l * lstride;
+        cplx<R>* line = buf + (lmap ? lmap[l] : l) * lstride;
 #pragma unroll
         for (int r = 0; r < RAD; ++r) {
           cplx<R> x = line[(b + r * NB) * estride];
@@ -218,7 +220,7 @@ struct Stages {
       const int i = tid + NT * vi;
       const int l = i % MAXL, b = i / MAXL;
       if (i < tot && l < nlines) {
-        cplx<R>* line = buf + l * lstride;
+        cplx<R>* line = buf + (lmap ? lmap[l] : l) * lstride;
         const int d = (b / NS) * NS * RAD + (b % NS);
 #pragma unroll
         for (int r = 0; r < RAD; ++r) line[(d + r * NS) * estride] = v[vi][r];
@@ -226,16 +228,19 @@ struct Stages {
     }
     __syncthreads();
     if constexpr (STAGE + 1 < Rad<N>::S)
-      Stages<R, N, NT, MAXL, INV, STAGE + 1, NS * RAD>::run(buf, nlines, lstride, estride, tw);
+      Stages<R, N, NT, MAXL, INV, STAGE + 1, NS * RAD>::run(buf, nlines, lstride, estride, tw,
+                                                            lmap);
   }
 };
 
-// Entry point: all lines transformed; caller must __syncthreads() before
-// (data written) -- the first stage's reads happen without a barrier.
+// Entry point: all lines transformed (or the nlines lines lmap lists);
+// caller must __syncthreads() before (data written) -- the first stage's
+// reads happen without a barrier.
 template <typename R, int N, int NT, int MAXL, bool INV>
 __device__ __forceinline__ void lds_fft(cplx<R>* buf, int nlines, int lstride,
-                                        int estride, const cplx<R>* tw) {
-  Stages<R, N, NT, MAXL, INV, 0, 1>::run(buf, nlines, lstride, estride, tw);
+                                        int estride, const cplx<R>* tw,
+                                        const int* lmap = nullptr) {
+  Stages<R, N, NT, MAXL, INV, 0, 1>::run(buf, nlines, lstride, estride, tw, lmap);
 }
 
 }  // namespace ikr

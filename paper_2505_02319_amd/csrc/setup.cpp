@@ -167,9 +167,20 @@ System* create_system(const ikr_system_desc* d, hipStream_t st) {
     s.d_col_pq.upload(cpq, st);
     s.d_col_clo.upload(clo, st);
     s.d_kin.upload(kin, st);
+    // rows of the (P, Q) plane that hold sphere columns, per k
+    std::vector<int> prow((size_t)s.nk * P, 0), nprow(s.nk, 0);
+    for (int k = 0; k < s.nk; ++k) {
+      std::vector<char> has(P, 0);
+      for (int pq : s.kp[k].col_pq) has[pq / Q] = 1;
+      for (int p = 0; p < P; ++p)
+        if (has[p]) prow[(size_t)k * P + nprow[k]++] = p;
+    }
+    s.d_prow.upload(prow, st);
+    s.d_nprow.upload(nprow, st);
   }
   s.geom = Geom{C, P, Q, s.nk, s.nb_max, s.ncol_max, s.d_nb.get(), s.d_ncol.get(),
-                s.d_col_start.get(), s.d_col_pq.get(), s.d_col_clo.get(), s.d_kin.get()};
+                s.d_col_start.get(), s.d_col_pq.get(), s.d_col_clo.get(), s.d_kin.get(),
+                s.d_prow.get(), s.d_nprow.get()};
 
   // -- twiddle tables e^{-2 pi i m / N} for the C, P and Q lengths
   {

@@ -549,11 +549,20 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
       dp[(size_t)j * MAXM + m] = cscale<double>(M[(size_t)j * MAXM + m], al);
     }
     // extra computed bands: their part of the unoccupied response,
-    // <phi_m, t_n> / (e_n - e_m), by sum over states
+    // <phi_m, t_n> / (e_n - e_m), by sum over states.  A pair within
+    // DEGEN_TOL across the occupation cut-off (smearing) takes the limit of
+    // the divided difference, f'(midpoint) / f_n, as the occupied pairs do.
     if (use_schur)
       for (int m = s.nocc_k[k]; m < nbn; ++m) {
         const double em = s.eps[(size_t)k * nbn + m];
-        dp[(size_t)j * MAXM + m] = cscale<double>(M[(size_t)j * MAXM + m], 1.0 / (en - em));
+        double c;
+        if (std::fabs(en - em) < DEGEN_TOL)
+          c = (s.temperature > 0 && fn > 0)
+                  ? focc_dx((0.5 * (en + em) - s.fermi) / s.temperature) / (s.temperature * fn)
+                  : 0.0;
+        else
+          c = 1.0 / (en - em);
+        dp[(size_t)j * MAXM + m] = cscale<double>(M[(size_t)j * MAXM + m], c);
       }
   }
   const double defermi = den != 0.0 ? num / den : 0.0;

@@ -144,7 +144,7 @@ struct System {
   // k-points and spheres
   int nk = 0, nb_max = 0, ncol_max = 0;
   std::vector<KPoint> kp;
-  DBuf<int> d_nb, d_ncol, d_col_start, d_col_pq, d_col_clo;
+  DBuf<int> d_nb, d_ncol, d_col_start, d_col_pq, d_col_clo, d_prow, d_nprow;
   DBuf<double> d_kin;
   DBuf<double> d_vloc;             // internal layout
   DBuf<double2> d_proj;            // [nk][natoms][nb_max]
