@@ -30,9 +30,9 @@ __device__ __forceinline__ int find_col(const int* s, int ncb, int e) {
 }
 
 // Twiddle table of length N copied into LDS (read by every butterfly stage).
-template <typename R, int N>
+template <typename R, int N, int BT_ = NT>
 __device__ __forceinline__ void load_tw(cplx<R>* dst, const cplx<R>* __restrict__ src) {
-  for (int i = threadIdx.x; i < N; i += NT) dst[i] = src[i];
+  for (int i = threadIdx.x; i < N; i += BT_) dst[i] = src[i];
 }
 
 template <int C> constexpr int ncb_for() { return C <= 24 ? 32 : (C <= 64 ? 32 : 16); }
@@ -180,32 +180,38 @@ __global__ __launch_bounds__(NT) void col_kernel(
 // rows (nullable): the nrows rows p that hold sphere columns.  The inverse
 // transform along q then skips the other rows (zero on input) and the
 // forward one along q skips them too (not read afterwards).
-template <typename R, int P, int Q, bool INV>
+template <typename R, int P, int Q, bool INV, int BT_ = NT>
 __device__ __forceinline__ void fft2d(cplx<R>* pl, const cplx<R>* twP,
                                       const cplx<R>* twQ, const int* rows = nullptr,
                                       int nrows = P) {
   constexpr int LQ = Q + 1;
   if (INV) {
-    lds_fft<R, Q, NT, P, true>(pl, rows ? nrows : P, LQ, 1, twQ, rows);
-    lds_fft<R, P, NT, Q, true>(pl, Q, 1, LQ, twP);
+    lds_fft<R, Q, BT_, P, true>(pl, rows ? nrows : P, LQ, 1, twQ, rows);
+    lds_fft<R, P, BT_, Q, true>(pl, Q, 1, LQ, twP);
   } else {
-    lds_fft<R, P, NT, Q, false>(pl, Q, 1, LQ, twP);
-    lds_fft<R, Q, NT, P, false>(pl, rows ? nrows : P, LQ, 1, twQ, rows);
+    lds_fft<R, P, BT_, Q, false>(pl, Q, 1, LQ, twP);
+    lds_fft<R, Q, BT_, P, false>(pl, rows ? nrows : P, LQ, 1, twQ, rows);
   }
 }
 
 // The footprint rows of k-point k in LDS (rows[P]); returns their number,
 // or P (all rows) when the geometry has no row lists.
-template <int P>
+template <int P, int BT_ = NT>
 __device__ __forceinline__ int load_rows(const Geom& g, int k, int* rows) {
   if (!g.prow) return P;
-  for (int i = threadIdx.x; i < P; i += NT) rows[i] = g.prow[(size_t)k * P + i];
+  for (int i = threadIdx.x; i < P; i += BT_) rows[i] = g.prow[(size_t)k * P + i];
   return g.nprow[k];
 }
 
+// Threads per plane block: the 60 x 108 FP64 plane (105 KiB of LDS, one
+// block per CU) takes 512 so that two wavefronts per SIMD share the barriers.
+template <typename R, int P, int Q> constexpr int plane_threads() {
+  return (sizeof(R) == 8 && P * Q > 4096) ? 512 : NT;
+}
+
 // H psi local part: T -> inverse 2D -> * V -> forward 2D -> T.
-template <typename R, int P, int Q>
-__global__ __launch_bounds__(NT) void plane_hv_kernel(
+template <typename R, int P, int Q, int PT = plane_threads<R, P, Q>()>
+__global__ __launch_bounds__(PT) void plane_hv_kernel(
     Geom g, const cplx<R>* __restrict__ twP, const cplx<R>* __restrict__ twQ,
     Slots s, const cplx<R>* __restrict__ Tin, cplx<R>* __restrict__ Tout,
     const R* __restrict__ V, int v_per_slot) {
@@ -213,8 +219,8 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
   __shared__ cplx<R> pl[P * LQ];
   __shared__ cplx<R> sP[P], sQ[Q];
   __shared__ int rows[P];
-  load_tw<R, P>(sP, twP);
-  load_tw<R, Q>(sQ, twQ);
+  load_tw<R, P, PT>(sP, twP);
+  load_tw<R, Q, PT>(sQ, twQ);
   if (!row_live(s, blockIdx.y)) return;
   const int slot = slot_of(s, blockIdx.y);
   if (s.active && !s.active[slot]) return;
@@ -222,18 +228,18 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
   const int k = s.k[slot];
   const int ncol = g.ncol[k];
   const int tid = threadIdx.x;
-  const int nrows = load_rows<P>(g, k, rows);
-  for (int i = tid; i < P * LQ; i += NT) pl[i] = mk<R>(0, 0);
+  const int nrows = load_rows<P, PT>(g, k, rows);
+  for (int i = tid; i < P * LQ; i += PT) pl[i] = mk<R>(0, 0);
   __syncthreads();
   const int* pq = g.col_pq + (size_t)k * g.ncol_max;
   const size_t tb = ((size_t)slot * g.C + c) * g.ncol_max;
   constexpr int U = 4;   // columns per thread and round, loads first
-  for (int c00 = tid; c00 < ncol; c00 += U * NT) {
+  for (int c00 = tid; c00 < ncol; c00 += U * PT) {
     cplx<R> tv[U];
     int pv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int col = c00 + u * NT;
+      const int col = c00 + u * PT;
       const bool in = col < ncol;
       pv[u] = in ? pq[col] : -1;
       tv[u] = in ? Tin[tb + col] : mk<R>(0, 0);
@@ -243,26 +249,26 @@ __global__ __launch_bounds__(NT) void plane_hv_kernel(
       if (pv[u] >= 0) pl[(pv[u] / Q) * LQ + (pv[u] % Q)] = tv[u];
   }
   __syncthreads();
-  fft2d<R, P, Q, true>(pl, sP, sQ, rows, nrows);
+  fft2d<R, P, Q, true, PT>(pl, sP, sQ, rows, nrows);
   const R* vp = V + (v_per_slot ? (size_t)slot * g.C * P * Q : 0) + (size_t)c * P * Q;
-  constexpr int NV = (P * Q + NT - 1) / NT;
+  constexpr int NV = (P * Q + PT - 1) / PT;
   R vv[NV];
 #pragma unroll
   for (int u = 0; u < NV; ++u) {
-    const int i = tid + u * NT;
+    const int i = tid + u * PT;
     if (i < P * Q) vv[u] = vp[i];
   }
 #pragma unroll
   for (int u = 0; u < NV; ++u) {
-    const int i = tid + u * NT;
+    const int i = tid + u * PT;
     if (i < P * Q) {
       const int p = i / Q, q = i % Q;
       pl[p * LQ + q] = cscale<R>(pl[p * LQ + q], vv[u]);
     }
   }
   __syncthreads();
-  fft2d<R, P, Q, false>(pl, sP, sQ, rows, nrows);
-  for (int col = tid; col < ncol; col += NT) {
+  fft2d<R, P, Q, false, PT>(pl, sP, sQ, rows, nrows);
+  for (int col = tid; col < ncol; col += PT) {
     const int v = pq[col];
     Tout[tb + col] = pl[(v / Q) * LQ + (v % Q)];
   }
@@ -504,8 +510,9 @@ void launch_plane_hv(const Geom& g, const FftTables& t, const Slots& s,
   const cplx<R>* tQ = twp<R>(t, t.offQ);
 #define X(a, b)                                                                \
   if (g.P == a && g.Q == b) {                                                  \
-    hipLaunchKernelGGL((plane_hv_kernel<R, a, b>), dim3(g.C, s.n), dim3(NT),   \
-                       0, st, g, tP, tQ, s, Tin, Tout, V, v_per_slot);         \
+    hipLaunchKernelGGL((plane_hv_kernel<R, a, b>), dim3(g.C, s.n),            \
+                       dim3(plane_threads<R, a, b>()), 0, st, g, tP, tQ, s, Tin, \
+                       Tout, V, v_per_slot);                                    \
     IKR_HIP(hipGetLastError());                                                \
     return;                                                                    \
   }

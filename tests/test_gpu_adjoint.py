@@ -182,3 +182,25 @@ def test_grad_amplitudes_rejects_smeared_occupations():
     v = to_dev(random_field(osys.spec, 2))
     with pytest.raises(IkrError):
         rs.grad_amplitudes(v, v, 1e-12)
+
+
+@pytest.mark.parametrize("name", ["small_rect", "cfg1"])
+def test_grad_amplitudes_matches_oracle_mid_size(name):
+    """dL/dA on larger cells (small_rect: 20 x 20 x 36 grid, 2 k, 4 atoms; cfg1:
+    20^3), from the library's own drho = E^-1 b and lambda = E^-T 2 (drho - t)
+    (grt, 1e-11): the library's gradient against the oracle's third-order form
+    on the same drho and lambda (Sternheimer CG at 1e-13 on both sides)."""
+    from oracle.gradient import amplitude_gradient
+    from oracle.response import HxcKernel
+    from paper_2505_02319_amd import default_opts
+    print(f"amplitude gradient vs oracle: {name}", flush=True)
+    rs, osys, ogs, perms = gpu_system(name)
+    b = random_field(osys.spec, 2)
+    t = random_field(osys.spec, 3)
+    opts = default_opts(strategy="grt", tol=1e-11)
+    x, _ = rs.solve(to_dev(b), opts)
+    lam, _ = rs.solve_adjoint(2 * (x - to_dev(t)), opts)
+    got, st = rs.grad_amplitudes(x, lam, 1e-13)
+    kern = HxcKernel(osys, ogs.rho, xc=osys.spec.xc)
+    ref = amplitude_gradient(osys, ogs, kern, to_host(x), to_host(lam), tol=1e-13)
+    assert rel(got, ref) < 1e-8, (got, ref)
