@@ -108,6 +108,8 @@ def main():
                          "whose name contains --trace-kernel")
     ap.add_argument("--trace-kernel", default="plane_hv_kernel<double")
     ap.add_argument("--trace-last", type=int, default=0)
+    ap.add_argument("--kernel-paths", type=int, default=0,
+                    help="kernel-path mask forced process-wide (0: by size)")
     ap.add_argument("--large-cell", default="cfg4",
                     help="workload of the one-solve large-cell leg ('none' to skip)")
     ap.add_argument("--large-strategy", default="grt")
@@ -138,6 +140,9 @@ def main():
 
     spec = config(args.workload)
     torch.cuda.set_device(0)
+    if args.kernel_paths:
+        from paper_2505_02319_amd import set_kernel_paths
+        set_kernel_paths(args.kernel_paths)
     if args.gradient:
         gradient_bench(torch, spec, args)
         return
