@@ -413,15 +413,18 @@ def strategy_legs(rs, b, bnorm, args, default_opts):
     eta_rel against D10, all in the headline's precision."""
     import math
     out = {}
-    for name, strat, kerk in [("grt", "grt", 0), ("bal", "bal", 0), ("D10", "D10", 0),
-                              ("Pgrt", "grt", 1), ("Pbal", "bal", 1), ("PD10", "D10", 1)]:
+    for name, strat, kerk, rec in [("grt", "grt", 0, 0), ("bal", "bal", 0, 0),
+                                   ("D10", "D10", 0, 0), ("Pgrt", "grt", 1, 0),
+                                   ("Pbal", "bal", 1, 0), ("PD10", "D10", 1, 0),
+                                   ("Pgrt_warm", "grt", 1, 4)]:
         o = default_opts(strategy=strat, tol=1e-8, tol_is_relative=1, precision=args.precision,
-                         schur=args.schur, kerker=kerk, want_true_residual=1)
+                         schur=args.schur, kerker=kerk, want_true_residual=1, recycle=rec)
         _, st = rs.solve(b, o)
         tr = st["true_res"] / bnorm
         eta = -math.log10(tr) / st["n_ham"] if tr > 0 else None
         out[name] = {"n_ham": st["n_ham"], "seconds": st["seconds"],
-                     "gmres_iters": st["gmres_iters"], "true_rel_residual": tr, "eta": eta}
+                     "gmres_iters": st["gmres_iters"], "true_rel_residual": tr, "eta": eta,
+                     "warm_started": st["warm_started"]}
     ref = out["D10"]["eta"]
     for v in out.values():
         v["eta_rel_vs_D10"] = v["eta"] / ref if (v["eta"] and ref) else None

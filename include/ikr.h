@@ -144,6 +144,16 @@ typedef struct {
                                ||b - E x||.  Forward solves only.  Default 0 */
   double kerker_alpha;      /* alpha of the Kerker symbol |G|^2/(|G|^2 + alpha^2),
                                1/bohr (default 0.8) */
+  int recycle;              /* Sternheimer warm starts across dielectric
+                               applications (0..8, default 0: off): the last
+                               `recycle` right-hand sides and CG solutions of every
+                               band are kept on the device (2 recycle J nb_max
+                               complex), and a band's CG starts from the
+                               least-squares combination of its earlier solutions
+                               whenever that leaves under a tenth of the new
+                               right-hand side (its residual b - A x0 is formed
+                               with one FP64 H application).  Reset at the start
+                               of every solve. */
 } ikr_solver_opts;
 
 typedef struct {
@@ -167,6 +177,8 @@ typedef struct {
   long long fp32_checked;   /* FP32 Sternheimer solves whose true residual was checked
                                with one FP64 H application (tolerance below 1e-3 ||b||,
                                or FP32 CG not converged) */
+  long long warm_started;   /* Sternheimer solves started from earlier solutions
+                               (solver option recycle) */
 } ikr_stats;
 
 /* Fill opts with the defaults above (strategy bal, tol 1e-8 relative). */

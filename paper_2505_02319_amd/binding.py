@@ -50,7 +50,7 @@ class SolverOpts(C.Structure):
                 ("fp32_theta", C.c_double), ("b_norm", C.c_double),
                 ("want_true_residual", C.c_int), ("true_res_cg_tol", C.c_double),
                 ("schur", C.c_int), ("batching", C.c_int), ("x0", C.c_void_p),
-                ("kerker", C.c_int), ("kerker_alpha", C.c_double)]
+                ("kerker", C.c_int), ("kerker_alpha", C.c_double), ("recycle", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -60,7 +60,8 @@ class Stats(C.Structure):
                 ("est_res", C.c_double), ("true_res", C.c_double),
                 ("s_final", C.c_double), ("sigma_min", C.c_double),
                 ("knorm_last", C.c_double), ("seconds", C.c_double),
-                ("fp64_fallback", C.c_longlong), ("fp32_checked", C.c_longlong)]
+                ("fp64_fallback", C.c_longlong), ("fp32_checked", C.c_longlong),
+                ("warm_started", C.c_longlong)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

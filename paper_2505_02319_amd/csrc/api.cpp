@@ -53,6 +53,7 @@ void check_opts(const ikr_solver_opts* o) {
   IKR_CHECK(o->precision == 0 || o->precision == 1, IKR_E_ARG, "precision must be 0 or 1");
   IKR_CHECK(o->batching >= 0 && o->batching <= 2, IKR_E_ARG, "batching must be 0, 1 or 2");
   IKR_CHECK(o->kerker == 0 || o->kerker == 1, IKR_E_ARG, "kerker must be 0 or 1");
+  IKR_CHECK(o->recycle >= 0 && o->recycle <= 8, IKR_E_ARG, "recycle must be in [0, 8]");
   IKR_CHECK(!o->kerker || (o->kerker_alpha > 0 && std::isfinite(o->kerker_alpha)), IKR_E_ARG,
             "kerker_alpha must be positive");
 }
@@ -63,8 +64,9 @@ struct GraphMode {
   GraphMode(System* sys, const ikr_solver_opts* o) : s(sys) {
     s->cg_graph = o->batching == 1;
     s->cg_plain = o->batching == 2;
+    s->cg_recycle = o->recycle;
   }
-  ~GraphMode() { s->cg_graph = 0; s->cg_plain = 0; }
+  ~GraphMode() { s->cg_graph = 0; s->cg_plain = 0; s->cg_recycle = 0; }
 };
 
 }  // namespace
@@ -91,6 +93,7 @@ void ikr_default_opts(ikr_solver_opts* o) {
   o->x0 = nullptr;
   o->kerker = 0;
   o->kerker_alpha = 0.8;
+  o->recycle = 0;
 }
 
 int ikr_supported_fft_size(int n) { return ikr::fft_length_supported(n) ? 1 : 0; }

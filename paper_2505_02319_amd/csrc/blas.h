@@ -117,6 +117,16 @@ void convert_array(size_t n, const double* in, float* out, hipStream_t st);
 void convert_array(size_t n, const double2* in, float2* out, hipStream_t st);
 void resid_norms(int nslots, int nb_max, const int* slot_k, const int* nb, const double2* HX,
                  const double2* X, const double* lam, double* part, hipStream_t st);
+// out[slot * nv + l] = <V[l][slot], x[slot]> (complex, over each slot's sphere) for all
+// nslots slots, through partials part (slot_dots_part_elems entries).
+void slot_dots(int nslots, int nb_max, const int* slot_k, const int* nb, int nv,
+               const double2* V, size_t vstride, const double2* x, double2* part,
+               double2* out, hipStream_t st);
+size_t slot_dots_part_elems(int nslots, int nb_max, int nv);
+// y[slot] = sum_l c[slot * nv + l] V[l][slot] for the nlist listed slots.
+void slot_combine(int nlist, const int* list, int nb_max, const int* slot_k, const int* nb,
+                  int nv, const double2* V, size_t vstride, const double2* c, double2* y,
+                  hipStream_t st);
 void to_internal(const Layout& L, const double* ext, double* in, hipStream_t st);
 void to_external(const Layout& L, const double* in, double* ext, double a,
                  const double* base, double bscale, hipStream_t st);

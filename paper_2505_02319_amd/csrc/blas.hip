@@ -627,6 +627,87 @@ __global__ __launch_bounds__(NT) void cheb_combine_kernel(
   X[o] = mk<double>(a * z.x + b * x.x, a * z.y + b * x.y);
 }
 
+// Per-slot dots against stored vectors (warm starts of the Sternheimer CG):
+// part[(slot * nv + l) * gridDim.x + b] = sum over block b's coefficients of
+// conj(V[l][slot][g]) x[slot][g], l < nv, V with a stride vstride per l.
+constexpr int SD_PER = 4;   // coefficients per thread
+__global__ __launch_bounds__(NT) void slot_dots_kernel(
+    int nb_max, const int* __restrict__ slot_k, const int* __restrict__ nb, int nv,
+    const double2* __restrict__ V, size_t vstride, const double2* __restrict__ x,
+    double2* __restrict__ part) {
+  __shared__ double rx[NT / 64], ry[NT / 64];
+  const int slot = blockIdx.y, tid = threadIdx.x;
+  const int n = nb[slot_k[slot]];
+  const size_t o = (size_t)slot * nb_max;
+  double2 xv[SD_PER];
+#pragma unroll
+  for (int u = 0; u < SD_PER; ++u) {
+    const int g = (blockIdx.x * SD_PER + u) * NT + tid;
+    xv[u] = g < n ? x[o + g] : mk<double>(0, 0);
+  }
+  for (int l = 0; l < nv; ++l) {
+    double sx = 0, sy = 0;
+#pragma unroll
+    for (int u = 0; u < SD_PER; ++u) {
+      const int g = (blockIdx.x * SD_PER + u) * NT + tid;
+      if (g < n) {
+        const double2 v = V[l * vstride + o + g];
+        sx += v.x * xv[u].x + v.y * xv[u].y;
+        sy += v.x * xv[u].y - v.y * xv[u].x;
+      }
+    }
+    sx = wave_sum(sx);
+    sy = wave_sum(sy);
+    if ((tid & 63) == 0) {
+      rx[tid >> 6] = sx;
+      ry[tid >> 6] = sy;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double ax = rx[0], ay = ry[0];
+      for (int w = 1; w < NT / 64; ++w) {
+        ax += rx[w];
+        ay += ry[w];
+      }
+      part[((size_t)slot * nv + l) * gridDim.x + blockIdx.x] = mk<double>(ax, ay);
+    }
+    __syncthreads();
+  }
+}
+
+// out[slot][i] = sum_b part[(slot * nv + i) * nb + b] (fixed order)
+__global__ void slot_dots_reduce_kernel(int total, int nblk, const double2* __restrict__ part,
+                                        double2* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  double sx = 0, sy = 0;
+  for (int b = 0; b < nblk; ++b) {
+    const double2 v = part[(size_t)i * nblk + b];
+    sx += v.x;
+    sy += v.y;
+  }
+  out[i] = mk<double>(sx, sy);
+}
+
+// y[slot][g] = sum_l c[slot * nv + l] V[l][slot][g] for the listed slots
+// (others untouched), over each slot's sphere.
+__global__ __launch_bounds__(NT) void slot_combine_kernel(
+    int nb_max, const int* __restrict__ list, const int* __restrict__ slot_k,
+    const int* __restrict__ nb, int nv, const double2* __restrict__ V, size_t vstride,
+    const double2* __restrict__ c, double2* __restrict__ y) {
+  const int slot = list[blockIdx.y];
+  const int g = blockIdx.x * NT + threadIdx.x;
+  if (g >= nb[slot_k[slot]]) return;
+  const size_t o = (size_t)slot * nb_max + g;
+  double ax = 0, ay = 0;
+  for (int l = 0; l < nv; ++l) {
+    const double2 v = V[l * vstride + o], w = c[(size_t)slot * nv + l];
+    ax += w.x * v.x - w.y * v.y;
+    ay += w.x * v.y + w.y * v.x;
+  }
+  y[o] = mk<double>(ax, ay);
+}
+
 // partial |HX - lam X|^2 per (slot, block)
 __global__ __launch_bounds__(NT) void resid_kernel(
     int nb_max, const int* __restrict__ slot_k, const int* __restrict__ nb,
@@ -1003,6 +1084,33 @@ void cheb_combine(int nslots, int nb_max, const int* slot_k, const int* nb, cons
                   double2* X, const double* alpha, const double* beta, hipStream_t st) {
   hipLaunchKernelGGL(cheb_combine_kernel, dim3(vec_nblocks(nb_max), nslots), dim3(NT), 0, st,
                      nb_max, slot_k, nb, Z, X, alpha, beta);
+  IKR_HIP(hipGetLastError());
+}
+
+void slot_dots(int nslots, int nb_max, const int* slot_k, const int* nb, int nv,
+               const double2* V, size_t vstride, const double2* x, double2* part,
+               double2* out, hipStream_t st) {
+  if (nslots <= 0 || nv <= 0) return;
+  const int nblk = (nb_max + SD_PER * NT - 1) / (SD_PER * NT);
+  hipLaunchKernelGGL(slot_dots_kernel, dim3(nblk, nslots), dim3(NT), 0, st, nb_max, slot_k, nb,
+                     nv, V, vstride, x, part);
+  IKR_HIP(hipGetLastError());
+  const int total = nslots * nv;
+  hipLaunchKernelGGL(slot_dots_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, st, total,
+                     nblk, part, out);
+  IKR_HIP(hipGetLastError());
+}
+
+size_t slot_dots_part_elems(int nslots, int nb_max, int nv) {
+  return (size_t)nslots * nv * ((nb_max + SD_PER * NT - 1) / (SD_PER * NT));
+}
+
+void slot_combine(int nlist, const int* list, int nb_max, const int* slot_k, const int* nb,
+                  int nv, const double2* V, size_t vstride, const double2* c, double2* y,
+                  hipStream_t st) {
+  if (nlist <= 0) return;
+  hipLaunchKernelGGL(slot_combine_kernel, dim3(vec_nblocks(nb_max), nlist), dim3(NT), 0, st,
+                     nb_max, list, slot_k, nb, nv, V, vstride, c, y);
   IKR_HIP(hipGetLastError());
 }
 

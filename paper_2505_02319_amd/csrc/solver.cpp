@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 
 #include "cg.h"
 #include "ktimer.h"
@@ -20,6 +21,54 @@ constexpr double DEGEN_TOL = 1e-8;
 constexpr double TOL_FLOOR = 1e-13;   // CG tolerances never below this times ||b_j||
 constexpr double CHECK_REL = 1e-3;    // FP32 results with tau_j below this times ||b_j||
                                       // get an FP64 true-residual check
+constexpr double WARM_REL = 0.1;      // warm start when it leaves under this of ||b_j||
+
+// Least squares over the stored right-hand sides of one band: c minimising
+// ||b - sum_l c_l b_l|| from the Gram matrix G (row-major, leading size ld,
+// the first nv entries) and h_l = <b_l, b>; Cholesky of G with a small ridge.
+// Returns the predicted squared residual ||b||^2 - Re(h^H c) (bb = ||b||^2).
+double warm_coefficients(const double2* G, int ld, int nv, const double2* h, double bb,
+                         std::vector<double2>& c) {
+  double tr = 0;
+  for (int i = 0; i < nv; ++i) tr += G[i * ld + i].x;
+  const double ridge = 1e-12 * tr + 1e-300;
+  std::vector<double2> Lc((size_t)nv * nv, mk<double>(0, 0));
+  for (int j = 0; j < nv; ++j) {
+    double d = G[j * ld + j].x + ridge;
+    for (int k = 0; k < j; ++k) {
+      const double2 l = Lc[(size_t)j * nv + k];
+      d -= l.x * l.x + l.y * l.y;
+    }
+    if (!(d > 0)) { c.assign(nv, mk<double>(0, 0)); return bb; }
+    const double ljj = std::sqrt(d);
+    Lc[(size_t)j * nv + j] = mk<double>(ljj, 0);
+    for (int i = j + 1; i < nv; ++i) {
+      double2 v = G[i * ld + j];
+      for (int k = 0; k < j; ++k)
+        v = csub<double>(v, cmul<double>(Lc[(size_t)i * nv + k],
+                                         mk<double>(Lc[(size_t)j * nv + k].x,
+                                                    -Lc[(size_t)j * nv + k].y)));
+      Lc[(size_t)i * nv + j] = cscale<double>(v, 1.0 / ljj);
+    }
+  }
+  // G c = h: L y = h, then L^H c = y
+  std::vector<double2> y(nv);
+  for (int i = 0; i < nv; ++i) {
+    double2 v = h[i];
+    for (int k = 0; k < i; ++k) v = csub<double>(v, cmul<double>(Lc[(size_t)i * nv + k], y[k]));
+    y[i] = cscale<double>(v, 1.0 / Lc[(size_t)i * nv + i].x);
+  }
+  c.assign(nv, mk<double>(0, 0));
+  for (int i = nv - 1; i >= 0; --i) {
+    double2 v = y[i];
+    for (int k = i + 1; k < nv; ++k)
+      v = csub<double>(v, cmulc<double>(Lc[(size_t)k * nv + i], c[k]));
+    c[i] = cscale<double>(v, 1.0 / Lc[(size_t)i * nv + i].x);
+  }
+  double hc = 0;
+  for (int i = 0; i < nv; ++i) hc += h[i].x * c[i].x + h[i].y * c[i].y;   // Re(h^H c)
+  return bb - hc;
+}
 
 double focc_dx(double x) {
   const double e = std::exp(-std::fabs(x));
@@ -592,6 +641,77 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
       for (int j = 0; j < J; ++j)
         if (tol_slot[j] >= theta * bn[j]) { m32[j] = 1; m64[j] = 0; ++n32; }
   }
+  // Warm starts (solver option recycle): x0 = the least-squares combination of
+  // the band's stored solutions for its stored right-hand sides, where that
+  // leaves under WARM_REL of b; the CG then runs on A d = b - A x0.
+  const int L = s.cg_recycle;
+  std::vector<double2> hdot;   // <b_l, b_j> of the stored right-hand sides
+  bool any_warm = false;
+  if (L > 0) {
+    if (s.rec_cap != L) {
+      s.rec_cap = L;
+      s.rec_count = s.rec_head = 0;
+      s.d_rec_b.alloc((size_t)L * J * nbm);
+      s.d_rec_x.alloc((size_t)L * J * nbm);
+      s.d_rec_tb.alloc((size_t)J * nbm);
+      s.d_rec_part.alloc(slot_dots_part_elems(J, nbm, L));
+      s.d_rec_h.alloc((size_t)J * L);
+      s.d_rec_c.alloc((size_t)J * L);
+      s.d_rec_list.alloc(J);
+      s.rec_G.assign((size_t)J * L * L, mk<double>(0, 0));
+    }
+    IKR_HIP(hipMemcpyAsync(s.d_rec_tb.get(), w.r.get(), (size_t)J * nbm * sizeof(double2),
+                           hipMemcpyDeviceToDevice, st));
+    const int nv = s.rec_count;
+    if (nv > 0) {
+      const size_t vs = (size_t)J * nbm;
+      slot_dots(J, nbm, s.d_slot_k.get(), s.d_nb.get(), nv, s.d_rec_b.get(), vs, w.r.get(),
+                s.d_rec_part.get(), s.d_rec_h.get(), st);
+      hdot = download(s.d_rec_h.get(), (size_t)J * nv, st);
+      std::vector<double2> c((size_t)J * nv, mk<double>(0, 0));
+      std::vector<int> wl;
+      std::vector<double> ratio(J);
+      for (int j = 0; j < J; ++j) {
+        const double2* h = hdot.data() + (size_t)j * nv;
+        std::vector<double2> c_j;
+        const double pred = warm_coefficients(s.rec_G.data() + (size_t)j * L * L, L, nv, h,
+                                              bn[j] * bn[j], c_j);
+        ratio[j] = std::sqrt(std::max(pred, 0.0)) / std::max(bn[j], 1e-300);
+        if (pred < WARM_REL * WARM_REL * bn[j] * bn[j]) {
+          std::copy(c_j.begin(), c_j.end(), c.begin() + (size_t)j * nv);
+          wl.push_back(j);
+        }
+      }
+      if (std::getenv("IKR_VERBOSE")) {
+        std::vector<double> r = ratio;
+        std::sort(r.begin(), r.end());
+        std::fprintf(stderr, "[ikr warm] stored %d: residual left by the stored solutions, "
+                     "min %.3f median %.3f max %.3f of ||b||; %zu warm\n", nv, r.front(),
+                     r[r.size() / 2], r.back(), wl.size());
+      }
+      if (!wl.empty()) {
+        any_warm = true;
+        res.warm = (int)wl.size();
+        IKR_HIP(hipMemcpyAsync(s.d_rec_c.get(), c.data(), c.size() * sizeof(double2),
+                               hipMemcpyHostToDevice, st));
+        IKR_HIP(hipMemcpyAsync(s.d_rec_list.get(), wl.data(), wl.size() * sizeof(int),
+                               hipMemcpyHostToDevice, st));
+        // x = 0 for every slot, then x0 on the warm ones; r = b - A x0 there
+        cg_zero<double>(Slots{J, s.d_slot_k.get(), nullptr}, nbm, w.x.get(), w.p.get(), st);
+        slot_combine((int)wl.size(), s.d_rec_list.get(), nbm, s.d_slot_k.get(), s.d_nb.get(), nv,
+                     s.d_rec_x.get(), vs, s.d_rec_c.get(), w.x.get(), st);
+        slot_combine((int)wl.size(), s.d_rec_list.get(), nbm, s.d_slot_k.get(), s.d_nb.get(), nv,
+                     s.d_rec_x.get(), vs, s.d_rec_c.get(), w.w.get(), st);
+        std::vector<int> mw(J, 0);
+        for (int j : wl) mw[j] = 1;
+        IKR_HIP(hipStreamSynchronize(st));
+        apply_sternheimer_op(s, mw, dMq, Mq_max, dMcg);
+        cg_axpy<double>(Slots{(int)wl.size(), s.d_slot_k.get(), nullptr, s.d_rec_list.get()},
+                        s.d_nb.get(), nbm, -1.0, w.w.get(), w.r.get(), st);
+        res.n_ham64 += (long long)wl.size();
+      }
+    }
+  }
   CgOut o64;
   if (s.cg_plain) {
     // plain FP64 reference: the k-points one after the other
@@ -599,15 +719,15 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
       std::vector<int> mk_(J, 0);
       for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) mk_[j] = 1;
       const CgOut ok = run_cg<double>(s, s.w64, w.r.get(), mk_, tol_slot, min_iter, max_iter,
-                                      dMq, Mq_max, dMcg);
+                                      dMq, Mq_max, dMcg, any_warm);
       o64.n_ham += ok.n_ham;
       o64.noconv += ok.noconv;
     }
   } else {
     o64 = run_cg<double>(s, s.w64, w.r.get(), m64, tol_slot, min_iter, max_iter, dMq, Mq_max,
-                         dMcg);
+                         dMcg, any_warm);
   }
-  res.n_ham64 = o64.n_ham;
+  res.n_ham64 += o64.n_ham;
   res.noconv = o64.noconv;
   if (n32 > 0) {
     ensure_fp32(s);
@@ -617,8 +737,11 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     DBuf<int> dl32;
     dl32.upload(l32, st);
     convert_slots(n32, dl32.get(), s.d_slot_k.get(), s.d_nb.get(), nbm, w.r.get(), s.w32.r.get(), st);
+    if (any_warm)
+      convert_slots(n32, dl32.get(), s.d_slot_k.get(), s.d_nb.get(), nbm, w.x.get(),
+                    s.w32.x.get(), st);
     const CgOut o32 = run_cg<float>(s, s.w32, s.w32.r.get(), m32, tol_slot, min_iter,
-                                      max_iter, dMq, Mq_max, dMcg);
+                                      max_iter, dMq, Mq_max, dMcg, any_warm);
     convert_slots(n32, dl32.get(), s.d_slot_k.get(), s.d_nb.get(), nbm, s.w32.x.get(), w.x.get(), st);
     res.n_ham32 = o32.n_ham;
     // FP64 check of the FP32 results: the true residual b - A x of every
@@ -627,6 +750,9 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     // each).  A band that fails continues in FP64 from its FP32 iterate
     // (defect correction); one that did not converge restarts from zero, as
     // its iterate may not be finite.
+    if (any_warm)   // the check below forms b - A x from r = b
+      IKR_HIP(hipMemcpyAsync(w.r.get(), s.d_rec_tb.get(), (size_t)J * nbm * sizeof(double2),
+                             hipMemcpyDeviceToDevice, st));
     const std::vector<float> rn = download(s.w32.rnorm2.get(), J, st);
     std::vector<int> mc(J, 0), mz(J, 0);
     int nc = 0, nz = 0;
@@ -674,6 +800,26 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     }
   }
   res.n_ham = res.n_ham64 + res.n_ham32;
+  if (L > 0) {   // keep this right-hand side and solution (the oldest pair goes)
+    const int pos = s.rec_head, nv = s.rec_count;
+    const size_t vs = (size_t)J * nbm;
+    IKR_HIP(hipMemcpyAsync(s.d_rec_b.get() + pos * vs, s.d_rec_tb.get(), vs * sizeof(double2),
+                           hipMemcpyDeviceToDevice, st));
+    IKR_HIP(hipMemcpyAsync(s.d_rec_x.get() + pos * vs, w.x.get(), vs * sizeof(double2),
+                           hipMemcpyDeviceToDevice, st));
+    for (int j = 0; j < J; ++j) {
+      double2* G = s.rec_G.data() + (size_t)j * L * L;
+      for (int l = 0; l < nv; ++l) {
+        if (l == pos) continue;
+        const double2 h = hdot[(size_t)j * nv + l];        // <b_l, b_new>
+        G[l * L + pos] = h;
+        G[pos * L + l] = mk<double>(h.x, -h.y);
+      }
+      G[pos * L + pos] = mk<double>(bn[j] * bn[j], 0);
+    }
+    s.rec_head = (pos + 1) % L;
+    s.rec_count = std::min(nv + 1, L);
+  }
   UpdTerm<double> phiA{s.d_phi.get(), phik, nbm, dMq, w.coefA.get(), MAXM, -1.0, Mq_max};
   const double S16 = 16.0;
   double ncol_avg = 0;
@@ -811,6 +957,7 @@ void apply_dielectric_ext(System& s, const double* v_ext, double* ev_ext, double
     stt->cg_unconverged += r.noconv;
     stt->fp64_fallback += r.fallback;
     stt->fp32_checked += r.checked;
+    stt->warm_started += r.warm;
   }
   check_finite_response(s, r, tol);
   to_external(s.L, s.d_drho.get(), ev_ext, -nu, v_ext, 1.0, st);
@@ -847,6 +994,7 @@ void apply_dielectric_adjoint_ext(System& s, const double* v_ext, double* ev_ext
     stt->cg_unconverged += r.noconv;
     stt->fp64_fallback += r.fallback;
     stt->fp32_checked += r.checked;
+    stt->warm_started += r.warm;
   }
   check_finite_response(s, r, tol);
   apply_kernel(s, s.d_drho.get(), s.d_u.get());
@@ -894,6 +1042,7 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
                     ikr_stats* stt, bool adjoint) {
   const bool kerker = o.kerker != 0;
   IKR_CHECK(!(kerker && adjoint), 1, "Kerker preconditioning is for forward solves only");
+  s.rec_count = s.rec_head = 0;   // warm starts only from this solve's own applications
   auto apply_op = [&](const double* v, double* ev, double common, double bn, ikr_stats* sp) {
     if (adjoint) apply_dielectric_adjoint_ext(s, v, ev, common, o, bn, sp);
     else apply_dielectric_ext(s, v, ev, common, o, bn, sp);
@@ -1038,8 +1187,11 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
     ikr_solver_opts ot = o;
     ot.strategy = IKR_FIXED;
     ikr_stats dummy{};
+    const int rec = s.cg_recycle;   // the check starts every CG from zero
+    s.cg_recycle = 0;
     if (adjoint) apply_dielectric_adjoint_ext(s, x_ext, tmp.get(), o.true_res_cg_tol, ot, bnorm, &dummy);
     else apply_dielectric_ext(s, x_ext, tmp.get(), o.true_res_cg_tol, ot, bnorm, &dummy);
+    s.cg_recycle = rec;
     axpy(1, b_ext, {1.0}, -1.0, tmp.get());
     stt->true_res = std::sqrt(dots(1, tmp.get(), tmp.get())[0]);
   }

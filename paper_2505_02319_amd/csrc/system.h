@@ -201,6 +201,14 @@ struct System {
   int cg_graph = 0;                // 1: CG iterations replayed from captured graphs
   int cg_plain = 0;                // 1: plain FP64 reference: one k-point per CG run,
                                    //    the host reads the live count every iteration
+  // Sternheimer warm starts: ring of the last rec_cap right-hand sides and CG
+  // solutions per slot ([rec_cap][J][nb_max]), the Gram matrices of the stored
+  // right-hand sides per slot ([J][rec_cap][rec_cap], host)
+  int cg_recycle = 0;              // capacity asked for by the current call (0: off)
+  int rec_cap = 0, rec_count = 0, rec_head = 0;
+  DBuf<double2> d_rec_b, d_rec_x, d_rec_tb, d_rec_part, d_rec_h, d_rec_c;
+  DBuf<int> d_rec_list;
+  std::vector<double2> rec_G;
   CgGraphs graphs;
 
   std::string name;
@@ -237,6 +245,7 @@ double apply_kernel(System& s, const double* v_int, double* kv_int);
 struct Chi0Result {
   long long n_ham = 0, n_ham32 = 0, n_ham64 = 0;
   int noconv = 0;
+  int warm = 0;         // Sternheimer solves warm-started from earlier solutions
   int fallback = 0;     // FP32 bands continued in FP64 (true residual above tolerance)
   int checked = 0;      // FP32 bands whose true residual was checked in FP64
 };
