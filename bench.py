@@ -152,6 +152,10 @@ def main():
     t_setup = time.perf_counter() - t0
     log(f"setup {spec.name}: {t_setup:.1f} s, eigensolver steps {info['gs_iters']}, "
         f"residual {info['gs_residual']:.1e}, min gap {min(info['gaps']):.2e}")
+    t0 = time.perf_counter()
+    rs.tune_launches(precision=args.precision, schur=args.schur)
+    t_tune = time.perf_counter() - t0
+    log(f"launch tuning: {t_tune:.2f} s")
     b = torch.from_numpy(random_field(spec, B_SEED)).cuda()
     opts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
                         precision=args.precision, schur=args.schur, kerker=args.kerker)
@@ -250,7 +254,9 @@ def main():
                      "avg_launch_us": 1e3 * ms / max(launches, 1), "launches": launches,
                      "bytes_per_launch": bytes_per_launch},
         "kernels_warmup_step": kernels,
+        "launch_tuning": tuning_of(rs),
         "setup_seconds": t_setup,
+        "launch_tuning_seconds": t_tune,
     }
     rs.close()
     if args.large_cell != "none":
@@ -445,6 +451,10 @@ def large_cell_leg(torch, args):
     info = rs.setup_info()
     t_setup = time.perf_counter() - t0
     log(f"large cell {spec.name}: setup {t_setup:.1f} s, eigensolver steps {info['gs_iters']}")
+    t0 = time.perf_counter()
+    rs.tune_launches(precision=1, schur=1)
+    t_tune = time.perf_counter() - t0
+    log(f"large cell launch tuning: {t_tune:.2f} s")
     b = torch.from_numpy(random_field(spec, B_SEED)).cuda()
     bnorm = float(torch.linalg.norm(b))
     o = default_opts(strategy=args.large_strategy, tol=1e-8, tol_is_relative=1, precision=1,
@@ -463,16 +473,23 @@ def large_cell_leg(torch, args):
     ex, _ = rs.apply_dielectric(x, 1e-14, default_opts(strategy="fixed", precision=0))
     true_rel = float(torch.linalg.norm(b - ex)) / bnorm
     log(f"large cell true relative residual {true_rel:.2e}")
+    tuning = tuning_of(rs)
     rs.close()
     kernels = {k: {"launches": v[0], "ms": round(v[1], 1),
                    "GB/s": round(v[2] / (v[1] * 1e-3) / 1e9, 1) if v[1] > 0 else None}
                for k, v in prof.items() if v[0]}
     return {"workload": describe_large(spec, args), "setup_seconds": t_setup,
+            "launch_tuning_seconds": t_tune,
             "eigensolver_steps": info["gs_iters"], "seconds": sec, "solves_per_s": 1.0 / sec,
             "n_ham": st["n_ham"], "n_ham_fp32": st["n_ham_fp32"], "gmres_iters": st["gmres_iters"],
             "true_rel_residual": true_rel,
             "note": "kernel times from HIP events on every hot launch of the timed solve",
-            "kernels": kernels}
+            "kernels": kernels, "launch_tuning": tuning}
+
+
+def tuning_of(rs):
+    """The launch shapes the system measured, keyed "fp64/thick" and so on."""
+    return {f"{p}/{c}": v for (p, c), v in rs.tuning().items()}
 
 
 def describe_large(spec, args):

@@ -351,10 +351,48 @@ ikr_status ikr_grad_amplitudes(ikr_handle h, const double* drho_dev,
  * per-tile matrix-core gram below 65 projection rows, the k-wide matrix-core
  * gram above), bit 1 the two-launch end of a CG iteration (otherwise one
  * block while the batch has few partials), bit 2 the k-wide matrix-core gram
- * (all bands of a k-point per block) at any row count.
+ * (all bands of a k-point per block) at any row count, bit 3 the size rules
+ * alone for every launch shape (no setup-time tuning, below).
  * Unknown bits: IKR_E_ARG.  ikr_get_kernel_paths returns the current mask. */
 ikr_status ikr_set_kernel_paths(int mask);
 int ikr_get_kernel_paths(void);
+
+/* Launch shapes picked by measurement.  At the first Sternheimer CG run of
+ * each precision, a system times the candidates of three launch shapes of
+ * the CG iteration with HIP events on its stream (one untimed and three timed
+ * runs each) and keeps the fastest: the projection gram's kernel and block
+ * count, the CG update's band group, and the plane kernel's block size.  It
+ * does so for the batch the run starts with, when that batch has more tiles
+ * of 16 bands than k-points ("thick"), and for batches of at most 8 and at
+ * most 2 bands per k-point ("thin": the late iterations, times added); each
+ * iteration then takes the shapes of its class.  The size rule is one of the
+ * candidates and is kept unless another is more than 3% faster.
+ * IKR_VERBOSE=1 in the environment logs every candidate's time to stderr.
+ * ikr_get_tuning fills out[24]: for precision p (0 FP64, 1 FP32) and class c
+ * (0 thick, 1 thin), the 6 entries from out[12 p + 6 c] are: measured (1) or
+ * not yet (0); the gram kernel (0 size rule, 1 per-tile matrix-core, 2
+ * k-wide matrix-core, 3 vector-FMA); the gram's block-count scale in percent
+ * (50, 100, 200); the update's bands per block (0 size rule, 4, 8, 16); the
+ * plane kernel's threads per block (0 size rule, 256, 512); the picked
+ * gram's time in ns (summed over the class's batches).  Errors: IKR_E_ARG for
+ * a null handle or out. */
+ikr_status ikr_get_tuning(ikr_handle h, int* out);
+/* Measures the launch shapes now rather than at the first CG run (so that a
+ * caller can count it as set-up): FP64, and FP32 too when precision != 0,
+ * on all occupied bands with the projection rows of the schur option
+ * (0: occupied bands, 1: every computed band); classes already measured or
+ * set are kept.  Synchronises the system's stream.  Errors: IKR_E_ARG for a
+ * null handle, IKR_E_STATE without a ground state. */
+ikr_status ikr_tune_launches(ikr_handle h, int precision, int schur);
+/* Sets the launch shapes by hand (tests, and callers that measured them
+ * before): in[24] in ikr_get_tuning's layout.  An entry whose first value is
+ * 0 is cleared (measured again at the next CG run that needs it); otherwise
+ * its gram kernel (0..3; a kernel the shape does not admit falls back to the
+ * size rule), scale (50, 100, 200), bands per block (0, 4, 8, 16; a group
+ * whose coefficients do not fit 64 KiB of LDS falls back to the size rule)
+ * and plane threads (0, 256, 512) are used as given, and its time is ignored.
+ * Errors: IKR_E_ARG for a null handle or in, or a value outside those sets. */
+ikr_status ikr_set_tuning(ikr_handle h, const int* in);
 
 /* Opt-in kernel timing (process-wide).  Bit i of kernel_mask brackets every
  * launch of hot kernel i of the Sternheimer CG by HIP events on the launching

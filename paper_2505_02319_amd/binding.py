@@ -102,6 +102,9 @@ SIGNATURES = {
                                       C.POINTER(Stats)]),
     "ikr_set_kernel_paths": (C.c_int, [C.c_int]),
     "ikr_get_kernel_paths": (C.c_int, []),
+    "ikr_get_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "ikr_set_tuning": (C.c_int, [C.c_void_p, C.POINTER(C.c_int)]),
+    "ikr_tune_launches": (C.c_int, [C.c_void_p, C.c_int, C.c_int]),
     "ikr_profile_enable": (C.c_int, [C.c_int]),
     "ikr_profile_reset": (C.c_int, []),
     "ikr_profile_kernel_count": (C.c_int, []),
@@ -156,7 +159,7 @@ def default_opts(**kw) -> SolverOpts:
     return o
 
 
-PATH_VECTOR_GRAM, PATH_SPLIT_END, PATH_KWIDE = 1, 2, 4
+PATH_VECTOR_GRAM, PATH_SPLIT_END, PATH_KWIDE, PATH_FIXED = 1, 2, 4, 8
 
 
 def set_kernel_paths(mask: int):
@@ -258,6 +261,39 @@ class ResponseSystem:
             self.import_ground_state(*ground_state)
 
     # ------------------------------------------------------------ queries
+    def tuning(self) -> dict:
+        """The launch shapes measured at the first CG run of each precision:
+        {(precision, batch): {...}} for precision "fp64"/"fp32" and batch
+        "thick"/"thin"; entries not yet measured are left out."""
+        out = (C.c_int * 24)()
+        _check(lib().ikr_get_tuning(self.h, out))
+        names = {0: "size_rule", 1: "per_tile_mfma", 2: "kwide_mfma", 3: "vector"}
+        res = {}
+        for p, pn in enumerate(("fp64", "fp32")):
+            for c, cn in enumerate(("thick", "thin")):
+                o = out[12 * p + 6 * c: 12 * p + 6 * c + 6]
+                if o[0]:
+                    res[(pn, cn)] = {"gram": names.get(o[1], "?"), "gram_scale": o[2] / 100.0,
+                                     "update_bands_per_block": o[3], "plane_threads": o[4],
+                                     "gram_us": o[5] / 1000.0}
+        return res
+
+    def tune_launches(self, precision=1, schur=1):
+        """Measure the CG launch shapes now (FP64, and FP32 when precision),
+        instead of at the first CG run of each precision."""
+        _check(lib().ikr_tune_launches(self.h, int(precision), int(schur)))
+
+    def pin_tuning(self, gram=None, gram_scale=1.0, update_bands_per_block=8,
+                   plane_threads=0):
+        """Pin every precision's and batch class's launch shapes to the given
+        ones (gram: 1 per-tile matrix-core, 2 k-wide, 3 vector); gram=None
+        clears them, so that the next CG runs measure them again (0 for gram,
+        update_bands_per_block or plane_threads: the size rule)."""
+        vals = [0] * 6 if gram is None else [1, int(gram), int(round(100 * gram_scale)),
+                                            int(update_bands_per_block), int(plane_threads), 0]
+        arr = (C.c_int * 24)(*(vals * 4))
+        _check(lib().ikr_set_tuning(self.h, arr))
+
     def info(self) -> Info:
         nk, nb, nbm, ng = C.c_int(), C.c_int(), C.c_int(), C.c_int()
         _check(lib().ikr_get_info(self.h, C.byref(nk), C.byref(nb), C.byref(nbm),

@@ -388,12 +388,71 @@ ikr_status ikr_grad_amplitudes(ikr_handle h, const double* drho_dev, const doubl
 
 ikr_status ikr_set_kernel_paths(int mask) {
   return guarded([&] {
-    IKR_CHECK(mask >= 0 && mask <= 7, IKR_E_ARG, "unknown kernel path bits");
+    IKR_CHECK(mask >= 0 && mask <= 15, IKR_E_ARG, "unknown kernel path bits");
     ikr::set_kernel_paths(mask);
   });
 }
 
 int ikr_get_kernel_paths(void) { return ikr::kernel_paths(); }
+
+ikr_status ikr_get_tuning(ikr_handle h, int* out) {
+  return guarded([&] {
+    IKR_CHECK(out, IKR_E_ARG, "null output");
+    const ikr::System* s = sys_of(h);
+    for (int p = 0; p < 2; ++p)
+      for (int c = 0; c < 2; ++c) {
+        int* o = out + 12 * p + 6 * c;
+        const ikr::KernelTune& t = s->tune[p][c];
+        o[0] = s->tuned[p][c] ? 1 : 0;
+        o[1] = o[0] ? t.gram : 0;
+        o[2] = o[0] ? (int)std::lround(100.0 * t.gram_scale) : 0;
+        o[3] = o[0] ? t.upd_bpt : 0;
+        o[4] = o[0] ? t.plane_pt : 0;
+        o[5] = o[0] ? (int)std::lround(1000.0 * s->tune_us[p][c][0]) : 0;
+      }
+  });
+}
+
+ikr_status ikr_tune_launches(ikr_handle h, int precision, int schur) {
+  return guarded([&] {
+    ikr::System* s = sys_of(h);
+    IKR_CHECK(s->have_gs, IKR_E_STATE, "no ground state");
+    ikr::tune_launches_now(*s, precision, schur);
+  });
+}
+
+ikr_status ikr_set_tuning(ikr_handle h, const int* in) {
+  return guarded([&] {
+    IKR_CHECK(in, IKR_E_ARG, "null input");
+    ikr::System* s = sys_of(h);
+    for (int i = 0; i < 4; ++i) {
+      const int* o = in + 6 * i;
+      if (!o[0]) continue;
+      IKR_CHECK(o[1] >= 0 && o[1] <= 3, IKR_E_ARG, "tuning: gram kernel not in 0..3");
+      IKR_CHECK(o[2] == 50 || o[2] == 100 || o[2] == 200, IKR_E_ARG,
+                "tuning: gram scale not 50, 100 or 200");
+      IKR_CHECK(o[3] == 0 || o[3] == 4 || o[3] == 8 || o[3] == 16, IKR_E_ARG,
+                "tuning: bands per block not 0, 4, 8 or 16");
+      IKR_CHECK(o[4] == 0 || o[4] == 256 || o[4] == 512, IKR_E_ARG,
+                "tuning: plane threads not 0, 256 or 512");
+    }
+    for (int p = 0; p < 2; ++p)
+      for (int c = 0; c < 2; ++c) {
+        const int* o = in + 12 * p + 6 * c;
+        ikr::KernelTune t{};
+        if (o[0]) {
+          t.gram = o[1];
+          t.gram_scale = o[2] / 100.0f;
+          t.upd_bpt = o[3];
+          t.plane_pt = o[4];
+        }
+        s->tune[p][c] = t;
+        s->tuned[p][c] = o[0] != 0;
+        for (double& v : s->tune_us[p][c]) v = 0;
+      }
+    s->graphs.clear();
+  });
+}
 
 ikr_status ikr_profile_enable(int kernel_mask) {
   return guarded([&] { ikr::KTimer::enable((unsigned)kernel_mask); });

@@ -59,6 +59,15 @@ enum KernelPath : int {
   PATH_VECTOR_GRAM = 1,   // projections by the vector-FMA gram kernel
   PATH_SPLIT_END = 2,     // CG iteration end as two launches (finish, compaction)
   PATH_KWIDE = 4,         // k-wide matrix-core gram at any row count
+  PATH_FIXED = 8,         // no setup-time tuning: launch shapes by the size rules alone
+};
+
+// Launch shapes chosen by the setup-time tuner (0 / 1: the size rules).
+struct KernelTune {
+  int gram = 0;            // 0 by size; 1 per-tile matrix-core; 2 k-wide matrix-core; 3 vector
+  float gram_scale = 1;    // multiplier of the gram's block-count target (0.5 .. 2)
+  int upd_bpt = 0;         // 0 by size; else bands per block of the tiled CG update (4, 8, 16)
+  int plane_pt = 0;        // 0 by size; else threads per block of the plane kernel (256, 512)
 };
 
 // Tiles grouped by k-point: the tiles of k are t0[k] .. t0[k + 1] - 1 of the
@@ -74,8 +83,9 @@ void set_kernel_paths(int mask);
 int kernel_paths();
 
 // Elements of the gram's partial-sum buffer for up to ntiles tiles of Mmax
-// rows (nk: k-points of the tile list, when the k-wide gram may be used).
-size_t gram_part_elems(int ntiles, int nb_max, int Mmax, int nk = 0);
+// rows (nk: k-points of the tile list, when the k-wide gram may be used;
+// max_scale: the largest KernelTune::gram_scale the calls may take).
+size_t gram_part_elems(int ntiles, int nb_max, int Mmax, int nk = 0, double max_scale = 1.0);
 int update_nblocks(int nb_max);
 int vec_nblocks(int nb_max);
 int multidot_nblocks(int n);
@@ -94,7 +104,9 @@ template <typename R>
 int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
                   const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
                   int x_stride, cplx<R>* part, hipStream_t st, const int* active = nullptr,
-                  const KTileRange& kr = KTileRange{});
+                  const KTileRange& kr = KTileRange{}, const KernelTune* kt = nullptr);
+// Which gram a call with these arguments takes (1 per-tile matrix-core, 2 k-wide, 3 vector).
+int gram_variant(int Mmax, const KTileRange& kr, const KernelTune* kt);
 
 // The second stage: coef[slot * cstride + m] = sum over the nsc super-chunks.
 template <typename R>

@@ -840,50 +840,62 @@ static int nsc_for(int nb_max, int ntiles, int target, int& sc_len) {
 // the nk k-points (four rounds of one block per CU), each at least one chunk.
 constexpr int KW_BLOCKS = 1024;
 template <typename R> constexpr int kw_chunk() { return sizeof(R) == 8 ? 32 : 64; }
-static int kw_nsc(int nb_max, int nk, int kch, int& sc_len) {
+static int kw_nsc(int nb_max, int nk, int kch, int& sc_len, double scale = 1.0) {
   const int nch = (nb_max + kch - 1) / kch;
-  int nsc = std::max(1, std::min(nch, KW_BLOCKS / std::max(nk, 1)));
+  int nsc = std::max(1, std::min(nch, (int)(scale * KW_BLOCKS) / std::max(nk, 1)));
   const int per = (nch + nsc - 1) / nsc;
   sc_len = per * kch;
   return (nb_max + sc_len - 1) / sc_len;
 }
 
-size_t gram_part_elems(int ntiles, int nb_max, int Mmax, int nk) {
+size_t gram_part_elems(int ntiles, int nb_max, int Mmax, int nk, double max_scale) {
+  const double sc = std::min(2.0, std::max(1.0, max_scale));
   size_t most = 0;
   for (int t = 1; t <= ntiles; ++t) {
     int sc_len;
     most = std::max(most, (size_t)t * nsc_for(nb_max, t,
-                                                 std::max(gram_blocks<double>(t, true),
-                                                          gram_blocks<float>(t, true)),
+                                                 (int)(sc * std::max(gram_blocks<double>(t, true),
+                                                                     gram_blocks<float>(t, true))),
                                                  sc_len));
   }
   if (nk > 0) {
     int sc_len;
-    const int nsc = std::max(kw_nsc(nb_max, nk, kw_chunk<double>(), sc_len),
-                             kw_nsc(nb_max, nk, kw_chunk<float>(), sc_len));
+    const int nsc = std::max(kw_nsc(nb_max, nk, kw_chunk<double>(), sc_len, sc),
+                             kw_nsc(nb_max, nk, kw_chunk<float>(), sc_len, sc));
     most = std::max(most, (size_t)ntiles * nsc);
   }
   return most * Mmax * BT;
+}
+
+int gram_variant(int Mmax, const KTileRange& kr, const KernelTune* kt) {
+  const int paths = kernel_paths();
+  // (k-wide instances: up to 6 tiles of 96 rows, or 5 tiles of 176 rows)
+  const bool kw_ok = kr.t0 && kr.nk > 0 &&
+                     ((kr.ktmax <= 6 && Mmax <= 96) || (kr.ktmax <= 5 && Mmax <= 176));
+  if (paths & PATH_VECTOR_GRAM) return 3;
+  if (paths & PATH_KWIDE) return kw_ok ? 2 : (Mmax <= 64 ? 1 : 3);
+  if (kt && kt->gram == 1 && Mmax <= 64) return 1;
+  if (kt && kt->gram == 2 && kw_ok) return 2;
+  if (kt && kt->gram == 3) return 3;
+  // by size: matrix cores per tile up to 64 rows, k-wide above when it fits
+  if (Mmax <= 64) return 1;
+  return kw_ok ? 2 : 3;
 }
 
 template <typename R>
 int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int Mmax,
                   const cplx<R>* W, size_t wk_stride, int w_stride, const cplx<R>* X,
                   int x_stride, cplx<R>* part, hipStream_t st, const int* active,
-                  const KTileRange& kr) {
+                  const KTileRange& kr, const KernelTune* kt) {
   IKR_CHECK(tl.k && tl.slot0 && tl.nb && nb && Mk && W && X && part, 8,
             "gram: null device pointer");
   if (tl.n <= 0) return 0;
-  const int paths = kernel_paths();
-  // k-wide on the matrix cores: above 64 rows (or forced), when every k has
-  // few enough tiles
-  // (instances: up to 6 tiles of 96 rows, or 5 tiles of 176 rows)
-  const bool kw_fits = (kr.ktmax <= 6 && Mmax <= 96) || (kr.ktmax <= 5 && Mmax <= 176);
-  if (kr.t0 && kr.nk > 0 && kw_fits && !(paths & PATH_VECTOR_GRAM) &&
-      (Mmax > 64 || (paths & PATH_KWIDE))) {
+  const int variant = gram_variant(Mmax, kr, kt);
+  const double scale = kt ? std::min(2.0, std::max(0.5, (double)kt->gram_scale)) : 1.0;
+  if (variant == 2) {
     constexpr int kch = kw_chunk<R>();
     int sc_len;
-    const int nsc = kw_nsc(nb_max, kr.nk, kch, sc_len);
+    const int nsc = kw_nsc(nb_max, kr.nk, kch, sc_len, scale);
     const dim3 grid(round8(nsc * kr.nk));
 #define IKR_GRAMKW(KT, RTM)                                                                   \
   hipLaunchKernelGGL((gram_kw_kernel<R, KT, RTM, kch>), grid, dim3(KW_NT), 0, st, tl, kr, nb,   \
@@ -895,12 +907,12 @@ int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int
     return nsc;
   }
   int sc_len;
-  const bool mfma = Mmax <= 64 && !(paths & PATH_VECTOR_GRAM);
-  const int nsc = nsc_for(nb_max, tl.n, gram_blocks<R>(tl.n, mfma), sc_len);
+  const bool mfma = variant == 1;
+  const int nsc = nsc_for(nb_max, tl.n, (int)(scale * gram_blocks<R>(tl.n, mfma)), sc_len);
   // matrix cores up to 64 rows (faster than the vector kernel on the 48^3
   // cell; with more rows the accumulators and prefetch registers leave one or
-  // two wavefronts per SIMD, and the vector kernel is faster: 48^2 x 96 cell)
-  if (Mmax <= 64 && !(paths & PATH_VECTOR_GRAM)) {
+  // two wavefronts per SIMD)
+  if (mfma) {
     const int rt = (Mmax + 15) / 16;
     const int chm = 64;
     const size_t lds = (size_t)(BT + 16 * rt) * (chm + 1) * sizeof(cplx<R>);
@@ -1133,7 +1145,8 @@ void cscale_vec(size_t n, cplx<R>* x, R a, hipStream_t st) {
                         hipStream_t, const int*, const KTileRange&);                      \
   template int gram_partials<R>(const Tiles&, const int*, int, const int*, int,           \
                                 const cplx<R>*, size_t, int, const cplx<R>*, int,         \
-                                cplx<R>*, hipStream_t, const int*, const KTileRange&);    \
+                                cplx<R>*, hipStream_t, const int*, const KTileRange&,     \
+                                const KernelTune*);                                       \
   template void gram_reduce<R>(const Tiles&, const int*, int, int, const cplx<R>*,        \
                                cplx<R>*, int, hipStream_t, const int*);                   \
   template void update<R>(const Tiles&, const int*, int, const int*, cplx<R>*, int, R,    \

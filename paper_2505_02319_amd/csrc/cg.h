@@ -44,7 +44,7 @@ template <typename R>
 void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, size_t wk,
                int Na, const int* Mq, int Mq_max, const cplx<R>* gam, int cstride,
                cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st,
-               const KTileRange& kr = KTileRange{});
+               const KTileRange& kr = KTileRange{}, const KernelTune* kt = nullptr);
 bool cg_update_kwide(int Mrows, const KTileRange& kr);
 int cg_update_parts(int nb_max, int Mrows, const KTileRange& kr);
 

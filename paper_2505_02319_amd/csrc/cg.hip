@@ -728,7 +728,8 @@ int cg_update_parts(int nb_max, int Mrows, const KTileRange& kr) {
 template <typename R>
 void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, size_t wk,
                int Na, const int* Mq, int Mq_max, const cplx<R>* gam, int cstride,
-               cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st, const KTileRange& kr) {
+               cplx<R>* Wv, cplx<R>* P, R* dpart, hipStream_t st, const KTileRange& kr,
+               const KernelTune* kt) {
   if (tl.n <= 0) return;
   IKR_CHECK(Na + 2 * Mq_max <= cstride, 1, "cg_update: row count");
   if (cg_update_kwide(Na + 2 * Mq_max, kr)) {
@@ -744,6 +745,9 @@ void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, s
   // FP64 caps the band group at 8 (16 would leave one wavefront per SIMD)
   int bpt = blocks >= 1024 ? 16 : (2 * blocks >= 1024 ? 8 : 4);
   if (sizeof(R) == 8 && bpt > 8) bpt = 8;
+  if (kt && (kt->upd_bpt == 4 || kt->upd_bpt == 8 || kt->upd_bpt == 16) &&
+      (size_t)kt->upd_bpt * (Na + 3 * Mq_max) * sizeof(cplx<R>) <= 65536)
+    bpt = kt->upd_bpt;
   const size_t lds = (size_t)bpt * (Na + 3 * Mq_max) * sizeof(cplx<R>);
   IKR_CHECK(lds <= 65536, 1, "cg_update: too many projection rows");
   const dim3 grid(round8(ngb * (BT / bpt) * tl.n));
@@ -837,7 +841,7 @@ void cg_end(const Slots& sl, int nparts, const R* rpart, const R* zpart, const C
                               hipStream_t);                                                    \
   template void cg_update<R>(const Tiles&, const int*, int, const cplx<R>*, size_t, int,       \
                              const int*, int, const cplx<R>*, int, cplx<R>*, cplx<R>*, R*,     \
-                             hipStream_t, const KTileRange&);                                  \
+                             hipStream_t, const KTileRange&, const KernelTune*);               \
   template void cg_step2<R>(const Slots&, const int*, const double*, int, const R*, int,       \
                             const R*, R*, int*, const R*, cplx<R>*, cplx<R>*, const cplx<R>*,  \
                             cplx<R>*, R*, R*, hipStream_t);                                    \

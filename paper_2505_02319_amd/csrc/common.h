@@ -134,10 +134,14 @@ void launch_col_fwd(const Geom& g, const FftTables& t, const Slots& s,
                     const cplx<R>* T, cplx<R>* y, int y_stride,
                     const cplx<R>* x, const R* shift, R scale, hipStream_t st);
 
+// pt: threads per plane block (0: by shape; 256 or 512 where both are built,
+// the planes of 48 x 48 points and larger)
 template <typename R>
 void launch_plane_hv(const Geom& g, const FftTables& t, const Slots& s,
                      const cplx<R>* Tin, cplx<R>* Tout, const R* V,
-                     int v_per_slot, hipStream_t st);
+                     int v_per_slot, hipStream_t st, int pt = 0);
+// Threads per plane block that launch_plane_hv takes for pt on this plane.
+int plane_hv_threads(const Geom& g, int pt, bool fp64);
 
 // Density accumulation: for slots in [s0, s0+ns), with weights wa[slot]
 // (2 f w_k / |Omega|) and wb[slot] (delta f w_k / |Omega|):

@@ -502,19 +502,49 @@ void launch_col_fwd(const Geom& g, const FftTables& t, const Slots& s,
                      g.ncol_max, st);
 }
 
+// Both 256 and 512 threads per block are built for planes of 48 x 48 points
+// and more; smaller planes take 256.
+template <int P, int Q> constexpr bool plane_pt_choice() { return P * Q >= 2304; }
+
+template <typename R, int P, int Q>
+static int plane_pt_pick(int pt) {
+  if constexpr (plane_pt_choice<P, Q>())
+    if (pt == NT || pt == 512) return pt;
+  return plane_threads<R, P, Q>();
+}
+
+int plane_hv_threads(const Geom& g, int pt, bool fp64) {
+#define X(a, b) \
+  if (g.P == a && g.Q == b) return fp64 ? plane_pt_pick<double, a, b>(pt) : plane_pt_pick<float, a, b>(pt);
+  IKR_PLANES(X)
+#undef X
+  return 0;
+}
+
+template <typename R, int P, int Q, int PT>
+static void plane_hv_go(const Geom& g, const cplx<R>* tP, const cplx<R>* tQ, const Slots& s,
+                        const cplx<R>* Tin, cplx<R>* Tout, const R* V, int v_per_slot,
+                        hipStream_t st) {
+  hipLaunchKernelGGL((plane_hv_kernel<R, P, Q, PT>), dim3(g.C, s.n), dim3(PT), 0, st, g, tP,
+                     tQ, s, Tin, Tout, V, v_per_slot);
+  IKR_HIP(hipGetLastError());
+}
+
 template <typename R>
 void launch_plane_hv(const Geom& g, const FftTables& t, const Slots& s,
                      const cplx<R>* Tin, cplx<R>* Tout, const R* V,
-                     int v_per_slot, hipStream_t st) {
+                     int v_per_slot, hipStream_t st, int pt) {
   const cplx<R>* tP = twp<R>(t, t.offP);
   const cplx<R>* tQ = twp<R>(t, t.offQ);
-#define X(a, b)                                                                \
-  if (g.P == a && g.Q == b) {                                                  \
-    hipLaunchKernelGGL((plane_hv_kernel<R, a, b>), dim3(g.C, s.n),            \
-                       dim3(plane_threads<R, a, b>()), 0, st, g, tP, tQ, s, Tin, \
-                       Tout, V, v_per_slot);                                    \
-    IKR_HIP(hipGetLastError());                                                \
-    return;                                                                    \
+#define X(a, b)                                                                      \
+  if (g.P == a && g.Q == b) {                                                        \
+    if constexpr (plane_pt_choice<a, b>()) {                                         \
+      if (plane_pt_pick<R, a, b>(pt) == 512)                                         \
+        return plane_hv_go<R, a, b, 512>(g, tP, tQ, s, Tin, Tout, V, v_per_slot, st); \
+      return plane_hv_go<R, a, b, NT>(g, tP, tQ, s, Tin, Tout, V, v_per_slot, st);   \
+    }                                                                                \
+    return plane_hv_go<R, a, b, plane_threads<R, a, b>()>(g, tP, tQ, s, Tin, Tout, V, \
+                                                          v_per_slot, st);           \
   }
   IKR_PLANES(X)
 #undef X
@@ -602,9 +632,9 @@ template void launch_col_fwd<float>(const Geom&, const FftTables&, const Slots&,
                                     const float*, float, hipStream_t);
 template void launch_plane_hv<double>(const Geom&, const FftTables&, const Slots&,
                                       const double2*, double2*, const double*, int,
-                                      hipStream_t);
+                                      hipStream_t, int);
 template void launch_plane_hv<float>(const Geom&, const FftTables&, const Slots&,
                                      const float2*, float2*, const float*, int,
-                                     hipStream_t);
+                                     hipStream_t, int);
 
 }  // namespace ikr

@@ -452,7 +452,7 @@ void finish_setup(System& s) {
   const int mrows = std::max(s.nocc_max, s.natoms) + 1;
   w.coefA.alloc((size_t)s.J * MAXM);
   w.coefB.alloc((size_t)s.J * MAXM);
-  w.part.alloc(gram_part_elems(s.tiles.n, s.nb_max, std::max({mrows, s.nbands, s.mcg}), nk));
+  w.part.alloc(gram_part_elems(s.tiles.n, s.nb_max, std::max({mrows, s.nbands, s.mcg}), nk, 2.0));
   w.craw.alloc((size_t)s.J * s.mcg);
   w.gam.alloc((size_t)s.J * s.mcg);
   w.rpart.alloc((size_t)s.J * vec_nblocks(s.nb_max));

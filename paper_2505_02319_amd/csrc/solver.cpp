@@ -264,6 +264,196 @@ template <typename R> const cplx<R>* wcg_of(const System& s);
 template <> const double2* wcg_of<double>(const System& s) { return s.w64.wcg.get(); }
 template <> const float2* wcg_of<float>(const System& s) { return s.w32.wcg.get(); }
 
+// ------------------------------------------------------------ launch tuning
+// Three launch shapes of the CG iteration are measured rather than only set
+// by size: the projection gram's kernel (per-tile or k-wide matrix-core, or
+// vector) and its block count, the tiled update's band group, and the
+// threads of the plane kernel.  At the first CG run of a precision, each
+// candidate runs once untimed and five times between HIP events on the CG
+// stream, on the batch the run starts with (when it has more tiles than
+// k-points: the "thick" class) and on two thin batches of at most 8 and 2
+// bands per k-point (the late iterations; their times are added).  The size
+// rule is a candidate too and stays unless another is more than 3% faster
+// (the size rules also adapt to the shrinking batch, a fixed pick does not).
+// All candidates compute the same quantities.  The runs write only scratch:
+// gram partials and coefficients, the plane buffer, and the direction rows
+// p, Ap of the batch's slots, which the CG run overwrites before reading.
+constexpr double TUNE_MARGIN = 0.97;
+
+template <typename R>
+static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<int>>& sets,
+                       int cls, const int* dMq, int Mq_max, const int* dMcg, hipStream_t st) {
+  const int pi = sizeof(R) == 8 ? 0 : 1;
+  const int J = s.J, nbm = s.nb_max, Na = s.natoms;
+  const int Mrows = Na + 2 * Mq_max;
+  const size_t wk = (size_t)s.mcg * nbm;
+  const R* vloc = vloc_of<R>(s);
+  const cplx<R>* wcg = wcg_of<R>(s);
+  const KTileRange kr = s.krange_compact();
+  int* cnt = s.d_cnt.get();
+  struct Batch { Slots sl; Tiles tl; };
+  // compacts one set into the device lists (each timing starts with this)
+  auto select = [&](const std::vector<int>& set) {
+    int na = 0, nt = 0;
+    for (int v : set) na += v != 0;
+    for (int k = 0; k < s.nk; ++k) {
+      int c = 0;
+      for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) c += set[j] != 0;
+      nt += (c + BT - 1) / BT;
+    }
+    IKR_HIP(hipMemcpyAsync(s.d_active.get(), set.data(), J * sizeof(int),
+                           hipMemcpyHostToDevice, st));
+    cg_compact(CgCompact{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_slot_k.get(), J,
+                         s.d_list.get(), s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), cnt,
+                         nullptr, 0, s.d_counters.get() + 2, nullptr, s.d_ktb.get()},
+               s.d_active.get(), st);
+    IKR_HIP(hipStreamSynchronize(st));   // the host vector may go
+    return Batch{Slots{na, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt},
+                 Tiles{nt, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(),
+                       cnt + 1}};
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  IKR_HIP(hipEventCreate(&e0));
+  IKR_HIP(hipEventCreate(&e1));
+  auto elapsed_us = [&] {
+    IKR_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    IKR_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return 1000.0 * ms;
+  };
+  // summed time (us per launch) of launch(batch) over the sets: one untimed
+  // launch, then 1 to 5 timed ones (about 1 ms of launches, at least one);
+  // a candidate already 30% behind the best after a set is not run further
+  auto time_us = [&](auto&& launch, double best) {
+    double tot = 0;
+    for (const auto& set : sets) {
+      const Batch bt = select(set);
+      IKR_HIP(hipEventRecord(e0, st));
+      launch(bt);
+      IKR_HIP(hipEventRecord(e1, st));
+      const double t1 = elapsed_us();
+      const int reps = std::max(1, std::min(5, (int)(1000.0 / std::max(t1, 1.0))));
+      IKR_HIP(hipEventRecord(e0, st));
+      for (int r = 0; r < reps; ++r) launch(bt);
+      IKR_HIP(hipEventRecord(e1, st));
+      tot += elapsed_us() / reps;
+      if (best > 0 && tot > 1.3 * best) return 1e300;
+    }
+    return tot;
+  };
+  // keeps the first candidate (the size rule) unless one is clearly faster
+  auto better = [](double t, double best, bool first) {
+    return first || t < TUNE_MARGIN * best;
+  };
+  KernelTune best{};
+  std::string log;
+  char buf[96];
+  try {
+    // the gram with the reduction of its partials (the block count sets both)
+    double tg = 0;
+    bool first = true;
+    const int vdef = gram_variant(Mrows, kr, nullptr);
+    for (int v = 0; v <= 3; ++v)
+      for (float sc : {1.0f, 0.5f, 2.0f}) {
+        KernelTune c{};
+        c.gram = v;
+        c.gram_scale = sc;
+        if (v == 0 && sc != 1.0f) continue;
+        if (v > 0 && (gram_variant(Mrows, kr, &c) != v || (v == vdef && sc == 1.0f))) continue;
+        const double t = time_us([&](const Batch& bt) {
+          const int nsc = gram_partials<R>(bt.tl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm,
+                                           w.p.get(), nbm, w.part.get(), st, nullptr, kr, &c);
+          gram_reduce<R>(bt.tl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
+        }, tg);
+        std::snprintf(buf, sizeof buf, t < 1e300 ? " %c%.1f:%.1f" : " %c%.1f:-", "SPKV"[v], sc, t);
+        log += buf;
+        if (better(t, tg, first)) { tg = t; best.gram = v; best.gram_scale = sc; }
+        first = false;
+      }
+    s.tune_us[pi][cls][0] = tg;
+    // the update's band group (the coefficients are whatever the gram left)
+    double tu = 0;
+    first = true;
+    log += " |";
+    for (int bpt : {0, 4, 8, 16}) {
+      if (bpt && (size_t)bpt * (Na + 3 * Mq_max) * sizeof(cplx<R>) > 65536) continue;
+      KernelTune c = best;
+      c.upd_bpt = bpt;
+      const double t = time_us([&](const Batch& bt) {
+        cg_update<R>(bt.tl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), s.mcg,
+                     w.w.get(), w.p.get(), w.dpart.get(), st, kr, &c);
+      }, tu);
+      std::snprintf(buf, sizeof buf, t < 1e300 ? " b%d:%.1f" : " b%d:-", bpt, t);
+      log += buf;
+      if (better(t, tu, first)) { tu = t; best.upd_bpt = bpt; }
+      first = false;
+    }
+    s.tune_us[pi][cls][1] = tu;
+    // the plane kernel's block size, where two are built
+    double tp = 0;
+    first = true;
+    log += " |";
+    const int pdef = plane_hv_threads(s.geom, 0, sizeof(R) == 8);
+    for (int pt : {0, 256, 512}) {
+      if (pt && (pt == pdef || plane_hv_threads(s.geom, pt, sizeof(R) == 8) != pt)) continue;
+      const double t = time_us([&](const Batch& bt) {
+        launch_plane_hv<R>(s.geom, s.fft, bt.sl, w.T1.get(), w.T2.get(), vloc, 0, st, pt);
+      }, tp);
+      std::snprintf(buf, sizeof buf, t < 1e300 ? " t%d:%.1f" : " t%d:-", pt ? pt : pdef, t);
+      log += buf;
+      if (better(t, tp, first)) { tp = t; best.plane_pt = pt; }
+      first = false;
+    }
+    s.tune_us[pi][cls][2] = tp;
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  IKR_HIP(hipEventDestroy(e0));
+  IKR_HIP(hipEventDestroy(e1));
+  s.tune[pi][cls] = best;
+  s.tuned[pi][cls] = true;
+  if (std::getenv("IKR_VERBOSE"))
+    std::fprintf(stderr, "[ikr] tuned %s %s batches (S: size rule, P/K/V: per-tile, k-wide, "
+                 "vector gram x block scale; b: bands per update block; t: plane threads; "
+                 "us):%s\n", pi ? "FP32" : "FP64", cls ? "thin" : "thick", log.c_str());
+}
+
+// Batch class of nt tiles: 0 with more tiles than k-points, else 1.
+static int batch_class(const System& s, int nt) { return nt > s.nk ? 0 : 1; }
+
+template <typename R>
+static void tune_launches(System& s, CgWork<R>& w, const std::vector<int>& member,
+                          const int* dMq, int Mq_max, const int* dMcg, hipStream_t st) {
+  const int pi = sizeof(R) == 8 ? 0 : 1;
+  if (kernel_paths() & PATH_FIXED) return;
+  if (s.tuned[pi][0] && s.tuned[pi][1]) return;
+  int nt = 0;
+  std::vector<int> thin8(s.J, 0), thin2(s.J, 0);
+  for (int k = 0; k < s.nk; ++k) {
+    int c = 0;
+    for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) {
+      if (!member[j]) continue;
+      thin8[j] = c < 8;
+      thin2[j] = c < 2;
+      ++c;
+    }
+    nt += (c + BT - 1) / BT;
+  }
+  bool changed = false;
+  if (batch_class(s, nt) == 0 && !s.tuned[pi][0]) {
+    tune_class<R>(s, w, {member}, 0, dMq, Mq_max, dMcg, st);
+    changed = true;
+  }
+  if (!s.tuned[pi][1]) {
+    tune_class<R>(s, w, {thin8, thin2}, 1, dMq, Mq_max, dMcg, st);
+    changed = true;
+  }
+  if (changed) s.graphs.clear();   // graphs captured before hold the size-rule shapes
+}
+
 // Preconditioned CG on Q (H - e_n) Q x = r for the member slots, all at once
 // (discretised Sternheimer equation; zero initial guess; at least min_iter
 // iterations; absolute stopping test on |r|).  The iterates stay in range Q
@@ -303,6 +493,9 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
     (void)hipEventDestroy(j0);
     IKR_HIP(e);
   }
+  tune_launches<R>(s, w, member, dMq, Mq_max, dMcg, st);
+  const int pi = sizeof(R) == 8 ? 0 : 1;
+  const bool tuned = !(kernel_paths() & PATH_FIXED);
   if (w.r.get() != rhs)
     IKR_HIP(hipMemcpyAsync(w.r.get(), rhs, (size_t)J * nbm * sizeof(cplx<R>),
                            hipMemcpyDeviceToDevice, st));
@@ -356,13 +549,16 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
   auto iteration = [&](int na, int nt) {
     Slots sl{na, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
     Tiles ctl{nt, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(), cnt + 1};
+    const int cls = batch_class(s, nt);
+    const KernelTune* kt = tuned && s.tuned[pi][cls] ? &s.tune[pi][cls] : nullptr;
     // p~ = z + beta p ; w~ = (H_loc - e) p~ through the pruned FFT
     KTimer::begin(kid<R>(K_COL_INV), st);
     launch_col_inv<R>(s.geom, s.fft, sl, w.p.get(), nbm, w.T1.get(), w.w.get(), w.beta.get(),
                       w.p.get(), st);
     KTimer::end(kid<R>(K_COL_INV), st, 0.0);
     KTimer::begin(kid<R>(K_PLANE_HV), st);
-    launch_plane_hv<R>(s.geom, s.fft, sl, w.T1.get(), w.T2.get(), vloc, 0, st);
+    launch_plane_hv<R>(s.geom, s.fft, sl, w.T1.get(), w.T2.get(), vloc, 0, st,
+                       kt ? kt->plane_pt : 0);
     KTimer::end(kid<R>(K_PLANE_HV), st, 0.0);
     KTimer::begin(kid<R>(K_COL_FWD), st);
     launch_col_fwd<R>(s.geom, s.fft, sl, w.T2.get(), w.w.get(), nbm, w.p.get(), w.shift.get(),
@@ -372,14 +568,14 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
     KTimer::begin(kid<R>(K_GRAM), st);
     const int nsc = gram_partials<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm,
                                      w.p.get(), nbm, w.part.get(), st, nullptr,
-                                     s.krange_compact());
+                                     s.krange_compact(), kt);
     KTimer::end(kid<R>(K_GRAM), st, 0.0);
     gram_reduce<R>(ctl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
     cg_combine<R>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
                   w.sT.get(), nbn, R(s.dnl), w.gam.get(), st);
     KTimer::begin(kid<R>(K_UPDATE), st);
     cg_update<R>(ctl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), s.mcg,
-                 w.w.get(), w.p.get(), w.dpart.get(), st, s.krange_compact());
+                 w.w.get(), w.p.get(), w.dpart.get(), st, s.krange_compact(), kt);
     KTimer::end(kid<R>(K_UPDATE), st, 0.0);
     // alpha ; x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, <r, z>
     KTimer::begin(kid<R>(K_CG_STEP), st);
@@ -533,6 +729,22 @@ void apply_sternheimer_op(System& s, const std::vector<int>& member, const int* 
 }
 
 }  // namespace
+
+void tune_launches_now(System& s, int precision, int schur) {
+  IKR_CHECK(s.have_gs, 2, "ground state not set up");
+  const bool use_schur = schur && s.nbands > s.nocc_max;
+  const int* dMq = use_schur ? s.d_nbands_k.get() : s.d_nocc_k.get();
+  const int* dMcg = use_schur ? s.d_mcg_all.get() : s.d_mcg_occ.get();
+  const int Mq_max = use_schur ? s.nbands : s.nocc_max;
+  const std::vector<int> all(s.J, 1);
+  tune_launches<double>(s, s.w64, all, dMq, Mq_max, dMcg, s.stream);
+  if (precision) {
+    ensure_fp32(s);
+    tune_launches<float>(s, s.w32, all, dMq, Mq_max, dMcg, s.stream);
+  }
+  IKR_HIP(hipStreamSynchronize(s.stream));
+}
+
 
 // ---------------------------------------------------------------- chi0
 Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,

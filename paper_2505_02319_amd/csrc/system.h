@@ -210,6 +210,12 @@ struct System {
   DBuf<int> d_rec_list;
   std::vector<double2> rec_G;
   CgGraphs graphs;
+  // Launch shapes of the CG iteration, measured at the first CG run that
+  // needs them: [precision: 0 FP64, 1 FP32][batch: 0 more tiles than
+  // k-points, 1 at most one tile per k-point on average]
+  KernelTune tune[2][2];
+  bool tuned[2][2] = {{false, false}, {false, false}};
+  double tune_us[2][2][3] = {};    // measured times of the picks (gram, update, plane)
 
   std::string name;
 };
@@ -265,6 +271,9 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
 std::vector<double> grad_amplitudes(System& s, const double* drho_ext, const double* lam_ext,
                                     double cg_tol, ikr_stats* st);
 void ensure_fp32(System& s);   // FP32 work space and operator copies (lazy)
+// Measures the CG launch shapes now (FP64, and FP32 too when precision != 0)
+// for the projection rows of the schur option, where not measured yet.
+void tune_launches_now(System& s, int precision, int schur);
 // out = T v (Kerker, eq. kerker), grid vectors in the external layout (may alias)
 void apply_kerker_ext(System& s, double alpha, const double* v_ext, double* out_ext);
 // b = chi0 dV0 for the displacement of one atom (local and nonlocal parts)

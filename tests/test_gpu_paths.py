@@ -125,7 +125,7 @@ def test_graph_replay_matches_launches_on_forced_paths(paths, mask):
 def test_kernel_path_mask_is_checked():
     from paper_2505_02319_amd import IkrError, set_kernel_paths
     with pytest.raises(IkrError):
-        set_kernel_paths(8)
+        set_kernel_paths(16)
 
 
 @pytest.mark.parametrize("name", ["small_metal", "wide_k"])

@@ -154,6 +154,9 @@ def _make_configs() -> Dict[str, SystemSpec]:
                                   nextra=2)
     c["tiny_metal"] = c["tiny"].with_(name="tiny_metal", kgrid=(1, 1, 2),
                                       nocc=3, nextra=7, temperature=0.002)
+    # A 48 x 48 plane (the smallest on which the plane kernel is built at
+    # both 256 and 512 threads) with the few bands of the tiny cell.
+    c["tiny48"] = c["tiny"].with_(name="tiny48", fft=(48, 48, 48))
     return c
 
 
