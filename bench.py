@@ -365,10 +365,29 @@ def trace_summary(path, kernel, last):
     if last > 0:
         sel = sel[-last:]
     us = [(int(r[ke]) - int(r[ks])) * 1e-3 for r in sel]
+    # occupancy of the GPU over the window of the selected dispatches: the
+    # union of all kernels' intervals in it, and the idle time between them
+    gaps = None
+    if sel:
+        w0, w1 = int(sel[0][ks]), int(sel[-1][ke])
+        iv = sorted((int(r[ks]), int(r[ke])) for r in rows
+                    if int(r[ks]) >= w0 and int(r[ke]) <= w1)
+        busy, cur0, cur1, idle_n = 0, iv[0][0], iv[0][1], 0
+        for a, b in iv[1:]:
+            if a > cur1:
+                busy += cur1 - cur0
+                cur0, cur1 = a, b
+                idle_n += 1
+            else:
+                cur1 = max(cur1, b)
+        busy += cur1 - cur0
+        win = w1 - w0
+        gaps = {"window_ms": win * 1e-6, "busy_ms": busy * 1e-6, "idle_frac": 1 - busy / win,
+                "dispatches": len(iv), "idle_us_per_dispatch": (win - busy) * 1e-3 / len(iv)}
     print(json.dumps({"trace": os.path.basename(path), "kernel": kernel, "dispatches": len(us),
                       "avg_us": sum(us) / max(len(us), 1), "min_us": min(us) if us else None,
                       "max_us": max(us) if us else None,
-                      "names": sorted({r[kn] for r in sel})}), flush=True)
+                      "names": sorted({r[kn] for r in sel}), "occupancy": gaps}), flush=True)
 
 
 def pmc_summary(path, kernel, last):

@@ -421,8 +421,8 @@ static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<in
                  "us):%s\n", pi ? "FP32" : "FP64", cls ? "thin" : "thick", log.c_str());
 }
 
-// Batch class of nt tiles: 0 with more tiles than k-points, else 1.
-static int batch_class(const System& s, int nt) { return nt > s.nk ? 0 : 1; }
+// Batch class of nt tiles over nkl k-points: 0 with more tiles than k-points, else 1.
+static int batch_class_of(int nt, int nkl) { return nt > nkl ? 0 : 1; }
 
 template <typename R>
 static void tune_launches(System& s, CgWork<R>& w, const std::vector<int>& member,
@@ -443,7 +443,7 @@ static void tune_launches(System& s, CgWork<R>& w, const std::vector<int>& membe
     nt += (c + BT - 1) / BT;
   }
   bool changed = false;
-  if (batch_class(s, nt) == 0 && !s.tuned[pi][0]) {
+  if (batch_class_of(nt, s.nk) == 0 && !s.tuned[pi][0]) {
     tune_class<R>(s, w, {member}, 0, dMq, Mq_max, dMcg, st);
     changed = true;
   }
@@ -454,103 +454,157 @@ static void tune_launches(System& s, CgWork<R>& w, const std::vector<int>& membe
   if (changed) s.graphs.clear();   // graphs captured before hold the size-rule shapes
 }
 
-// Preconditioned CG on Q (H - e_n) Q x = r for the member slots, all at once
-// (discretised Sternheimer equation; zero initial guess; at least min_iter
-// iterations; absolute stopping test on |r|).  The iterates stay in range Q
-// (remark after Lemma cgtol_E) through the exact projection of p and Ap that
-// one gram of p~ = z + beta p against [projectors | phi, H phi] provides.
-// The active set is compacted on the device after every iteration; the
-// host reads its size one iteration late (an upper bound, since bands only
-// leave the set), so the stream never drains between iterations.  With
-// s.cg_graph set (and no kernel timing), each iteration is one replay of a
-// captured graph whose grids cover the live count rounded up to a power of
-// two; the kernels skip rows past the device count, so a graph stays valid
-// while the set shrinks, and a smaller one is taken once the count halves.
+// Device state one CG run works with (the system's compaction lists,
+// counters and partial sums, and the stream the run is enqueued on).
+template <typename R> struct CgCtx {
+  hipStream_t st;
+  int *active, *iters, *counters, *list, *ctk, *cto, *ctn, *cnt, *ktb;
+  double* tol2;
+  DBuf<int>* hist;
+  HBuf<int>* h_cnt;
+  int* d_hcnt;
+  cplx<R>* part;
+};
+
+template <typename R> CgCtx<R> main_ctx(System& s, CgWork<R>& w, hipStream_t st) {
+  return CgCtx<R>{st, s.d_active.get(), s.d_iters.get(), s.d_counters.get(), s.d_list.get(),
+                  s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_cnt.get(), s.d_ktb.get(),
+                  s.d_tol2.get(), &s.d_hist, &s.h_cnt, s.d_hcnt, w.part.get()};
+}
+
+
+// Preconditioned CG on Q (H - e_n) Q x = r for the member slots, all at once (discretised Sternheimer equation; zero initial guess; at least
+// min_iter iterations; absolute stopping test on |r|).  The iterates stay in
+// range Q (remark after Lemma cgtol_E) through the exact projection of p and
+// Ap that one gram of p~ = z + beta p against [projectors | phi, H phi]
+// provides.  The active set is compacted on the device after every
+// iteration; the host reads its size one iteration late (an upper bound,
+// since bands only leave the set), so the stream never drains between
+// iterations.  With s.cg_graph set (and no kernel timing), each
+// iteration is one replay of a captured graph whose grids cover the live
+// count rounded up to a power of two; the kernels skip rows past the device
+// count, so a graph stays valid while the set shrinks, and a smaller one is
+// taken once the count halves.  start() enqueues the set-up, step() one
+// iteration and the lagged read, finish() waits and collects the counts.
 //
 // keep_x: the member rows of w.x hold an initial guess and rhs the initial
 // residual b - A x (defect correction); otherwise the guess is zero and rhs = b.
-template <typename R>
-CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>& member,
-             const std::vector<double>& tol_slot, int min_iter, int max_iter,
-             const int* dMq, int Mq_max, const int* dMcg, bool keep_x = false) {
-  const bool use_graph = s.cg_graph != 0 && !KTimer::enabled();
-  const hipStream_t st = use_graph ? s.graphs.get_stream() : s.stream;
-  const int J = s.J, nbm = s.nb_max, nbn = s.nbands, Na = s.natoms;
-  const R inv_ng = R(1.0 / s.ng);
-  const R* vloc = vloc_of<R>(s);
-  const cplx<R>* wcg = wcg_of<R>(s);
-  const size_t wk = (size_t)s.mcg * nbm;
-  const int Mrows = Na + 2 * Mq_max;
-  CgOut out;
-  int nmem = 0;
-  for (int v : member) nmem += v != 0;
-  if (nmem == 0 || max_iter <= 0) return out;
-  if (use_graph) {   // the private stream starts after the work queued so far
-    hipEvent_t j0;
-    IKR_HIP(hipEventCreateWithFlags(&j0, hipEventDisableTiming));
-    (void)hipEventRecord(j0, s.stream);
-    const hipError_t e = hipStreamWaitEvent(st, j0, 0);
-    (void)hipEventDestroy(j0);
-    IKR_HIP(e);
+template <typename R> struct CgRunner {
+  System& s;
+  CgWork<R>& w;
+  CgCtx<R> c;
+  const std::vector<int>& member;
+  const int* dMq;
+  int Mq_max;
+  const int* dMcg;
+  int min_iter, max_iter, nkl;
+  bool use_graph, timing;
+  int J, nbm, nbn, Na, Mrows, nvb, nup, nmem = 0, nact = 0, nct = 0, nt0 = 0;
+  int it = 0, iters = 0, lag_seen = 0, lag_copied = 0;
+  bool done = false;
+  size_t wk;
+  CgScalars<R> cs{};
+  CgCompact cp{};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+
+  CgRunner(System& s_, CgWork<R>& w_, const CgCtx<R>& c_, const std::vector<int>& member_,
+           int nkl_, int min_iter_, int max_iter_, const int* dMq_, int Mq_max_,
+           const int* dMcg_, bool graph)
+      : s(s_), w(w_), c(c_), member(member_), dMq(dMq_), Mq_max(Mq_max_), dMcg(dMcg_),
+        min_iter(min_iter_), max_iter(max_iter_), nkl(nkl_) {
+    use_graph = graph;
+    timing = KTimer::enabled();
+    J = s.J;
+    nbm = s.nb_max;
+    nbn = s.nbands;
+    Na = s.natoms;
+    Mrows = Na + 2 * Mq_max;
+    wk = (size_t)s.mcg * nbm;
+    for (int v : member) nmem += v != 0;
+    done = nmem == 0 || max_iter <= 0;
   }
-  tune_launches<R>(s, w, member, dMq, Mq_max, dMcg, st);
-  const int pi = sizeof(R) == 8 ? 0 : 1;
-  const bool tuned = !(kernel_paths() & PATH_FIXED);
-  if (w.r.get() != rhs)
-    IKR_HIP(hipMemcpyAsync(w.r.get(), rhs, (size_t)J * nbm * sizeof(cplx<R>),
-                           hipMemcpyDeviceToDevice, st));
-  std::vector<double> tol2(J);
-  for (int j = 0; j < J; ++j) tol2[j] = tol_slot[j] * tol_slot[j];
-  IKR_HIP(hipMemcpyAsync(s.d_tol2.get(), tol2.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
-  IKR_HIP(hipMemcpyAsync(s.d_active.get(), member.data(), J * sizeof(int), hipMemcpyHostToDevice, st));
-  IKR_HIP(hipMemsetAsync(s.d_iters.get(), 0, J * sizeof(int), st));
-  // counters: [1] slots that missed their tolerance, [2] compaction step
-  IKR_HIP(hipMemsetAsync(s.d_counters.get(), 0, 8 * sizeof(int), st));
-  if (s.d_hist.n < (size_t)2 * (max_iter + 1)) {
-    s.graphs.clear();   // captured graphs hold the old pointer
-    s.d_hist.alloc((size_t)2 * (max_iter + 1));
+  ~CgRunner() {
+    for (hipEvent_t& e : ev)
+      if (e) (void)hipEventDestroy(e);
   }
-  CgScalars<R> cs{w.rz.get(), w.alpha.get(), w.beta.get(), w.rnorm2.get(), s.d_tol2.get(),
-                  s.d_iters.get(), s.d_counters.get(), s.d_counters.get() + 1,
-                  min_iter, max_iter};
-  const int nvb = vec_nblocks(nbm);
-  const int nup = cg_update_parts(nbm, Mrows, s.krange_compact());
-  int* cnt = s.d_cnt.get();
-  CgCompact cp{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_slot_k.get(), J,
-               s.d_list.get(), s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), cnt,
-               s.d_hist.get(), max_iter + 1, s.d_counters.get() + 2, s.d_hcnt,
-               s.d_ktb.get()};
-  // host bound on the tiles of the member set
-  int nct = 0;
-  for (int k = 0; k < s.nk; ++k) {
-    int c = 0;
-    for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) c += member[j] != 0;
-    nct += (c + BT - 1) / BT;
+  KTileRange kr() const { return KTileRange{s.nk, c.ktb, s.ktmax}; }
+
+  void start(const cplx<R>* rhs, const std::vector<double>& tol_slot, bool keep_x) {
+    if (done) return;
+    const hipStream_t st = c.st;
+    if (st != s.stream) {   // the lane starts after the work queued so far
+      hipEvent_t j0;
+      IKR_HIP(hipEventCreateWithFlags(&j0, hipEventDisableTiming));
+      (void)hipEventRecord(j0, s.stream);
+      const hipError_t e = hipStreamWaitEvent(st, j0, 0);
+      (void)hipEventDestroy(j0);
+      IKR_HIP(e);
+    }
+    if (w.r.get() != rhs)
+      IKR_HIP(hipMemcpyAsync(w.r.get(), rhs, (size_t)J * nbm * sizeof(cplx<R>),
+                             hipMemcpyDeviceToDevice, st));
+    std::vector<double> tol2(J);
+    for (int j = 0; j < J; ++j) tol2[j] = tol_slot[j] * tol_slot[j];
+    IKR_HIP(hipMemcpyAsync(c.tol2, tol2.data(), J * sizeof(double), hipMemcpyHostToDevice, st));
+    IKR_HIP(hipMemcpyAsync(c.active, member.data(), J * sizeof(int), hipMemcpyHostToDevice, st));
+    IKR_HIP(hipMemsetAsync(c.iters, 0, J * sizeof(int), st));
+    // counters: [1] slots that missed their tolerance, [2] compaction step
+    IKR_HIP(hipMemsetAsync(c.counters, 0, 8 * sizeof(int), st));
+    // (the pageable sources above are copied before the calls return)
+    if (c.hist->n < (size_t)2 * (max_iter + 1)) {
+      if (c.hist == &s.d_hist) s.graphs.clear();   // captured graphs hold the old pointer
+      c.hist->alloc((size_t)2 * (max_iter + 1));
+    }
+    cs = CgScalars<R>{w.rz.get(), w.alpha.get(), w.beta.get(), w.rnorm2.get(), c.tol2,
+                      c.iters, c.counters, c.counters + 1, min_iter, max_iter};
+    nvb = vec_nblocks(nbm);
+    nup = cg_update_parts(nbm, Mrows, kr());
+    cp = CgCompact{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_slot_k.get(), J,
+                   c.list, c.ctk, c.cto, c.ctn, c.cnt, c.hist->get(), max_iter + 1,
+                   c.counters + 2, c.d_hcnt, c.ktb};
+    // host bound on the tiles of the member set
+    for (int k = 0; k < s.nk; ++k) {
+      int n = 0;
+      for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) n += member[j] != 0;
+      nct += (n + BT - 1) / BT;
+    }
+    nt0 = nct;
+    nact = nmem;
+    {
+      CgCompact c0 = cp;
+      c0.hist = nullptr;
+      c0.hcnt = nullptr;
+      cg_compact(c0, c.active, st);
+    }
+    // p = 0 (and x = 0 unless it is the initial guess) for the members only:
+    // other slots keep what they hold
+    cg_zero<R>(Slots{nact, s.d_slot_k.get(), c.active, c.list, c.cnt}, nbm,
+               keep_x ? nullptr : w.x.get(), w.p.get(), st);
+    {
+      // z = M^-1 r, rz = <r, z>, beta = 0
+      Slots sl{nact, s.d_slot_k.get(), c.active, c.list, c.cnt};
+      cg_start<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.pshift.get(), w.r.get(), w.w.get(),
+                  w.rpart.get(), w.zpart.get(), st);
+      cg_finish<R>(sl, nvb, w.rpart.get(), w.zpart.get(), cs, c.active, 1, st);
+    }
+    IKR_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    IKR_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+      // no compaction is in flight here (every run ends with a stream sync)
+    for (int i = 0; i < 4; ++i) c.h_cnt->p[i] = -1;
   }
-  int nact = nmem;
-  {
-    CgCompact c0 = cp;
-    c0.hist = nullptr;
-    c0.hcnt = nullptr;
-    cg_compact(c0, s.d_active.get(), st);
-  }
-  // p = 0 (and x = 0 unless it is the initial guess) for the members only:
-  // other slots keep what they hold
-  cg_zero<R>(Slots{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt}, nbm,
-             keep_x ? nullptr : w.x.get(), w.p.get(), st);
-  {
-    // z = M^-1 r, rz = <r, z>, beta = 0
-    Slots sl{nact, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
-    cg_start<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.pshift.get(), w.r.get(), w.w.get(),
-                w.rpart.get(), w.zpart.get(), st);
-    cg_finish<R>(sl, nvb, w.rpart.get(), w.zpart.get(), cs, s.d_active.get(), 1, st);
-  }
+
   // one CG iteration over grids of na rows and nt tiles
-  auto iteration = [&](int na, int nt) {
-    Slots sl{na, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt};
-    Tiles ctl{nt, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(), cnt + 1};
-    const int cls = batch_class(s, nt);
-    const KernelTune* kt = tuned && s.tuned[pi][cls] ? &s.tune[pi][cls] : nullptr;
+  void iteration(int na, int nt) {
+    const hipStream_t st = c.st;
+    const int pi = sizeof(R) == 8 ? 0 : 1;
+    const R inv_ng = R(1.0 / s.ng);
+    const R* vloc = vloc_of<R>(s);
+    const cplx<R>* wcg = wcg_of<R>(s);
+    Slots sl{na, s.d_slot_k.get(), c.active, c.list, c.cnt};
+    Tiles ctl{nt, c.ctk, c.cto, c.ctn, c.list, c.cnt + 1};
+    const int cls = batch_class_of(nt, nkl);
+    const KernelTune* kt = !(kernel_paths() & PATH_FIXED) && s.tuned[pi][cls]
+                               ? &s.tune[pi][cls] : nullptr;
     // p~ = z + beta p ; w~ = (H_loc - e) p~ through the pruned FFT
     KTimer::begin(kid<R>(K_COL_INV), st);
     launch_col_inv<R>(s.geom, s.fft, sl, w.p.get(), nbm, w.T1.get(), w.w.get(), w.beta.get(),
@@ -567,120 +621,141 @@ CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>
     // q, a, h = W_k^H p~ ; update coefficients ; Ap and p = Q p~ ; <p, Ap>
     KTimer::begin(kid<R>(K_GRAM), st);
     const int nsc = gram_partials<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm,
-                                     w.p.get(), nbm, w.part.get(), st, nullptr,
-                                     s.krange_compact(), kt);
+                                     w.p.get(), nbm, c.part, st, nullptr, kr(), kt);
     KTimer::end(kid<R>(K_GRAM), st, 0.0);
-    gram_reduce<R>(ctl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
+    gram_reduce<R>(ctl, dMcg, Mrows, nsc, c.part, w.craw.get(), s.mcg, st);
     cg_combine<R>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
                   w.sT.get(), nbn, R(s.dnl), w.gam.get(), st);
     KTimer::begin(kid<R>(K_UPDATE), st);
     cg_update<R>(ctl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), s.mcg,
-                 w.w.get(), w.p.get(), w.dpart.get(), st, s.krange_compact(), kt);
+                 w.w.get(), w.p.get(), w.dpart.get(), st, kr(), kt);
     KTimer::end(kid<R>(K_UPDATE), st, 0.0);
     // alpha ; x += alpha p, r -= alpha Ap, z = M^-1 r, |r|^2, <r, z>
     KTimer::begin(kid<R>(K_CG_STEP), st);
-    cg_step2<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.dpart.get(), nup, w.rz.get(), w.alpha.get(),
-                s.d_active.get(), w.pshift.get(), w.x.get(), w.r.get(), w.p.get(), w.w.get(),
-                w.rpart.get(), w.zpart.get(), st);
+    cg_step2<R>(sl, s.d_nb.get(), s.d_kin.get(), nbm, w.dpart.get(), nup, w.rz.get(),
+                w.alpha.get(), c.active, w.pshift.get(), w.x.get(), w.r.get(), w.p.get(),
+                w.w.get(), w.rpart.get(), w.zpart.get(), st);
     KTimer::end(kid<R>(K_CG_STEP), st, 0.0);
     // beta, convergence, and the active set of the next iteration
-    cg_end<R>(sl, nvb, w.rpart.get(), w.zpart.get(), cs, s.d_active.get(), cp, st);
-  };
-  auto pow2_cap = [](int n, int cap) {
+    cg_end<R>(sl, nvb, w.rpart.get(), w.zpart.get(), cs, c.active, cp, st);
+  }
+
+  static int pow2_cap(int n, int cap) {
     int p = 1;
     while (p < n) p <<= 1;
     return std::min(p, cap);
-  };
-  hipEvent_t ev[2];
-  IKR_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-  IKR_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-  int iters = 0;
-  const bool timing = KTimer::enabled();
-  // no compaction is in flight here (every run ends with a stream sync)
-  for (int i = 0; i < 4; ++i) s.h_cnt.p[i] = -1;
-  try {
-    for (int it = 0; it < max_iter; ++it) {
-      if (use_graph) {
-        const int na = pow2_cap(nact, J), nt = pow2_cap(nct, s.tiles.n);
-        const CgGraphs::Key key{(long long)sizeof(R), na, nt, (long long)(intptr_t)dMq,
-                                min_iter, max_iter, kernel_paths()};
-        const hipGraphExec_t ge = s.graphs.get(key, st, [&] { iteration(na, nt); });
-        IKR_HIP(hipGraphLaunch(ge, st));
-      } else {
-        iteration(nact, nct);
-      }
-      iters = it + 1;
-      if (s.cg_plain) {   // reference loop: the host waits for every iteration's count
-        IKR_HIP(hipMemcpyAsync(s.h_cnt.p, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-        IKR_HIP(hipStreamSynchronize(st));
-        nact = s.h_cnt.p[0];
-        nct = s.h_cnt.p[1];
-        s.h_cnt.p[0] = s.h_cnt.p[1] = -1;
-        if (nact == 0) break;
-        continue;
-      }
+  }
+
+  // Enqueues one iteration and reads the live counts of the one before;
+  // false once the run is over (converged, or max_iter iterations).
+  bool step() {
+    if (done) return false;
+    const hipStream_t st = c.st;
+    if (use_graph) {
+      const int na = pow2_cap(nact, J), nt = pow2_cap(nct, s.tiles.n);
+      const CgGraphs::Key key{(long long)sizeof(R), na, nt, (long long)(intptr_t)dMq,
+                              min_iter, max_iter, kernel_paths()};
+      const hipGraphExec_t ge = s.graphs.get(key, st, [&] { iteration(na, nt); });
+      IKR_HIP(hipGraphLaunch(ge, st));
+    } else {
+      iteration(nact, nct);
+    }
+    iters = it + 1;
+    if (s.cg_plain) {   // reference loop: the host waits for every iteration's count
+      IKR_HIP(hipMemcpyAsync(c.h_cnt->p, c.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      IKR_HIP(hipStreamSynchronize(st));
+      nact = c.h_cnt->p[0];
+      nct = c.h_cnt->p[1];
+      c.h_cnt->p[0] = c.h_cnt->p[1] = -1;
+    } else {
       // the compaction of iteration it writes its counts to h_cnt[2 (it & 1)]
       IKR_HIP(hipEventRecord(ev[it & 1], st));
       if (it >= 1) {
         IKR_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
-        volatile int* hc = s.h_cnt.p + 2 * ((it - 1) & 1);
+        volatile int* hc = c.h_cnt->p + 2 * ((it - 1) & 1);
         if (hc[0] < 0 || hc[1] < 0) {
           // not seen yet: the device counts are as fresh or fresher, so also a bound
-          IKR_HIP(hipMemcpyAsync((void*)hc, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+          IKR_HIP(hipMemcpyAsync((void*)hc, c.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
           IKR_HIP(hipStreamSynchronize(st));
+          ++lag_copied;
+        } else {
+          ++lag_seen;
         }
         nact = hc[0];
         nct = hc[1];
         hc[0] = hc[1] = -1;   // consumed: iteration it + 1 writes this slot next
-        if (nact == 0) break;
       }
     }
+    ++it;
+    if (nact == 0 || it >= max_iter) done = true;
+    return !done;
+  }
+
+  CgOut finish() {
+    CgOut out;
+    if (nmem == 0 || max_iter <= 0) return out;
+    const hipStream_t st = c.st;
     IKR_HIP(hipStreamSynchronize(st));
+    if (std::getenv("IKR_VERBOSE"))
+      std::fprintf(stderr, "[ikr] CG run %s: %d iterations, %d bands; live counts read from "
+                   "pinned memory %d times, copied %d times\n",
+                   sizeof(R) == 8 ? "FP64" : "FP32", iters, nmem, lag_seen, lag_copied);
+    const std::vector<int> hits = download(c.iters, J, st);
+    for (int j = 0; j < J; ++j) out.n_ham += hits[j];
+    const std::vector<int> ctr = download(c.counters, 4, st);
+    const std::vector<int> last = download(c.cnt, 2, st);
+    out.noconv = ctr[1] + last[0];
+    if (timing) {
+      // algorithmic bytes of the launches, from the live counts of each iteration
+      double nb_avg = 0, ncol_avg = 0;
+      for (int j = 0; j < J; ++j) {
+        nb_avg += s.kp[s.slot_k[j]].nb;
+        ncol_avg += s.kp[s.slot_k[j]].ncol;
+      }
+      nb_avg /= J;
+      ncol_avg /= J;
+      const double SZ = sizeof(cplx<R>), colC = ncol_avg * s.L.C;
+      const std::vector<int> hist = download(c.hist->get(), (size_t)2 * iters, st);
+      double b[K_COUNT] = {};
+      int na = nmem, nt = nt0;
+      for (int i = 0; i < iters; ++i) {
+        b[K_COL_INV] += na * (3.0 * nb_avg + colC) * SZ;
+        b[K_PLANE_HV] += na * 2.0 * colC * SZ + (na > 0 ? sizeof(R) * (double)s.ng : 0.0);
+        b[K_COL_FWD] += na * (colC * SZ + nb_avg * (2.0 * SZ + 8.0));
+        b[K_GRAM] += nt * Mrows * nb_avg * SZ + na * nb_avg * SZ;
+        b[K_UPDATE] += nt * Mrows * nb_avg * SZ + na * 4.0 * nb_avg * SZ;
+        b[K_CG_STEP] += na * nb_avg * (7.0 * SZ + 8.0);
+        na = hist[2 * i];
+        nt = hist[2 * i + 1];
+      }
+      for (int id = 0; id < K_PLANE_RHO; ++id)
+        if (b[id] > 0) KTimer::add_bytes(kid<R>(id), b[id]);
+    }
+    return out;
+  }
+};
+
+template <typename R>
+CgOut run_cg(System& s, CgWork<R>& w, const cplx<R>* rhs, const std::vector<int>& member,
+             const std::vector<double>& tol_slot, int min_iter, int max_iter,
+             const int* dMq, int Mq_max, const int* dMcg, bool keep_x = false) {
+  const bool use_graph = s.cg_graph != 0 && !KTimer::enabled();
+  int nmem = 0;
+  for (int v : member) nmem += v != 0;
+  if (nmem == 0 || max_iter <= 0) return CgOut{};
+  tune_launches<R>(s, w, member, dMq, Mq_max, dMcg, s.stream);
+  // (a graph's private stream starts after the work queued so far: start())
+  const hipStream_t st = use_graph ? s.graphs.get_stream() : s.stream;
+  CgRunner<R> r(s, w, main_ctx<R>(s, w, st), member, s.nk, min_iter, max_iter, dMq, Mq_max,
+                dMcg, use_graph);
+  try {
+    r.start(rhs, tol_slot, keep_x);
+    while (r.step()) {}
+    return r.finish();
   } catch (...) {
     (void)hipStreamSynchronize(st);
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
     throw;
   }
-  IKR_HIP(hipEventDestroy(ev[0]));
-  IKR_HIP(hipEventDestroy(ev[1]));
-  const std::vector<int> hits = download(s.d_iters.get(), J, st);
-  for (int j = 0; j < J; ++j) out.n_ham += hits[j];
-  const std::vector<int> ctr = download(s.d_counters.get(), 4, st);
-  const std::vector<int> last = download(cnt, 2, st);
-  out.noconv = ctr[1] + last[0];
-  if (timing) {
-    // algorithmic bytes of the launches, from the live counts of each iteration
-    double nb_avg = 0, ncol_avg = 0;
-    for (int j = 0; j < J; ++j) {
-      nb_avg += s.kp[s.slot_k[j]].nb;
-      ncol_avg += s.kp[s.slot_k[j]].ncol;
-    }
-    nb_avg /= J;
-    ncol_avg /= J;
-    const double SZ = sizeof(cplx<R>), colC = ncol_avg * s.L.C;
-    const std::vector<int> hist = download(s.d_hist.get(), (size_t)2 * iters, st);
-    double b[K_COUNT] = {};
-    int na = nmem, nt = 0;
-    for (int k = 0; k < s.nk; ++k) {
-      int c = 0;
-      for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) c += member[j] != 0;
-      nt += (c + BT - 1) / BT;
-    }
-    for (int it = 0; it < iters; ++it) {
-      b[K_COL_INV] += na * (3.0 * nb_avg + colC) * SZ;
-      b[K_PLANE_HV] += na * 2.0 * colC * SZ + (na > 0 ? sizeof(R) * (double)s.ng : 0.0);
-      b[K_COL_FWD] += na * (colC * SZ + nb_avg * (2.0 * SZ + 8.0));
-      b[K_GRAM] += nt * Mrows * nb_avg * SZ + na * nb_avg * SZ;
-      b[K_UPDATE] += nt * Mrows * nb_avg * SZ + na * 4.0 * nb_avg * SZ;
-      b[K_CG_STEP] += na * nb_avg * (7.0 * SZ + 8.0);
-      na = hist[2 * it];
-      nt = hist[2 * it + 1];
-    }
-    for (int id = 0; id < K_PLANE_RHO; ++id)
-      if (b[id] > 0) KTimer::add_bytes(kid<R>(id), b[id]);
-  }
-  return out;
 }
 
 // w.w := Q (H - e_j) Q v (FP64) for the member slots, with v in the member
