@@ -76,6 +76,48 @@ def cpu_baseline(spec, n_ham_per_solve, seconds):
             "seconds_per_band_iteration": per_iter}
 
 
+def whole_solve_small(args):
+    """The whole solve on the small cell (cfg1, the 2-atom cell at Gamma) by the
+    oracle's Alg. 1 on the host and by the library on the GPU, same b, tau,
+    strategy and preconditioner: an end-to-end comparison beside the sampled
+    baseline of the bench workload (whose oracle solve would take hours)."""
+    import numpy as np
+    import torch
+
+    from oracle.gmres import inexact_gmres
+    from oracle.groundstate import ground_state
+    from oracle.response import HxcKernel
+    from oracle.system import WORKERS, System
+    from paper_2505_02319_amd import ResponseSystem, default_opts
+    from workloads import B_SEED, config, random_field
+    spec = config("cfg1")
+    sys_ = System(spec)
+    gs = ground_state(sys_)
+    kern = HxcKernel(sys_, gs.rho, xc=spec.xc)
+    b = random_field(spec, B_SEED)
+    tau = 1e-8 * float(np.linalg.norm(b))
+    t0 = time.perf_counter()
+    ref = inexact_gmres(sys_, gs, kern, b, tau, strategy=args.strategy, m=20,
+                        kerker_alpha=0.8 if args.kerker else None)
+    t_cpu = time.perf_counter() - t0
+    rs = ResponseSystem(spec, ground_state="compute")
+    bd = torch.from_numpy(b).cuda()
+    opts = default_opts(strategy=args.strategy, tol=1e-8, tol_is_relative=1,
+                        precision=args.precision, schur=args.schur, kerker=args.kerker)
+    rs.solve(bd, opts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, st = rs.solve(bd, opts)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    diff = float(np.linalg.norm(x.cpu().numpy() - ref.x) / np.linalg.norm(ref.x))
+    rs.close()
+    return {"workload": "cfg1: 2-atom cell 10.26^3 bohr, Ecut 8 Ha, FFT 20^3, Gamma, 5+2 bands",
+            "oracle_seconds": t_cpu, "oracle_cores": WORKERS, "oracle_n_ham": ref.n_ham,
+            "oracle_gmres_iters": ref.iterations, "gpu_seconds": t_gpu, "gpu_n_ham": st["n_ham"],
+            "gpu_gmres_iters": st["gmres_iters"], "rel_diff_gpu_vs_oracle": diff}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +306,8 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(spec, n_ham / args.steps, args.cpu_seconds)
+        log("whole solve on the small cell, oracle and GPU ...")
+        out["cpu_baseline"]["whole_solve_small_cell"] = whole_solve_small(args)
     print(json.dumps(out), flush=True)
 
 

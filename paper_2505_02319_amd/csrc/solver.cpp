@@ -696,7 +696,8 @@ template <typename R> struct CgRunner {
     if (nmem == 0 || max_iter <= 0) return out;
     const hipStream_t st = c.st;
     IKR_HIP(hipStreamSynchronize(st));
-    if (std::getenv("IKR_VERBOSE"))
+    const char* vb = std::getenv("IKR_VERBOSE");
+    if (vb && std::atoi(vb) >= 2)
       std::fprintf(stderr, "[ikr] CG run %s: %d iterations, %d bands; live counts read from "
                    "pinned memory %d times, copied %d times\n",
                    sizeof(R) == 8 ? "FP64" : "FP32", iters, nmem, lag_seen, lag_copied);
