@@ -347,9 +347,10 @@ ikr_status ikr_grad_amplitudes(ikr_handle h, const double* drho_dev,
 
 /* Kernel-path selection (process-wide; for tests and tuning).  Every path
  * computes the same quantities; by default (mask 0) each launch picks its
- * path by size.  Bit 0 forces the vector-FMA projection gram (otherwise the
- * per-tile matrix-core gram below 65 projection rows, the k-wide matrix-core
- * gram above), bit 1 the two-launch end of a CG iteration (otherwise one
+ * path by size.  Bit 0 forces the vector-FMA projections: the gram (otherwise
+ * the per-tile matrix-core gram below 65 projection rows, the k-wide
+ * matrix-core gram above) and the CG update (otherwise on the matrix cores,
+ * one 16-band tile per block), bit 1 the two-launch end of a CG iteration (otherwise one
  * block while the batch has few partials), bit 2 the k-wide matrix-core gram
  * (all bands of a k-point per block) at any row count, bit 3 the size rules
  * alone for every launch shape (no setup-time tuning, below).
@@ -360,19 +361,21 @@ int ikr_get_kernel_paths(void);
 /* Launch shapes picked by measurement.  At the first Sternheimer CG run of
  * each precision, a system times the candidates of three launch shapes of
  * the CG iteration with HIP events on its stream (one untimed and three timed
- * runs each) and keeps the fastest: the projection gram's kernel and block
+ * runs each, the caches flushed before each) and keeps the fastest: the projection gram's kernel and block
  * count, the CG update's band group, and the plane kernel's block size.  It
  * does so for the batch the run starts with, when that batch has more tiles
  * of 16 bands than k-points ("thick"), and for batches of at most 8 and at
- * most 2 bands per k-point ("thin": the late iterations, times added); each
- * iteration then takes the shapes of its class.  The size rule is one of the
- * candidates and is kept unless another is more than 3% faster.
+ * most 2 bands per k-point, with the run's own batch when that is thin too
+ * ("thin": the late iterations, times added); each iteration then takes the
+ * shapes of its class.  The size rule is one of the candidates and is kept
+ * unless another is more than 5% faster.
  * IKR_VERBOSE=1 in the environment logs every candidate's time to stderr.
  * ikr_get_tuning fills out[24]: for precision p (0 FP64, 1 FP32) and class c
  * (0 thick, 1 thin), the 6 entries from out[12 p + 6 c] are: measured (1) or
  * not yet (0); the gram kernel (0 size rule, 1 per-tile matrix-core, 2
  * k-wide matrix-core, 3 vector-FMA); the gram's block-count scale in percent
- * (50, 100, 200); the update's bands per block (0 size rule, 4, 8, 16); the
+ * (50, 100, 200); the CG update's bands per block (0: the size rule, the
+ * matrix-core update; 4, 8, 16: the vector update with that band group); the
  * plane kernel's threads per block (0 size rule, 256, 512); the picked
  * gram's time in ns (summed over the class's batches).  Errors: IKR_E_ARG for
  * a null handle or out. */

@@ -45,7 +45,13 @@ template <typename R> struct CgScalars {
   int* nactive;            // device counter of still-active slots
   int* noconv;             // device counter of slots that hit the cap
   int min_iter, max_iter;
+  // stagnation stop (0: off): a slot whose |r|^2 has not fallen below
+  // STAG_DROP times its best value for `stag` iterations stops unconverged
+  int stag = 0;
+  R* rbest = nullptr;      // best |r|^2 per slot
+  int* rlast = nullptr;    // iteration of the last such fall per slot
 };
+constexpr double STAG_DROP = 0.5;
 
 // Internal <-> external grid layout.
 struct Layout {
@@ -56,7 +62,7 @@ struct Layout {
 // Process-wide choice of kernel paths, for tests and tuning.  0: by size
 // (the default); each bit forces one path at any size.
 enum KernelPath : int {
-  PATH_VECTOR_GRAM = 1,   // projections by the vector-FMA gram kernel
+  PATH_VECTOR_GRAM = 1,   // projections (gram and CG update) by the vector-FMA kernels
   PATH_SPLIT_END = 2,     // CG iteration end as two launches (finish, compaction)
   PATH_KWIDE = 4,         // k-wide matrix-core gram at any row count
   PATH_FIXED = 8,         // no setup-time tuning: launch shapes by the size rules alone
@@ -66,7 +72,8 @@ enum KernelPath : int {
 struct KernelTune {
   int gram = 0;            // 0 by size; 1 per-tile matrix-core; 2 k-wide matrix-core; 3 vector
   float gram_scale = 1;    // multiplier of the gram's block-count target (0.5 .. 2)
-  int upd_bpt = 0;         // 0 by size; else bands per block of the tiled CG update (4, 8, 16)
+  int upd_bpt = 0;         // 0 by size (the matrix-core update); else the vector update with
+                           // this many bands per block (4, 8, 16)
   int plane_pt = 0;        // 0 by size; else threads per block of the plane kernel (256, 512)
 };
 

@@ -281,15 +281,15 @@ __global__ __launch_bounds__(NT) void gram_mfma_kernel(
 // A block takes one (k, super-chunk) item and the up to KT tiles of k
 // (t0[k] .. t0[k+1]); it stages chunks of KCH coefficients of all Mr rows of
 // W_k and of the k's bands in LDS, so W_k is read once per iteration
-// whatever the number of bands, and its 8 wavefronts deal the (row tile,
-// band tile) pairs of the output round-robin (pair = wave + 8 q).  Each pair
+// whatever the number of bands, and its wavefronts deal the (row tile,
+// band tile) pairs of the output round-robin (pair = wave + NWV q).  Each pair
 // is four real 16x16x4 MFMA products per 4 coefficients (Re += Wr Xr + Wi Xi,
 // Im += Wr Xi - Wi Xr).  The next chunk is fetched into registers while the
 // current one is used.
 constexpr int KW_NT = 512;
 
-template <typename R, int KT, int RTM, int KCH>
-__global__ __launch_bounds__(KW_NT) void gram_kw_kernel(
+template <typename R, int KT, int RTM, int KCH, int NTH>
+__global__ __launch_bounds__(NTH) void gram_kw_kernel(
     Tiles tl, KTileRange kr, const int* __restrict__ nb, const int* __restrict__ Mk, int Mmax,
     const cplx<R>* __restrict__ W, size_t wk_stride, int w_stride,
     const cplx<R>* __restrict__ X, int x_stride, int nsc, int sc_len,
@@ -297,7 +297,8 @@ __global__ __launch_bounds__(KW_NT) void gram_kw_kernel(
   using M = Mfma<R>;
   constexpr int LC = KCH + 1;
   constexpr int NBT = KT * 16;                       // band rows staged
-  constexpr int PW = (KT * RTM + 7) / 8;             // pairs per wavefront
+  constexpr int NWV = NTH / 64;                      // wavefronts
+  constexpr int PW = (KT * RTM + NWV - 1) / NWV;     // pairs per wavefront
   __shared__ cplx<R> Xs[NBT * LC];
   __shared__ cplx<R> Ws[RTM * 16 * LC];
   __shared__ int ss[NBT];
@@ -329,17 +330,17 @@ __global__ __launch_bounds__(KW_NT) void gram_kw_kernel(
   for (int q = 0; q < PW; ++q)
 #pragma unroll
     for (int v = 0; v < 4; ++v) cre[q][v] = cim[q][v] = R(0);
-  constexpr int XL = NBT * KCH / KW_NT, WLM = RTM * 16 * KCH / KW_NT;
-  // 16 KCH is a multiple of KW_NT, so whole band and row tiles fill the
+  constexpr int XL = NBT * KCH / NTH, WLM = RTM * 16 * KCH / NTH;
+  // 16 KCH is a multiple of NTH, so whole band and row tiles fill the
   // fetch registers exactly
-  static_assert(16 * KCH % KW_NT == 0, "k-wide gram staging");
-  const int xl = nt * 16 * KCH / KW_NT, wl = RT * 16 * KCH / KW_NT;
+  static_assert(16 * KCH % NTH == 0, "k-wide gram staging");
+  const int xl = nt * 16 * KCH / NTH, wl = RT * 16 * KCH / NTH;
   cplx<R> xr[XL], wr[WLM];
   auto fetch = [&](int g0) {
 #pragma unroll
     for (int u = 0; u < XL; ++u) {
       if (u < xl) {
-        const int i = tid + u * KW_NT, b = i / KCH, g = g0 + i % KCH;
+        const int i = tid + u * NTH, b = i / KCH, g = g0 + i % KCH;
         const int slot = b < NBT ? ss[b] : -1;
         xr[u] = (slot >= 0 && g < gend) ? X[(size_t)slot * x_stride + g] : mk<R>(0, 0);
       }
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(KW_NT) void gram_kw_kernel(
 #pragma unroll
     for (int u = 0; u < WLM; ++u) {
       if (u < wl) {
-        const int i = tid + u * KW_NT, m = i / KCH, g = g0 + i % KCH;
+        const int i = tid + u * NTH, m = i / KCH, g = g0 + i % KCH;
         wr[u] = (m < Mr && g < gend) ? Wk[(size_t)m * w_stride + g] : mk<R>(0, 0);
       }
     }
@@ -356,12 +357,12 @@ __global__ __launch_bounds__(KW_NT) void gram_kw_kernel(
   for (int g0 = gbeg; g0 < gend; g0 += KCH) {
 #pragma unroll
     for (int u = 0; u < XL; ++u) {
-      const int i = tid + u * KW_NT;
+      const int i = tid + u * NTH;
       if (i < nt * 16 * KCH) Xs[(i / KCH) * LC + i % KCH] = xr[u];
     }
 #pragma unroll
     for (int u = 0; u < WLM; ++u) {
-      const int i = tid + u * KW_NT;
+      const int i = tid + u * NTH;
       if (i < RT * 16 * KCH) Ws[(i / KCH) * LC + i % KCH] = wr[u];
     }
     __syncthreads();
@@ -371,7 +372,7 @@ __global__ __launch_bounds__(KW_NT) void gram_kw_kernel(
       const int e = 4 * ks + (lane >> 4);
 #pragma unroll
       for (int q = 0; q < PW; ++q) {
-        const int pr = wave + 8 * q;
+        const int pr = wave + NWV * q;
         if (pr < npair) {
           const int rt = pr / nt, bt = pr - rt * nt;
           const cplx<R> wa = Ws[(16 * rt + (lane & 15)) * LC + e];
@@ -388,7 +389,7 @@ __global__ __launch_bounds__(KW_NT) void gram_kw_kernel(
   const int j = lane & 15;
 #pragma unroll
   for (int q = 0; q < PW; ++q) {
-    const int pr = wave + 8 * q;
+    const int pr = wave + NWV * q;
     if (pr >= npair) continue;
     const int rt = pr / nt, bt = pr - rt * nt, t = t0 + bt;
     if (j >= tl.nb[t]) continue;
@@ -840,6 +841,8 @@ static int nsc_for(int nb_max, int ntiles, int target, int& sc_len) {
 // the nk k-points (four rounds of one block per CU), each at least one chunk.
 constexpr int KW_BLOCKS = 1024;
 template <typename R> constexpr int kw_chunk() { return sizeof(R) == 8 ? 32 : 64; }
+constexpr int KW_NT_THIN = 256;
+template <typename R> constexpr int kw_chunk_thin() { return sizeof(R) == 8 ? 16 : 32; }
 static int kw_nsc(int nb_max, int nk, int kch, int& sc_len, double scale = 1.0) {
   const int nch = (nb_max + kch - 1) / kch;
   int nsc = std::max(1, std::min(nch, (int)(scale * KW_BLOCKS) / std::max(nk, 1)));
@@ -863,6 +866,10 @@ size_t gram_part_elems(int ntiles, int nb_max, int Mmax, int nk, double max_scal
     const int nsc = std::max(kw_nsc(nb_max, nk, kw_chunk<double>(), sc_len, sc),
                              kw_nsc(nb_max, nk, kw_chunk<float>(), sc_len, sc));
     most = std::max(most, (size_t)ntiles * nsc);
+    // the one-tile-per-k instance: at most nk tiles
+    const int nsc1 = std::max(kw_nsc(nb_max, nk, kw_chunk_thin<double>(), sc_len, 2 * sc),
+                              kw_nsc(nb_max, nk, kw_chunk_thin<float>(), sc_len, 2 * sc));
+    most = std::max(most, (size_t)std::min(ntiles, nk) * nsc1);
   }
   return most * Mmax * BT;
 }
@@ -893,13 +900,31 @@ int gram_partials(const Tiles& tl, const int* nb, int nb_max, const int* Mk, int
   const int variant = gram_variant(Mmax, kr, kt);
   const double scale = kt ? std::min(2.0, std::max(0.5, (double)kt->gram_scale)) : 1.0;
   if (variant == 2) {
-    constexpr int kch = kw_chunk<R>();
     int sc_len;
+    if (kr.ktmax <= 1) {
+      // at most one band tile per k-point (the late iterations of a CG run):
+      // a 4-wavefront block with one band tile and half the chunk, three
+      // blocks per CU, twice the blocks
+      constexpr int kch = kw_chunk_thin<R>();
+      const int nsc = kw_nsc(nb_max, kr.nk, kch, sc_len, 2 * scale);
+      const dim3 grid(round8(nsc * kr.nk));
+#define IKR_GRAMKW1(RTM)                                                                         \
+  hipLaunchKernelGGL((gram_kw_kernel<R, 1, RTM, kch, KW_NT_THIN>), grid, dim3(KW_NT_THIN), 0, st, \
+                     tl, kr, nb, Mk, Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part,  \
+                     active)
+      if (Mmax <= 96) IKR_GRAMKW1(6);
+      else IKR_GRAMKW1(11);
+#undef IKR_GRAMKW1
+      IKR_HIP(hipGetLastError());
+      return nsc;
+    }
+    constexpr int kch = kw_chunk<R>();
     const int nsc = kw_nsc(nb_max, kr.nk, kch, sc_len, scale);
     const dim3 grid(round8(nsc * kr.nk));
 #define IKR_GRAMKW(KT, RTM)                                                                   \
-  hipLaunchKernelGGL((gram_kw_kernel<R, KT, RTM, kch>), grid, dim3(KW_NT), 0, st, tl, kr, nb,   \
-                     Mk, Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part, active)
+  hipLaunchKernelGGL((gram_kw_kernel<R, KT, RTM, kch, KW_NT>), grid, dim3(KW_NT), 0, st, tl,  \
+                     kr, nb, Mk, Mmax, W, wk_stride, w_stride, X, x_stride, nsc, sc_len, part, \
+                     active)
     if (Mmax <= 96) IKR_GRAMKW(6, 6);
     else IKR_GRAMKW(5, 11);
 #undef IKR_GRAMKW

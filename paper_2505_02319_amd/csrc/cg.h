@@ -38,8 +38,10 @@ void cg_combine(const Slots& sl, int Na, const int* Mq, int Mq_max, const cplx<R
 
 // Ap = w~ + sum_r W[r] gam[r] (in place in Wv), p = p~ - sum_m phi_m a_m (in
 // place in P), partial <p, Ap> -> dpart[slot * nparts + gb] with nparts =
-// cg_update_parts(...).  With kr given, above 64 rows (or forced) all bands of
-// a k-point are updated per block on the matrix cores.
+// cg_update_parts(...).  By default one 16-band tile per block on the matrix
+// cores; the vector-FMA kernel when the vector paths are forced or kt asks
+// for a band group; with kr given and the k-wide path forced, all bands of a
+// k-point per block on the matrix cores.
 template <typename R>
 void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, size_t wk,
                int Na, const int* Mq, int Mq_max, const cplx<R>* gam, int cstride,
@@ -73,6 +75,9 @@ void cg_axpy(const Slots& sl, const int* nb, int nb_max, R a, const cplx<R>* x, 
 // cnt[1] = tiles; with hist set, hist[2 * it ..] the same, it = step[0]
 // (a device counter, then incremented; entries past hist_len pairs are
 // dropped).
+constexpr int CNT = 3;          // counts the compaction writes
+constexpr int CNT_STRIDE = 4;   // their stride in the host-mapped double buffer
+
 struct CgCompact {
   int nk;
   const int* slot0_k;
@@ -83,12 +88,13 @@ struct CgCompact {
   int* ctk;
   int* cto;
   int* ctn;
-  int* cnt;
+  int* cnt;            // [CNT]: live slots, live tiles, most live tiles of one k-point
   int* hist;
   int hist_len;
   int* step;
-  int* hcnt = nullptr;   // host-mapped [2][2]: with hist, step s also writes (slots, tiles) to
-                         // hcnt[2 (s & 1)], for the host loop to read without a copy
+  int* hcnt = nullptr;   // host-mapped [2][CNT_STRIDE]: with hist, step s also writes the
+                         // counts to hcnt[CNT_STRIDE (s & 1)], for the host loop to read
+                         // without a copy
   int* ktb = nullptr;    // [nk + 1]: first compact tile of each k (nullable)
 };
 

@@ -247,6 +247,137 @@ __global__ __launch_bounds__(NT) void cg_update_kernel(
   }
 }
 
+// The tiled update on the matrix cores: a block takes NT coefficients g of
+// one 16-band tile, its wavefronts take 16 of them at a time, and each step
+// of 4 rows of W_k is a 16x16x4 product (A = the tile's coefficients
+// [band][row] from LDS, B = W [row][g] straight from its loads, 16 running g
+// per row: 256-byte runs; D = [band][g], so a lane's results lie along g).
+// Rows go in three groups: projectors (Ap only), phi rows (Ap and p) and
+// H phi rows (Ap only), U steps of loads in flight.  Complex products are
+// four real ones (Re += Gr Wr - Gi Wi, Im += Gr Wi + Gi Wr).  W_k is read
+// once per tile whatever the number of bands, where the vector kernel reads
+// it once per band group.  The <p, Ap> partials of the block's NT
+// coefficients: per band over the 16 lanes of a g run, then over the
+// wavefronts in order.  LDS: coefficients [Mr][16], -a [Mq_max][16].
+template <typename R, int U>
+__global__ __launch_bounds__(NT) void cg_update_mfma_kernel(
+    Tiles tl, const int* __restrict__ nb, int nb_max, const cplx<R>* __restrict__ Wcg,
+    size_t wk, int Na, const int* __restrict__ Mq, int Mq_max,
+    const cplx<R>* __restrict__ gam, int cstride, cplx<R>* __restrict__ Wv,
+    cplx<R>* __restrict__ P, R* __restrict__ dpart, int nparts) {
+  using MF = Mfma<R>;
+  extern __shared__ __align__(16) unsigned char cgm_smem[];
+  const int Mr = Na + 2 * Mq_max;
+  cplx<R>* cgl = reinterpret_cast<cplx<R>*>(cgm_smem);   // [Mr][16]
+  cplx<R>* cal = cgl + 16 * Mr;                            // [Mq_max][16]
+  __shared__ R red[NW * 16];
+  __shared__ int ss[16];
+  const int item = xcd_item(blockIdx.x, gridDim.x);
+  if (item >= nparts * tl.n) return;
+  const int tid = threadIdx.x;
+  const int t = item % tl.n, gb = item / tl.n;
+  if (tl.dn && t >= *tl.dn) return;
+  const int k = tl.k[t], nbt = tl.nb[t], n = nb[k];
+  const int M = min(Mq[k], Mq_max);
+  if (tid < 16) ss[tid] = tid < nbt ? tslot(tl, t, tid) : 0;
+  __syncthreads();
+  for (int i = tid; i < 16 * Mr; i += NT) {
+    const int r = i / 16, b = i % 16;
+    cgl[i] = (b < nbt && r < Na + 2 * M) ? gam[(size_t)ss[b] * cstride + r] : mk<R>(0, 0);
+  }
+  for (int i = tid; i < 16 * Mq_max; i += NT) {   // -a_m, held by gam
+    const int m = i / 16, b = i % 16;
+    cal[i] = (b < nbt && m < M) ? gam[(size_t)ss[b] * cstride + Na + 2 * m + 1] : mk<R>(0, 0);
+  }
+  __syncthreads();
+  const int wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const cplx<R>* Wk = Wcg + (size_t)k * wk;
+  R dsum[4] = {0, 0, 0, 0};
+  for (int c = wave; c < NT / 16; c += NW) {
+    const int g0 = gb * NT + 16 * c;
+    if (g0 >= n) break;
+    const int g = g0 + li;
+    const bool gin = g < n;
+    typename MF::acc are, aim, pre, pim;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) are[v] = aim[v] = pre[v] = pim[v] = R(0);
+    // Ap += G W over rows [r0, r0 + 4 nst) of stride rs (coefficient row of
+    // step s: r0 + rs (4 s + lk)); with PHI, p += (-a) W as well
+    auto group = [&](int r0, int rs, int nrows, int nst, bool phi) {
+      for (int s0 = 0; s0 < nst; s0 += U) {
+        cplx<R> w[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int q = 4 * (s0 + u) + lk;
+          w[u] = (s0 + u < nst && q < nrows && gin) ? Wk[(size_t)(r0 + rs * q) * nb_max + g]
+                                                    : mk<R>(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (s0 + u >= nst) break;
+          const int q = min(4 * (s0 + u) + lk, nrows - 1);
+          const cplx<R> a = cgl[(r0 + rs * q) * 16 + li];
+          are = MF::mac(a.x, w[u].x, are);
+          are = MF::mac(-a.y, w[u].y, are);
+          aim = MF::mac(a.x, w[u].y, aim);
+          aim = MF::mac(a.y, w[u].x, aim);
+          if (phi) {
+            const cplx<R> b = cal[q * 16 + li];
+            pre = MF::mac(b.x, w[u].x, pre);
+            pre = MF::mac(-b.y, w[u].y, pre);
+            pim = MF::mac(b.x, w[u].y, pim);
+            pim = MF::mac(b.y, w[u].x, pim);
+          }
+        }
+      }
+    };
+    if (Na > 0) group(0, 1, Na, (Na + 3) / 4, false);
+    if (M > 0) {
+      group(Na, 2, M, (M + 3) / 4, true);
+      group(Na + 1, 2, M, (M + 3) / 4, false);
+    }
+    // Ap = w~ + D, p = p~ + Dp for the lane's four (band, g); loads first
+    cplx<R> wv[4], pv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = MF::row(lane, v);
+      wv[v] = pv[v] = mk<R>(0, 0);
+      if (b < nbt && gin) {
+        const size_t o = (size_t)ss[b] * nb_max + g;
+        wv[v] = Wv[o];
+        pv[v] = P[o];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int b = MF::row(lane, v);
+      if (b < nbt && gin) {
+        const size_t o = (size_t)ss[b] * nb_max + g;
+        const cplx<R> ap = mk<R>(wv[v].x + are[v], wv[v].y + aim[v]);
+        const cplx<R> pn = mk<R>(pv[v].x + pre[v], pv[v].y + pim[v]);
+        Wv[o] = ap;
+        P[o] = pn;
+        dsum[v] += pn.x * ap.x + pn.y * ap.y;
+      }
+    }
+  }
+  // per band: over the 16 lanes of a g run (fixed tree), then the wavefronts in order
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    R d = dsum[v];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) d += __shfl_xor(d, o, 16);
+    if (li == 0) red[wave * 16 + MF::row(lane, v)] = d;
+  }
+  __syncthreads();
+  if (tid < nbt) {
+    R v = red[tid];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[w * 16 + tid];
+    dpart[(size_t)ss[tid] * nparts + gb] = v;
+  }
+}
+
 // The same update for all bands of a k-point at once, on the matrix cores:
 //   Ap[b][g] = w~[b][g] + sum_r gam[b][r] W[r][g]          (all Mr rows)
 //   p[b][g]  = p~[b][g] + sum_m gam[b][Na + 2m + 1] W[Na + 2m][g]   (phi rows)
@@ -542,17 +673,20 @@ __device__ void compact_block(const CgCompact& cp, const int* active, int* sh) {
   }
   __syncthreads();
   if (tid == 0) {
-    int a = 0, t = 0;
+    int a = 0, t = 0, tmax = 0;
     for (int k = 0; k < nk; ++k) {
       lb[k] = a;
       tb[k] = t;
       a += na[k];
-      t += (na[k] + BT - 1) / BT;
+      const int tk = (na[k] + BT - 1) / BT;
+      t += tk;
+      tmax = max(tmax, tk);
     }
     tb[nk] = t;
     if (cp.ktb) cp.ktb[nk] = t;
     cp.cnt[0] = a;
     cp.cnt[1] = t;
+    cp.cnt[2] = tmax;
     if (cp.hist) {
       const int it = cp.step[0];
       cp.step[0] = it + 1;
@@ -561,8 +695,9 @@ __device__ void compact_block(const CgCompact& cp, const int* active, int* sh) {
         cp.hist[2 * it + 1] = t;
       }
       if (cp.hcnt) {
-        cp.hcnt[2 * (it & 1)] = a;
-        cp.hcnt[2 * (it & 1) + 1] = t;
+        cp.hcnt[CNT_STRIDE * (it & 1)] = a;
+        cp.hcnt[CNT_STRIDE * (it & 1) + 1] = t;
+        cp.hcnt[CNT_STRIDE * (it & 1) + 2] = tmax;
       }
     }
   }
@@ -585,6 +720,10 @@ __device__ __forceinline__ void finish_slot(int slot, R rr, R rz, const CgScalar
   if (start) {
     cs.rz[slot] = rz;
     cs.beta[slot] = 0;
+    if (cs.stag) {
+      cs.rbest[slot] = rr;
+      cs.rlast[slot] = 0;
+    }
     return;
   }
   const int it = ++cs.iters[slot];
@@ -599,6 +738,16 @@ __device__ __forceinline__ void finish_slot(int slot, R rr, R rz, const CgScalar
     active[slot] = 0;
     if (!conv) atomicAdd(cs.noconv, 1);
     return;
+  }
+  if (cs.stag) {   // stagnation at the precision's floor: stop, unconverged
+    if (rr < R(STAG_DROP) * cs.rbest[slot]) {
+      cs.rbest[slot] = rr;
+      cs.rlast[slot] = it;
+    } else if (it - cs.rlast[slot] >= cs.stag) {
+      active[slot] = 0;
+      atomicAdd(cs.noconv, 1);
+      return;
+    }
   }
   const R beta = cs.rz[slot] != R(0) ? rz / cs.rz[slot] : R(0);
   if (!(beta == beta && beta - beta == R(0))) {   // overflow: a breakdown
@@ -742,6 +891,15 @@ void cg_update(const Tiles& tl, const int* nb, int nb_max, const cplx<R>* Wcg, s
   }
   const int ngb = update_nblocks(nb_max);
   const int blocks = ngb * tl.n;
+  // the matrix cores unless the vector paths are forced or a band group is asked for
+  const size_t lds_mf = (size_t)16 * (Na + 3 * Mq_max) * sizeof(cplx<R>);
+  if (!(kernel_paths() & PATH_VECTOR_GRAM) && !(kt && kt->upd_bpt) && lds_mf <= 65536) {
+    hipLaunchKernelGGL((cg_update_mfma_kernel<R, 8>), dim3(round8(ngb * tl.n)), dim3(NT), lds_mf,
+                       st, tl, nb, nb_max, Wcg, wk, Na, Mq, Mq_max, gam, cstride, Wv, P, dpart,
+                       ngb);
+    IKR_HIP(hipGetLastError());
+    return;
+  }
   // FP64 caps the band group at 8 (16 would leave one wavefront per SIMD)
   int bpt = blocks >= 1024 ? 16 : (2 * blocks >= 1024 ? 8 : 4);
   if (sizeof(R) == 8 && bpt > 8) bpt = 8;

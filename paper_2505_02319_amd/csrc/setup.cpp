@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <memory>
 
+#include "cg.h"
 #include "system.h"
 
 namespace ikr {
@@ -303,6 +304,7 @@ void ensure_fp32(System& s) {
   w.T1.alloc(tbuf); w.T2.alloc(tbuf);
   w.coefA.alloc(d.coefA.n); w.coefB.alloc(d.coefB.n); w.part.alloc(d.part.n);
   w.rz.alloc(s.J); w.alpha.alloc(s.J); w.beta.alloc(s.J); w.rnorm2.alloc(s.J);
+  w.rbest.alloc(s.J);
   w.dpart.alloc(d.dpart.n);
   w.pshift.alloc(s.J); w.shift.alloc(s.J);
   convert_array(s.J, d.pshift.get(), w.pshift.get(), st);
@@ -458,6 +460,7 @@ void finish_setup(System& s) {
   w.rpart.alloc((size_t)s.J * vec_nblocks(s.nb_max));
   w.zpart.alloc((size_t)s.J * vec_nblocks(s.nb_max));
   w.rz.alloc(s.J); w.alpha.alloc(s.J); w.beta.alloc(s.J); w.rnorm2.alloc(s.J);
+  w.rbest.alloc(s.J);
   w.dpart.alloc((size_t)s.J * std::max({update_nblocks(s.nb_max), vec_nblocks(s.nb_max),
                                          (s.nb_max + 63) / 64}));
   w.pshift.alloc(s.J); w.shift.alloc(s.J);
@@ -467,6 +470,7 @@ void finish_setup(System& s) {
   s.d_cto.alloc(s.tiles.n);
   s.d_ctn.alloc(s.tiles.n);
   s.d_iters.alloc(s.J);
+  s.d_rlast.alloc(s.J);
   s.d_counters.alloc(8);
   s.d_slot0_k.upload(s.slot0_k, st);
   {
@@ -475,9 +479,9 @@ void finish_setup(System& s) {
     s.d_mcg_occ.upload(mo, st);
     s.d_mcg_all.upload(ma, st);
   }
-  s.d_cnt.alloc(2);
-  s.h_cnt.alloc(4, hipHostMallocCoherent);
-  for (int i = 0; i < 4; ++i) s.h_cnt.p[i] = -1;
+  s.d_cnt.alloc(CNT);
+  s.h_cnt.alloc(2 * CNT_STRIDE, hipHostMallocCoherent);
+  for (int i = 0; i < 2 * CNT_STRIDE; ++i) s.h_cnt.p[i] = -1;
   IKR_HIP(hipHostGetDevicePointer((void**)&s.d_hcnt, s.h_cnt.p, 0));
   s.d_tol2.alloc(s.J);
   s.d_wa.alloc(s.J);

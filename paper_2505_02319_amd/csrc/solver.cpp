@@ -22,6 +22,8 @@ constexpr double TOL_FLOOR = 1e-13;   // CG tolerances never below this times ||
 constexpr double CHECK_REL = 1e-3;    // FP32 results with tau_j below this times ||b_j||
                                       // get an FP64 true-residual check
 constexpr double WARM_REL = 0.1;      // warm start when it leaves under this of ||b_j||
+constexpr int FP32_STAG_ITERS = 30;   // an FP32 band whose |r|^2 has not halved in this many
+                                      // iterations stops (and is solved again in FP64)
 
 // Least squares over the stored right-hand sides of one band: c minimising
 // ||b - sum_l c_l b_l|| from the Gram matrix G (row-major, leading size ld,
@@ -269,16 +271,19 @@ template <> const float2* wcg_of<float>(const System& s) { return s.w32.wcg.get(
 // by size: the projection gram's kernel (per-tile or k-wide matrix-core, or
 // vector) and its block count, the tiled update's band group, and the
 // threads of the plane kernel.  At the first CG run of a precision, each
-// candidate runs once untimed and five times between HIP events on the CG
-// stream, on the batch the run starts with (when it has more tiles than
-// k-points: the "thick" class) and on two thin batches of at most 8 and 2
-// bands per k-point (the late iterations; their times are added).  The size
-// rule is a candidate too and stays unless another is more than 3% faster
-// (the size rules also adapt to the shrinking batch, a fixed pick does not).
+// candidate runs once untimed and three times between HIP events on the CG
+// stream, each time after a write of 512 MB that flushes the caches (as the
+// other kernels of an iteration do), on the batch the run starts with (when
+// it has more tiles than k-points: the "thick" class) and on thin batches of
+// at most 8 and 2 bands per k-point, with the run's own batch when that is
+// thin too (the "thin" class; its times are added).  The size rule is a
+// candidate too and stays unless another is more than 5% faster (the size
+// rules also adapt to the shrinking batch, a fixed pick does not).
 // All candidates compute the same quantities.  The runs write only scratch:
 // gram partials and coefficients, the plane buffer, and the direction rows
 // p, Ap of the batch's slots, which the CG run overwrites before reading.
-constexpr double TUNE_MARGIN = 0.97;
+constexpr double TUNE_MARGIN = 0.95;
+constexpr int TUNE_REPS = 3;
 
 template <typename R>
 static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<int>>& sets,
@@ -291,15 +296,16 @@ static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<in
   const cplx<R>* wcg = wcg_of<R>(s);
   const KTileRange kr = s.krange_compact();
   int* cnt = s.d_cnt.get();
-  struct Batch { Slots sl; Tiles tl; };
+  struct Batch { Slots sl; Tiles tl; int ktmax; };
   // compacts one set into the device lists (each timing starts with this)
   auto select = [&](const std::vector<int>& set) {
-    int na = 0, nt = 0;
+    int na = 0, nt = 0, kt = 0;
     for (int v : set) na += v != 0;
     for (int k = 0; k < s.nk; ++k) {
       int c = 0;
       for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) c += set[j] != 0;
       nt += (c + BT - 1) / BT;
+      kt = std::max(kt, (c + BT - 1) / BT);
     }
     IKR_HIP(hipMemcpyAsync(s.d_active.get(), set.data(), J * sizeof(int),
                            hipMemcpyHostToDevice, st));
@@ -310,7 +316,8 @@ static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<in
     IKR_HIP(hipStreamSynchronize(st));   // the host vector may go
     return Batch{Slots{na, s.d_slot_k.get(), s.d_active.get(), s.d_list.get(), cnt},
                  Tiles{nt, s.d_ctk.get(), s.d_cto.get(), s.d_ctn.get(), s.d_list.get(),
-                       cnt + 1}};
+                       cnt + 1},
+                 kt};
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;
   IKR_HIP(hipEventCreate(&e0));
@@ -324,19 +331,29 @@ static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<in
   // summed time (us per launch) of launch(batch) over the sets: one untimed
   // launch, then 1 to 5 timed ones (about 1 ms of launches, at least one);
   // a candidate already 30% behind the best after a set is not run further
+  // the caches (L2 and the 256 MB last-level cache) are flushed before every
+  // timed launch by writing a buffer larger than both, as the other kernels of
+  // a CG iteration do between two grams: back to back, a launch would find
+  // its operands cached
+  DBuf<unsigned char> flush;
+  constexpr size_t FLUSH_BYTES = (size_t)512 << 20;
+  flush.alloc(FLUSH_BYTES);
+  unsigned char fv = 0;
+  auto one = [&](auto&& launch, const Batch& bt) {
+    IKR_HIP(hipMemsetAsync(flush.get(), ++fv, FLUSH_BYTES, st));
+    IKR_HIP(hipEventRecord(e0, st));
+    launch(bt);
+    IKR_HIP(hipEventRecord(e1, st));
+    return elapsed_us();
+  };
   auto time_us = [&](auto&& launch, double best) {
     double tot = 0;
     for (const auto& set : sets) {
       const Batch bt = select(set);
-      IKR_HIP(hipEventRecord(e0, st));
-      launch(bt);
-      IKR_HIP(hipEventRecord(e1, st));
-      const double t1 = elapsed_us();
-      const int reps = std::max(1, std::min(5, (int)(1000.0 / std::max(t1, 1.0))));
-      IKR_HIP(hipEventRecord(e0, st));
-      for (int r = 0; r < reps; ++r) launch(bt);
-      IKR_HIP(hipEventRecord(e1, st));
-      tot += elapsed_us() / reps;
+      (void)one(launch, bt);   // untimed: first use
+      double t = 0;
+      for (int r = 0; r < TUNE_REPS; ++r) t += one(launch, bt);
+      tot += t / TUNE_REPS;
       if (best > 0 && tot > 1.3 * best) return 1e300;
     }
     return tot;
@@ -361,8 +378,9 @@ static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<in
         if (v == 0 && sc != 1.0f) continue;
         if (v > 0 && (gram_variant(Mrows, kr, &c) != v || (v == vdef && sc == 1.0f))) continue;
         const double t = time_us([&](const Batch& bt) {
+          const KTileRange krg{s.nk, s.d_ktb.get(), bt.ktmax};
           const int nsc = gram_partials<R>(bt.tl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm,
-                                           w.p.get(), nbm, w.part.get(), st, nullptr, kr, &c);
+                                           w.p.get(), nbm, w.part.get(), st, nullptr, krg, &c);
           gram_reduce<R>(bt.tl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
         }, tg);
         std::snprintf(buf, sizeof buf, t < 1e300 ? " %c%.1f:%.1f" : " %c%.1f:-", "SPKV"[v], sc, t);
@@ -448,7 +466,11 @@ static void tune_launches(System& s, CgWork<R>& w, const std::vector<int>& membe
     changed = true;
   }
   if (!s.tuned[pi][1]) {
-    tune_class<R>(s, w, {thin8, thin2}, 1, dMq, Mq_max, dMcg, st);
+    // with the run's own batch when that is thin too (its first iterations)
+    if (batch_class_of(nt, s.nk) == 1)
+      tune_class<R>(s, w, {member, thin8, thin2}, 1, dMq, Mq_max, dMcg, st);
+    else
+      tune_class<R>(s, w, {thin8, thin2}, 1, dMq, Mq_max, dMcg, st);
     changed = true;
   }
   if (changed) s.graphs.clear();   // graphs captured before hold the size-rule shapes
@@ -500,6 +522,7 @@ template <typename R> struct CgRunner {
   int min_iter, max_iter, nkl;
   bool use_graph, timing;
   int J, nbm, nbn, Na, Mrows, nvb, nup, nmem = 0, nact = 0, nct = 0, nt0 = 0;
+  int nkt = 0;   // bound on the live tiles of any one k-point (one iteration old)
   int it = 0, iters = 0, lag_seen = 0, lag_copied = 0;
   bool done = false;
   size_t wk;
@@ -557,6 +580,11 @@ template <typename R> struct CgRunner {
     }
     cs = CgScalars<R>{w.rz.get(), w.alpha.get(), w.beta.get(), w.rnorm2.get(), c.tol2,
                       c.iters, c.counters, c.counters + 1, min_iter, max_iter};
+    if (sizeof(R) == 4) {   // FP32 bands stop when they stall at the FP32 floor
+      cs.stag = FP32_STAG_ITERS;
+      cs.rbest = w.rbest.get();
+      cs.rlast = s.d_rlast.get();
+    }
     nvb = vec_nblocks(nbm);
     nup = cg_update_parts(nbm, Mrows, kr());
     cp = CgCompact{s.nk, s.d_slot0_k.get(), s.d_nocc_k.get(), s.d_slot_k.get(), J,
@@ -567,6 +595,7 @@ template <typename R> struct CgRunner {
       int n = 0;
       for (int j = s.slot0_k[k]; j < s.slot0_k[k] + s.nocc_k[k]; ++j) n += member[j] != 0;
       nct += (n + BT - 1) / BT;
+      nkt = std::max(nkt, (n + BT - 1) / BT);
     }
     nt0 = nct;
     nact = nmem;
@@ -590,7 +619,7 @@ template <typename R> struct CgRunner {
     IKR_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     IKR_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
       // no compaction is in flight here (every run ends with a stream sync)
-    for (int i = 0; i < 4; ++i) c.h_cnt->p[i] = -1;
+    for (int i = 0; i < 2 * CNT_STRIDE; ++i) c.h_cnt->p[i] = -1;
   }
 
   // one CG iteration over grids of na rows and nt tiles
@@ -620,8 +649,10 @@ template <typename R> struct CgRunner {
     KTimer::end(kid<R>(K_COL_FWD), st, 0.0);
     // q, a, h = W_k^H p~ ; update coefficients ; Ap and p = Q p~ ; <p, Ap>
     KTimer::begin(kid<R>(K_GRAM), st);
+    // the gram's kernel may follow the live tiles per k-point (graphs keep the bound of the set-up)
+    const KTileRange krg{s.nk, c.ktb, use_graph ? s.ktmax : std::min(nkt, s.ktmax)};
     const int nsc = gram_partials<R>(ctl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm,
-                                     w.p.get(), nbm, c.part, st, nullptr, kr(), kt);
+                                     w.p.get(), nbm, c.part, st, nullptr, krg, kt);
     KTimer::end(kid<R>(K_GRAM), st, 0.0);
     gram_reduce<R>(ctl, dMcg, Mrows, nsc, c.part, w.craw.get(), s.mcg, st);
     cg_combine<R>(sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(), w.gT.get(),
@@ -662,20 +693,21 @@ template <typename R> struct CgRunner {
     }
     iters = it + 1;
     if (s.cg_plain) {   // reference loop: the host waits for every iteration's count
-      IKR_HIP(hipMemcpyAsync(c.h_cnt->p, c.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      IKR_HIP(hipMemcpyAsync(c.h_cnt->p, c.cnt, CNT * sizeof(int), hipMemcpyDeviceToHost, st));
       IKR_HIP(hipStreamSynchronize(st));
       nact = c.h_cnt->p[0];
       nct = c.h_cnt->p[1];
-      c.h_cnt->p[0] = c.h_cnt->p[1] = -1;
+      nkt = c.h_cnt->p[2];
+      for (int i = 0; i < CNT; ++i) c.h_cnt->p[i] = -1;
     } else {
-      // the compaction of iteration it writes its counts to h_cnt[2 (it & 1)]
+      // the compaction of iteration it writes its counts to h_cnt[CNT_STRIDE (it & 1)]
       IKR_HIP(hipEventRecord(ev[it & 1], st));
       if (it >= 1) {
         IKR_HIP(hipEventSynchronize(ev[(it - 1) & 1]));
-        volatile int* hc = c.h_cnt->p + 2 * ((it - 1) & 1);
-        if (hc[0] < 0 || hc[1] < 0) {
+        volatile int* hc = c.h_cnt->p + CNT_STRIDE * ((it - 1) & 1);
+        if (hc[0] < 0 || hc[1] < 0 || hc[2] < 0) {
           // not seen yet: the device counts are as fresh or fresher, so also a bound
-          IKR_HIP(hipMemcpyAsync((void*)hc, c.cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+          IKR_HIP(hipMemcpyAsync((void*)hc, c.cnt, CNT * sizeof(int), hipMemcpyDeviceToHost, st));
           IKR_HIP(hipStreamSynchronize(st));
           ++lag_copied;
         } else {
@@ -683,7 +715,8 @@ template <typename R> struct CgRunner {
         }
         nact = hc[0];
         nct = hc[1];
-        hc[0] = hc[1] = -1;   // consumed: iteration it + 1 writes this slot next
+        nkt = hc[2];
+        for (int i = 0; i < CNT; ++i) hc[i] = -1;   // consumed: iteration it + 1 writes here next
       }
     }
     ++it;
@@ -1034,10 +1067,10 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     res.n_ham32 = o32.n_ham;
     // FP64 check of the FP32 results: the true residual b - A x of every
     // FP32 band whose tolerance is below CHECK_REL ||b_j||, and of every band
-    // the FP32 CG did not bring below its tolerance (one FP64 H application
-    // each).  A band that fails continues in FP64 from its FP32 iterate
-    // (defect correction); one that did not converge restarts from zero, as
-    // its iterate may not be finite.
+    // the FP32 CG did not bring below its tolerance (stalled at the FP32
+    // floor, or at the cap; one FP64 H application each).  A band that fails
+    // continues in FP64 from its FP32 iterate (defect correction); one that
+    // did not converge restarts from zero, as its iterate may be far off.
     if (any_warm)   // the check below forms b - A x from r = b
       IKR_HIP(hipMemcpyAsync(w.r.get(), s.d_rec_tb.get(), (size_t)J * nbm * sizeof(double2),
                              hipMemcpyDeviceToDevice, st));

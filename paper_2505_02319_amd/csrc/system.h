@@ -51,7 +51,7 @@ struct KPoint {
 // Per-precision Sternheimer CG work space.
 template <typename R> struct CgWork {
   DBuf<cplx<R>> x, r, p, w, T1, T2, coefA, coefB, part;
-  DBuf<R> rz, alpha, beta, rnorm2, dpart, pshift, shift;
+  DBuf<R> rz, alpha, beta, rnorm2, dpart, pshift, shift, rbest;
   DBuf<cplx<R>> phi, proj;     // copies of Phi / projectors in this precision
   DBuf<R> vloc;
   // fused CG projections: W_k = [projectors | phi_1, H phi_1, phi_2, ...]
@@ -187,13 +187,13 @@ struct System {
   CgWork<float> w32;
   DBuf<double> d_u, d_drho, d_tmpg, d_kpart, d_rhopart, d_wa, d_wb, d_multi;
   DBuf<double2> d_kw1, d_kw2;
-  DBuf<int> d_active, d_iters, d_counters;
+  DBuf<int> d_active, d_iters, d_counters, d_rlast;
   DBuf<int> d_list, d_ctk, d_cto, d_ctn;   // compact active slots and their tiles
   DBuf<int> d_slot0_k;             // first slot of each k
   int mcg = 0;                     // rows of W_k: natoms + 2 nbands
   DBuf<int> d_mcg_occ, d_mcg_all;  // rows used per k: natoms + 2 nocc_k / + 2 nbands
   DBuf<int> d_cnt, d_hist;         // live counts of the compaction, per-iteration history
-  HBuf<int> h_cnt;                 // [2][2] lagged copies of d_cnt (coherent pinned memory)
+  HBuf<int> h_cnt;                 // [2][CNT_STRIDE] lagged copies of d_cnt (coherent pinned memory)
   int* d_hcnt = nullptr;           // h_cnt as a device address: the compaction writes it
   std::vector<double> dvloc;       // [natoms][ng] dV_loc/dA_a, internal layout (lazy)
   DBuf<double> d_tol2;
