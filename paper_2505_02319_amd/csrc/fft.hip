@@ -209,6 +209,34 @@ template <typename R, int P, int Q> constexpr int plane_threads() {
   return (sizeof(R) == 8 && P * Q > 4096) ? 512 : NT;
 }
 
+// The plane transform pair with the multiply by V as a pass of its own
+// (lengths of three stages along p).
+template <typename R, int P, int Q, int PT>
+__device__ __forceinline__ void plane_hv_mul(cplx<R>* pl, const cplx<R>* sP, const cplx<R>* sQ,
+                                             const int* rows, int nrows,
+                                             const R* __restrict__ vp) {
+  constexpr int LQ = Q + 1;
+  const int tid = threadIdx.x;
+  fft2d<R, P, Q, true, PT>(pl, sP, sQ, rows, nrows);
+  constexpr int NV = (P * Q + PT - 1) / PT;
+  R vv[NV];
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int i = tid + u * PT;
+    if (i < P * Q) vv[u] = vp[i];
+  }
+#pragma unroll
+  for (int u = 0; u < NV; ++u) {
+    const int i = tid + u * PT;
+    if (i < P * Q) {
+      const int p = i / Q, q = i % Q;
+      pl[p * LQ + q] = cscale<R>(pl[p * LQ + q], vv[u]);
+    }
+  }
+  __syncthreads();
+  fft2d<R, P, Q, false, PT>(pl, sP, sQ, rows, nrows);
+}
+
 // H psi local part: T -> inverse 2D -> * V -> forward 2D -> T.
 template <typename R, int P, int Q, int PT = plane_threads<R, P, Q>()>
 __global__ __launch_bounds__(PT) void plane_hv_kernel(
@@ -249,30 +277,23 @@ __global__ __launch_bounds__(PT) void plane_hv_kernel(
       if (pv[u] >= 0) pl[(pv[u] / Q) * LQ + (pv[u] % Q)] = tv[u];
   }
   __syncthreads();
-  fft2d<R, P, Q, true, PT>(pl, sP, sQ, rows, nrows);
   const R* vp = V + (v_per_slot ? (size_t)slot * g.C * P * Q : 0) + (size_t)c * P * Q;
-  constexpr int NV = (P * Q + PT - 1) / PT;
-  R vv[NV];
-#pragma unroll
-  for (int u = 0; u < NV; ++u) {
-    const int i = tid + u * PT;
-    if (i < P * Q) vv[u] = vp[i];
+  if constexpr (Rad<P>::S <= 2) {
+    // inverse along q, then along p with the multiply by V and the forward
+    // transform along p fused into the middle stage, then forward along q
+    lds_fft<R, Q, PT, P, true>(pl, rows ? nrows : P, LQ, 1, sQ, rows);
+    lds_fft_pair<R, P, PT, Q>(pl, 1, LQ, sP, [&](int q, int p) { return vp[p * Q + q]; });
+    lds_fft<R, Q, PT, P, false>(pl, rows ? nrows : P, LQ, 1, sQ, rows);
+  } else {
+    plane_hv_mul<R, P, Q, PT>(pl, sP, sQ, rows, nrows, vp);
   }
-#pragma unroll
-  for (int u = 0; u < NV; ++u) {
-    const int i = tid + u * PT;
-    if (i < P * Q) {
-      const int p = i / Q, q = i % Q;
-      pl[p * LQ + q] = cscale<R>(pl[p * LQ + q], vv[u]);
-    }
-  }
-  __syncthreads();
-  fft2d<R, P, Q, false, PT>(pl, sP, sQ, rows, nrows);
   for (int col = tid; col < ncol; col += PT) {
     const int v = pq[col];
     Tout[tb + col] = pl[(v / Q) * LQ + (v % Q)];
   }
 }
+
+
 
 // Density terms: for the slots of a group, a = IFFT2(Ta), b = IFFT2(Tb),
 // acc += wa Re(conj a b) + wb |a|^2, per plane element; written per group.

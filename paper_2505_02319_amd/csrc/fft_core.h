@@ -44,6 +44,14 @@ IKR_RAD(120, 8, 5, 3)
 IKR_RAD(128, 16, 8)
 #undef IKR_RAD
 
+// The same radices in reverse order, for lengths of one or two stages: a
+// transform in this order starts with the butterflies the forward order
+// ends with, on the same elements (see plane_mid).
+template <int N> struct RadRev {
+  static constexpr int S = Rad<N>::S;
+  static constexpr int r[2] = {Rad<N>::r[S - 1], Rad<N>::r[0]};
+};
+
 // ------------------------------------------------------------ small DFTs
 template <typename R, bool INV>
 __host__ __device__ __forceinline__ cplx<R> mul_mi(cplx<R> a) {  // a * (-i) forward, a * (+i) inverse
@@ -183,13 +191,15 @@ template <typename R, bool INV> struct Dft<R, 16, INV> : DftComp<R, 4, 4, INV> {
 // butterfly of neighbouring lines (an LDS stride of lstride, which is 1 or
 // an odd pitch: no bank conflicts) and read the same twiddle (a broadcast).
 // With lmap, line l is the buffer line lmap[l] (a subset of the lines).
-template <typename R, int N, int NT, int MAXL, bool INV, int STAGE, int NS>
+template <typename R, int N, int NT, int MAXL, bool INV, int STAGE, int NS,
+          typename ORD = Rad<N>>
 struct Stages {
-  __device__ __forceinline__ static void run(cplx<R>* buf, int nlines,
+  // this stage alone
+  __device__ __forceinline__ static void one(cplx<R>* buf, int nlines,
                                              int lstride, int estride,
                                              const cplx<R>* __restrict__ tw,
                                              const int* lmap = nullptr) {
-    constexpr int RAD = Rad<N>::r[STAGE];
+    constexpr int RAD = ORD::r[STAGE];
     constexpr int NB = N / RAD;                   // butterflies per line
     constexpr int NV = (MAXL * NB + NT - 1) / NT; // butterflies per thread
     constexpr int tot = MAXL * NB;
@@ -227,9 +237,16 @@ struct Stages {
       }
     }
     __syncthreads();
-    if constexpr (STAGE + 1 < Rad<N>::S)
-      Stages<R, N, NT, MAXL, INV, STAGE + 1, NS * RAD>::run(buf, nlines, lstride, estride, tw,
-                                                            lmap);
+  }
+  // this stage and the ones after it
+  __device__ __forceinline__ static void run(cplx<R>* buf, int nlines,
+                                             int lstride, int estride,
+                                             const cplx<R>* __restrict__ tw,
+                                             const int* lmap = nullptr) {
+    one(buf, nlines, lstride, estride, tw, lmap);
+    if constexpr (STAGE + 1 < ORD::S)
+      Stages<R, N, NT, MAXL, INV, STAGE + 1, NS * ORD::r[STAGE], ORD>::run(
+          buf, nlines, lstride, estride, tw, lmap);
   }
 };
 
@@ -241,6 +258,74 @@ __device__ __forceinline__ void lds_fft(cplx<R>* buf, int nlines, int lstride,
                                         int estride, const cplx<R>* tw,
                                         const int* lmap = nullptr) {
   Stages<R, N, NT, MAXL, INV, 0, 1>::run(buf, nlines, lstride, estride, tw, lmap);
+}
+
+// An inverse transform of all MAXL lines, a pointwise multiply by
+// scale(line, element), and the forward transform, for lengths of one or two
+// stages.  The inverse runs in the order of Rad<N>, the forward one in the
+// reverse order: the last inverse stage (radix A, stride NS = N / A) reads
+// and writes elements b + r N/A of a line, and a forward transform that
+// starts with radix A (stride 1) reads exactly those, so the two stages and
+// the multiply between them run on the butterfly's registers, with one LDS
+// read and one write where separate passes take three of each.
+template <typename R, int N, int NT, int MAXL, typename F>
+__device__ __forceinline__ void lds_fft_pair(cplx<R>* buf, int lstride, int estride,
+                                             const cplx<R>* __restrict__ tw, F&& scale) {
+  static_assert(Rad<N>::S <= 2, "lds_fft_pair: one or two stages");
+  constexpr int S = Rad<N>::S;
+  constexpr int RAD = Rad<N>::r[S - 1];      // radix of the last inverse stage
+  constexpr int NB = N / RAD;                // its butterflies per line = its stride
+  constexpr int NV = (MAXL * NB + NT - 1) / NT;
+  constexpr int tot = MAXL * NB;
+  const int tid = threadIdx.x;
+  // the multipliers of this thread's elements, requested before the first stage
+  R sv[NV][RAD];
+#pragma unroll
+  for (int vi = 0; vi < NV; ++vi) {
+    const int i = tid + NT * vi;
+    const int l = i % MAXL, b = i / MAXL;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) sv[vi][r] = i < tot ? scale(l, b + r * NB) : R(0);
+  }
+  if constexpr (S == 2)
+    Stages<R, N, NT, MAXL, true, 0, 1>::one(buf, MAXL, lstride, estride, tw);
+  cplx<R> v[NV][RAD];
+#pragma unroll
+  for (int vi = 0; vi < NV; ++vi) {
+    const int i = tid + NT * vi;
+    const int l = i % MAXL, b = i / MAXL;
+    if (i < tot) {
+      cplx<R>* line = buf + l * lstride;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) {
+        cplx<R> x = line[(b + r * NB) * estride];
+        if (NB > 1 && r > 0) {   // inverse twiddles of the last stage
+          cplx<R> w = tw[r * b];
+          w.y = -w.y;
+          x = cmul<R>(x, w);
+        }
+        v[vi][r] = x;
+      }
+      Dft<R, RAD, true>::run(v[vi]);
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) v[vi][r] = cscale<R>(v[vi][r], sv[vi][r]);
+      Dft<R, RAD, false>::run(v[vi]);   // the first forward stage (stride 1: no twiddles)
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int vi = 0; vi < NV; ++vi) {
+    const int i = tid + NT * vi;
+    const int l = i % MAXL, b = i / MAXL;
+    if (i < tot) {
+      cplx<R>* line = buf + l * lstride;
+#pragma unroll
+      for (int r = 0; r < RAD; ++r) line[(b * RAD + r) * estride] = v[vi][r];
+    }
+  }
+  __syncthreads();
+  if constexpr (S == 2)
+    Stages<R, N, NT, MAXL, false, 1, RAD, RadRev<N>>::run(buf, MAXL, lstride, estride, tw);
 }
 
 }  // namespace ikr
