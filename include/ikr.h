@@ -360,15 +360,16 @@ int ikr_get_kernel_paths(void);
 
 /* Launch shapes picked by measurement.  At the first Sternheimer CG run of
  * each precision, a system times the candidates of three launch shapes of
- * the CG iteration with HIP events on its stream (one untimed and three timed
- * runs each, the caches flushed before each) and keeps the fastest: the projection gram's kernel and block
+ * the CG iteration with HIP events on its stream (one untimed and three
+ * timed runs each, each after the kernels that precede it in a CG
+ * iteration) and keeps the fastest: the projection gram's kernel and block
  * count, the CG update's band group, and the plane kernel's block size.  It
  * does so for the batch the run starts with, when that batch has more tiles
  * of 16 bands than k-points ("thick"), and for batches of at most 8 and at
  * most 2 bands per k-point, with the run's own batch when that is thin too
  * ("thin": the late iterations, times added); each iteration then takes the
  * shapes of its class.  The size rule is one of the candidates and is kept
- * unless another is more than 5% faster.
+ * unless another is more than 15% faster.
  * IKR_VERBOSE=1 in the environment logs every candidate's time to stderr.
  * ikr_get_tuning fills out[24]: for precision p (0 FP64, 1 FP32) and class c
  * (0 thick, 1 thin), the 6 entries from out[12 p + 6 c] are: measured (1) or

@@ -272,17 +272,18 @@ template <> const float2* wcg_of<float>(const System& s) { return s.w32.wcg.get(
 // vector) and its block count, the tiled update's band group, and the
 // threads of the plane kernel.  At the first CG run of a precision, each
 // candidate runs once untimed and three times between HIP events on the CG
-// stream, each time after a write of 512 MB that flushes the caches (as the
-// other kernels of an iteration do), on the batch the run starts with (when
+// stream, each time after the kernels that precede it in a CG iteration (so
+// that it meets the caches as in the solve), on the batch the run starts with (when
 // it has more tiles than k-points: the "thick" class) and on thin batches of
 // at most 8 and 2 bands per k-point, with the run's own batch when that is
 // thin too (the "thin" class; its times are added).  The size rule is a
-// candidate too and stays unless another is more than 5% faster (the size
-// rules also adapt to the shrinking batch, a fixed pick does not).
+// candidate too and stays unless another is more than 15% faster: the size
+// rules also adapt to the shrinking batch, a fixed pick does not, and picks
+// with smaller margins did not hold in whole solves.
 // All candidates compute the same quantities.  The runs write only scratch:
 // gram partials and coefficients, the plane buffer, and the direction rows
 // p, Ap of the batch's slots, which the CG run overwrites before reading.
-constexpr double TUNE_MARGIN = 0.95;
+constexpr double TUNE_MARGIN = 0.85;
 constexpr int TUNE_REPS = 3;
 
 template <typename R>
@@ -328,31 +329,44 @@ static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<in
     IKR_HIP(hipEventElapsedTime(&ms, e0, e1));
     return 1000.0 * ms;
   };
-  // summed time (us per launch) of launch(batch) over the sets: one untimed
-  // launch, then 1 to 5 timed ones (about 1 ms of launches, at least one);
-  // a candidate already 30% behind the best after a set is not run further
-  // the caches (L2 and the 256 MB last-level cache) are flushed before every
-  // timed launch by writing a buffer larger than both, as the other kernels of
-  // a CG iteration do between two grams: back to back, a launch would find
-  // its operands cached
-  DBuf<unsigned char> flush;
-  constexpr size_t FLUSH_BYTES = (size_t)512 << 20;
-  flush.alloc(FLUSH_BYTES);
-  unsigned char fv = 0;
-  auto one = [&](auto&& launch, const Batch& bt) {
-    IKR_HIP(hipMemsetAsync(flush.get(), ++fv, FLUSH_BYTES, st));
+  // Each timed launch runs where it runs in a CG iteration: after the
+  // kernels before it in the iteration (prefix), so that it meets the caches
+  // as they are there; back to back, or after a flush, a launch finds its
+  // operands cached, or not at all, and the picks do not hold in the solve.
+  const R inv_ng = R(1.0 / s.ng);
+  auto col_inv = [&](const Batch& bt) {
+    launch_col_inv<R>(s.geom, s.fft, bt.sl, w.p.get(), nbm, w.T1.get(), w.w.get(),
+                      w.beta.get(), w.p.get(), st);
+  };
+  auto to_gram = [&](const Batch& bt, const KernelTune& kt) {   // p~ and w~ of an iteration
+    col_inv(bt);
+    launch_plane_hv<R>(s.geom, s.fft, bt.sl, w.T1.get(), w.T2.get(), vloc, 0, st, kt.plane_pt);
+    launch_col_fwd<R>(s.geom, s.fft, bt.sl, w.T2.get(), w.w.get(), nbm, w.p.get(),
+                      w.shift.get(), inv_ng, st);
+  };
+  auto gram_and_reduce = [&](const Batch& bt, const KernelTune& kt) {
+    const KTileRange krg{s.nk, s.d_ktb.get(), bt.ktmax};
+    const int nsc = gram_partials<R>(bt.tl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm,
+                                     w.p.get(), nbm, w.part.get(), st, nullptr, krg, &kt);
+    gram_reduce<R>(bt.tl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
+  };
+  auto one = [&](auto&& prefix, auto&& launch, const Batch& bt) {
+    prefix(bt);
     IKR_HIP(hipEventRecord(e0, st));
     launch(bt);
     IKR_HIP(hipEventRecord(e1, st));
     return elapsed_us();
   };
-  auto time_us = [&](auto&& launch, double best) {
+  // summed time (us per launch) over the sets: one untimed run, then
+  // TUNE_REPS timed ones; a candidate already 30% behind the best after a
+  // set is not run further
+  auto time_us = [&](auto&& prefix, auto&& launch, double best) {
     double tot = 0;
     for (const auto& set : sets) {
       const Batch bt = select(set);
-      (void)one(launch, bt);   // untimed: first use
+      (void)one(prefix, launch, bt);   // untimed: first use
       double t = 0;
-      for (int r = 0; r < TUNE_REPS; ++r) t += one(launch, bt);
+      for (int r = 0; r < TUNE_REPS; ++r) t += one(prefix, launch, bt);
       tot += t / TUNE_REPS;
       if (best > 0 && tot > 1.3 * best) return 1e300;
     }
@@ -377,12 +391,8 @@ static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<in
         c.gram_scale = sc;
         if (v == 0 && sc != 1.0f) continue;
         if (v > 0 && (gram_variant(Mrows, kr, &c) != v || (v == vdef && sc == 1.0f))) continue;
-        const double t = time_us([&](const Batch& bt) {
-          const KTileRange krg{s.nk, s.d_ktb.get(), bt.ktmax};
-          const int nsc = gram_partials<R>(bt.tl, s.d_nb.get(), nbm, dMcg, Mrows, wcg, wk, nbm,
-                                           w.p.get(), nbm, w.part.get(), st, nullptr, krg, &c);
-          gram_reduce<R>(bt.tl, dMcg, Mrows, nsc, w.part.get(), w.craw.get(), s.mcg, st);
-        }, tg);
+        const double t = time_us([&](const Batch& bt) { to_gram(bt, KernelTune{}); },
+                                 [&](const Batch& bt) { gram_and_reduce(bt, c); }, tg);
         std::snprintf(buf, sizeof buf, t < 1e300 ? " %c%.1f:%.1f" : " %c%.1f:-", "SPKV"[v], sc, t);
         log += buf;
         if (better(t, tg, first)) { tg = t; best.gram = v; best.gram_scale = sc; }
@@ -397,10 +407,18 @@ static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<in
       if (bpt && (size_t)bpt * (Na + 3 * Mq_max) * sizeof(cplx<R>) > 65536) continue;
       KernelTune c = best;
       c.upd_bpt = bpt;
-      const double t = time_us([&](const Batch& bt) {
-        cg_update<R>(bt.tl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(), s.mcg,
-                     w.w.get(), w.p.get(), w.dpart.get(), st, kr, &c);
-      }, tu);
+      const double t = time_us(
+          [&](const Batch& bt) {
+            to_gram(bt, KernelTune{});
+            gram_and_reduce(bt, best);
+            cg_combine<R>(bt.sl, Na, dMq, Mq_max, w.craw.get(), s.mcg, w.shift.get(),
+                          w.gT.get(), w.sT.get(), s.nbands, R(s.dnl), w.gam.get(), st);
+          },
+          [&](const Batch& bt) {
+            cg_update<R>(bt.tl, s.d_nb.get(), nbm, wcg, wk, Na, dMq, Mq_max, w.gam.get(),
+                         s.mcg, w.w.get(), w.p.get(), w.dpart.get(), st, kr, &c);
+          },
+          tu);
       std::snprintf(buf, sizeof buf, t < 1e300 ? " b%d:%.1f" : " b%d:-", bpt, t);
       log += buf;
       if (better(t, tu, first)) { tu = t; best.upd_bpt = bpt; }
@@ -414,7 +432,7 @@ static void tune_class(System& s, CgWork<R>& w, const std::vector<std::vector<in
     const int pdef = plane_hv_threads(s.geom, 0, sizeof(R) == 8);
     for (int pt : {0, 256, 512}) {
       if (pt && (pt == pdef || plane_hv_threads(s.geom, pt, sizeof(R) == 8) != pt)) continue;
-      const double t = time_us([&](const Batch& bt) {
+      const double t = time_us(col_inv, [&](const Batch& bt) {
         launch_plane_hv<R>(s.geom, s.fft, bt.sl, w.T1.get(), w.T2.get(), vloc, 0, st, pt);
       }, tp);
       std::snprintf(buf, sizeof buf, t < 1e300 ? " t%d:%.1f" : " t%d:-", pt ? pt : pdef, t);
