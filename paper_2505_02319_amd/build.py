@@ -15,7 +15,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libikr.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["fft.hip", "blas.hip", "cg.hip", "noalloc.hip", "setup.cpp", "groundstate.cpp", "solver.cpp", "gradient.cpp", "displacement.cpp", "ktimer.cpp",
+SOURCES = ["fft.hip", "blas.hip", "cg.hip", "noalloc.hip", "setup.cpp", "groundstate.cpp", "solver.cpp", "hostmath.cpp", "gradient.cpp", "displacement.cpp", "ktimer.cpp",
            "api.cpp"]
 
 FLAGS = [

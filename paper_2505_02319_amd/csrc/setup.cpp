@@ -8,6 +8,7 @@
 #include <memory>
 
 #include "cg.h"
+#include "hostmath.h"
 #include "system.h"
 
 namespace ikr {
@@ -21,15 +22,8 @@ constexpr double EPS_OCC = 1e-10;    // occupied when f > EPS_OCC
 
 int fold(int i, int n) { return i < 0 ? i + n : i; }
 
-// 2 / (1 + e^x) without overflow, and its x-derivative.
-double focc(double x) {
-  const double e = std::exp(-std::fabs(x));
-  return x > 0 ? 2.0 * e / (1.0 + e) : 2.0 / (1.0 + e);
-}
-double focc_dx(double x) {
-  const double e = std::exp(-std::fabs(x));
-  return -2.0 * e / ((1.0 + e) * (1.0 + e));
-}
+using host::focc;
+using host::focc_dx;
 
 }  // namespace
 

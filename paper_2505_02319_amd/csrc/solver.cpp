@@ -10,6 +10,7 @@
 #include <cstdlib>
 
 #include "cg.h"
+#include "hostmath.h"
 #include "ktimer.h"
 #include "system.h"
 
@@ -25,128 +26,14 @@ constexpr double WARM_REL = 0.1;      // warm start when it leaves under this of
 constexpr int FP32_STAG_ITERS = 30;   // an FP32 band whose |r|^2 has not halved in this many
                                       // iterations stops (and is solved again in FP64)
 
-// Least squares over the stored right-hand sides of one band: c minimising
-// ||b - sum_l c_l b_l|| from the Gram matrix G (row-major, leading size ld,
-// the first nv entries) and h_l = <b_l, b>; Cholesky of G with a small ridge.
-// Returns the predicted squared residual ||b||^2 - Re(h^H c) (bb = ||b||^2).
-double warm_coefficients(const double2* G, int ld, int nv, const double2* h, double bb,
-                         std::vector<double2>& c) {
-  double tr = 0;
-  for (int i = 0; i < nv; ++i) tr += G[i * ld + i].x;
-  const double ridge = 1e-12 * tr + 1e-300;
-  std::vector<double2> Lc((size_t)nv * nv, mk<double>(0, 0));
-  for (int j = 0; j < nv; ++j) {
-    double d = G[j * ld + j].x + ridge;
-    for (int k = 0; k < j; ++k) {
-      const double2 l = Lc[(size_t)j * nv + k];
-      d -= l.x * l.x + l.y * l.y;
-    }
-    if (!(d > 0)) { c.assign(nv, mk<double>(0, 0)); return bb; }
-    const double ljj = std::sqrt(d);
-    Lc[(size_t)j * nv + j] = mk<double>(ljj, 0);
-    for (int i = j + 1; i < nv; ++i) {
-      double2 v = G[i * ld + j];
-      for (int k = 0; k < j; ++k)
-        v = csub<double>(v, cmul<double>(Lc[(size_t)i * nv + k],
-                                         mk<double>(Lc[(size_t)j * nv + k].x,
-                                                    -Lc[(size_t)j * nv + k].y)));
-      Lc[(size_t)i * nv + j] = cscale<double>(v, 1.0 / ljj);
-    }
-  }
-  // G c = h: L y = h, then L^H c = y
-  std::vector<double2> y(nv);
-  for (int i = 0; i < nv; ++i) {
-    double2 v = h[i];
-    for (int k = 0; k < i; ++k) v = csub<double>(v, cmul<double>(Lc[(size_t)i * nv + k], y[k]));
-    y[i] = cscale<double>(v, 1.0 / Lc[(size_t)i * nv + i].x);
-  }
-  c.assign(nv, mk<double>(0, 0));
-  for (int i = nv - 1; i >= 0; --i) {
-    double2 v = y[i];
-    for (int k = i + 1; k < nv; ++k)
-      v = csub<double>(v, cmulc<double>(Lc[(size_t)k * nv + i], c[k]));
-    c[i] = cscale<double>(v, 1.0 / Lc[(size_t)i * nv + i].x);
-  }
-  double hc = 0;
-  for (int i = 0; i < nv; ++i) hc += h[i].x * c[i].x + h[i].y * c[i].y;   // Re(h^H c)
-  return bb - hc;
-}
-
-double focc_dx(double x) {
-  const double e = std::exp(-std::fabs(x));
-  return -2.0 * e / ((1.0 + e) * (1.0 + e));
-}
+using host::sigma_min;
+using host::small_ls;
 
 template <typename T> std::vector<T> download(const T* d, size_t n, hipStream_t st) {
   std::vector<T> h(n);
   if (n) IKR_HIP(hipMemcpyAsync(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost, st));
   IKR_HIP(hipStreamSynchronize(st));
   return h;
-}
-
-// Smallest singular value of an (r x c) row-major matrix, one-sided Jacobi.
-double sigma_min(const std::vector<double>& H, int r, int c) {
-  std::vector<double> A(H);
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0;
-    for (int p = 0; p < c; ++p)
-      for (int q = p + 1; q < c; ++q) {
-        double al = 0, be = 0, ga = 0;
-        for (int i = 0; i < r; ++i) {
-          al += A[i * c + p] * A[i * c + p];
-          be += A[i * c + q] * A[i * c + q];
-          ga += A[i * c + p] * A[i * c + q];
-        }
-        if (ga == 0) continue;
-        off = std::max(off, std::fabs(ga) / std::sqrt(al * be));
-        const double zeta = (be - al) / (2 * ga);
-        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1 + zeta * zeta));
-        const double cs = 1 / std::sqrt(1 + t * t), sn = cs * t;
-        for (int i = 0; i < r; ++i) {
-          const double x = A[i * c + p], y = A[i * c + q];
-          A[i * c + p] = cs * x - sn * y;
-          A[i * c + q] = sn * x + cs * y;
-        }
-      }
-    if (off < 1e-15) break;
-  }
-  double mn = 1e300;
-  for (int p = 0; p < c; ++p) {
-    double n2 = 0;
-    for (int i = 0; i < r; ++i) n2 += A[i * c + p] * A[i * c + p];
-    mn = std::min(mn, std::sqrt(n2));
-  }
-  return mn;
-}
-
-// min_y ||beta e1 - H y|| for the (i+1) x i Hessenberg (row-major, ld = m)
-// by Givens rotations; returns the residual norm and y.
-double small_ls(const std::vector<double>& H, int ld, int i, double beta,
-                std::vector<double>& y) {
-  std::vector<double> R((size_t)(i + 1) * i), g(i + 1, 0.0);
-  for (int a = 0; a <= i; ++a)
-    for (int b = 0; b < i; ++b) R[a * i + b] = H[a * ld + b];
-  g[0] = beta;
-  for (int j = 0; j < i; ++j) {
-    const double a = R[j * i + j], b = R[(j + 1) * i + j];
-    const double rr = std::hypot(a, b);
-    const double c = rr > 0 ? a / rr : 1.0, sn = rr > 0 ? b / rr : 0.0;
-    for (int col = j; col < i; ++col) {
-      const double x = R[j * i + col], z = R[(j + 1) * i + col];
-      R[j * i + col] = c * x + sn * z;
-      R[(j + 1) * i + col] = -sn * x + c * z;
-    }
-    const double x = g[j], z = g[j + 1];
-    g[j] = c * x + sn * z;
-    g[j + 1] = -sn * x + c * z;
-  }
-  y.assign(i, 0.0);
-  for (int j = i - 1; j >= 0; --j) {
-    double v = g[j];
-    for (int col = j + 1; col < i; ++col) v -= R[j * i + col] * y[col];
-    y[j] = R[j * i + j] != 0 ? v / R[j * i + j] : 0.0;
-  }
-  return std::fabs(g[i]);
 }
 
 }  // namespace
@@ -924,14 +811,8 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     for (int m = 0; m < s.nocc_k[k]; ++m) {
       if (m == n) continue;
       const double fm = s.occ[(size_t)k * nbn + m], em = s.eps[(size_t)k * nbn + m];
-      double d;
-      if (std::fabs(en - em) < DEGEN_TOL) {
-        d = s.temperature > 0
-                ? focc_dx((0.5 * (en + em) - s.fermi) / s.temperature) / s.temperature
-                : 0.0;
-      } else {
-        d = (fn - fm) / (en - em);
-      }
+      const double d = host::occupation_divided_difference(fn, fm, en, em, s.fermi,
+                                                           s.temperature, DEGEN_TOL);
       if (d == 0.0) continue;
       const double al = fn * d / (fn * fn + fm * fm);
       dp[(size_t)j * MAXM + m] = cscale<double>(M[(size_t)j * MAXM + m], al);
@@ -943,13 +824,8 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
     if (use_schur)
       for (int m = s.nocc_k[k]; m < nbn; ++m) {
         const double em = s.eps[(size_t)k * nbn + m];
-        double c;
-        if (std::fabs(en - em) < DEGEN_TOL)
-          c = (s.temperature > 0 && fn > 0)
-                  ? focc_dx((0.5 * (en + em) - s.fermi) / s.temperature) / (s.temperature * fn)
-                  : 0.0;
-        else
-          c = 1.0 / (en - em);
+        const double c = host::extra_band_coefficient(fn, en, em, s.fermi, s.temperature,
+                                                      DEGEN_TOL);
         dp[(size_t)j * MAXM + m] = cscale<double>(M[(size_t)j * MAXM + m], c);
       }
   }
@@ -1012,12 +888,14 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
       std::vector<double> ratio(J);
       for (int j = 0; j < J; ++j) {
         const double2* h = hdot.data() + (size_t)j * nv;
-        std::vector<double2> c_j;
-        const double pred = warm_coefficients(s.rec_G.data() + (size_t)j * L * L, L, nv, h,
-                                              bn[j] * bn[j], c_j);
+        std::vector<host::zd> c_j;
+        const double pred = host::warm_coefficients(
+            reinterpret_cast<const host::zd*>(s.rec_G.data() + (size_t)j * L * L), L, nv,
+            reinterpret_cast<const host::zd*>(h), bn[j] * bn[j], c_j);
         ratio[j] = std::sqrt(std::max(pred, 0.0)) / std::max(bn[j], 1e-300);
         if (pred < WARM_REL * WARM_REL * bn[j] * bn[j]) {
-          std::copy(c_j.begin(), c_j.end(), c.begin() + (size_t)j * nv);
+          for (int l = 0; l < nv; ++l)
+            c[(size_t)j * nv + l] = mk<double>(c_j[l].real(), c_j[l].imag());
           wl.push_back(j);
         }
       }
@@ -1209,38 +1087,31 @@ Chi0Result apply_chi0_internal(System& s, const double* u_int, double* drho_int,
 static std::vector<double> prefactors(const System& s, int strategy, double knorm,
                                       double bnorm, bool schur) {
   std::vector<double> p(s.J, 1.0);
-  const double nocc_tot = s.J;
   for (int j = 0; j < s.J; ++j) {
-    const int k = s.slot_k[j];
-    const double f = s.occ[(size_t)k * s.nbands + s.slot_n[j]];
-    const double wk = s.kp[k].weight;
-    switch (strategy) {
-      case IKR_AGR: p[j] = 1.0; break;
-      case IKR_BAL: p[j] = s.volume / (2.0 * f * wk * nocc_tot * std::sqrt((double)s.ng)); break;
-      case IKR_GRT:
-        p[j] = std::sqrt(s.volume) / (2.0 * f * wk * std::sqrt((double)s.ng) *
-                                      std::sqrt(nocc_tot) * knorm * s.orbnorm_k[k]);
-        break;
-      case IKR_THM2: {
-        // C_{i,nk} of Theorem 2 in its k-point form; where every computed band
-        // is occupied the gap is taken to the highest computed band (>= 1e-4 Ha)
-        // With the extra bands taken by sum over states the CG operator's
-        // smallest eigenvalue is e_{nbands+1} - e_n >= e_{nbands} - e_n.
-        const int n = s.slot_n[j], no = s.nocc_k[k];
-        const double en = s.eps[(size_t)k * s.nbands + n];
-        const double eup = (no < s.nbands && !schur) ? s.eps[(size_t)k * s.nbands + no]
-                                                     : s.eps[(size_t)k * s.nbands + s.nbands - 1];
-        const double gap = std::max(eup - en, (no < s.nbands && !schur) ? 0.0 : 1e-4);
-        p[j] = std::sqrt(s.volume) * gap /
-               (2.0 * f * wk * knorm * s.orbnorm_full_k[k] * s.nk *
-                std::sqrt((double)s.ng * no));
-        break;
-      }
-      case IKR_D10: p[j] = 0.1; break;
-      case IKR_D100: p[j] = 0.01; break;
-      case IKR_D10N: p[j] = 0.1 / bnorm; break;
-      default: p[j] = 1.0;
+    const int k = s.slot_k[j], n = s.slot_n[j], no = s.nocc_k[k];
+    host::BandTolInputs a;
+    a.volume = s.volume;
+    a.ng = (double)s.ng;
+    a.nocc_tot = s.J;
+    a.f = s.occ[(size_t)k * s.nbands + n];
+    a.wk = s.kp[k].weight;
+    a.knorm = knorm;
+    a.orbnorm = s.orbnorm_k[k];
+    a.orbnorm_full = s.orbnorm_full_k[k];
+    a.nk = s.nk;
+    a.nocc_k = no;
+    a.bnorm = bnorm;
+    if (strategy == IKR_THM2) {
+      // where every computed band is occupied the gap is taken to the highest
+      // computed band (>= 1e-4 Ha); with the extra bands taken by sum over
+      // states the CG operator's smallest eigenvalue is e_{nbands+1} - e_n >=
+      // e_{nbands} - e_n
+      const double en = s.eps[(size_t)k * s.nbands + n];
+      const bool above = no < s.nbands && !schur;
+      const double eup = s.eps[(size_t)k * s.nbands + (above ? no : s.nbands - 1)];
+      a.gap = std::max(eup - en, above ? 0.0 : 1e-4);
     }
+    p[j] = host::band_prefactor(strategy, a);
   }
   return p;
 }
