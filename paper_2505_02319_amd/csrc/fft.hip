@@ -186,21 +186,26 @@ __device__ __forceinline__ void fft2d(cplx<R>* pl, const cplx<R>* twP,
                                       int nrows = P) {
   constexpr int LQ = Q + 1;
   if (INV) {
-    lds_fft<R, Q, BT_, P, true>(pl, rows ? nrows : P, LQ, 1, twQ, rows);
+    if (rows)
+      lds_fft_rows<R, Q, BT_, P, true>(pl, nrows, LQ, 1, twQ, rows);
+    else
+      lds_fft<R, Q, BT_, P, true>(pl, P, LQ, 1, twQ);
     lds_fft<R, P, BT_, Q, true>(pl, Q, 1, LQ, twP);
   } else {
     lds_fft<R, P, BT_, Q, false>(pl, Q, 1, LQ, twP);
-    lds_fft<R, Q, BT_, P, false>(pl, rows ? nrows : P, LQ, 1, twQ, rows);
+    if (rows)
+      lds_fft_rows<R, Q, BT_, P, false>(pl, nrows, LQ, 1, twQ, rows);
+    else
+      lds_fft<R, Q, BT_, P, false>(pl, P, LQ, 1, twQ);
   }
 }
 
-// The footprint rows of k-point k in LDS (rows[P]); returns their number,
-// or P (all rows) when the geometry has no row lists.
+// The footprint rows of k-point k in LDS (rows[P]); returns their number.
+// A geometry without row lists gives all P rows.
 template <int P, int BT_ = NT>
 __device__ __forceinline__ int load_rows(const Geom& g, int k, int* rows) {
-  if (!g.prow) return P;
-  for (int i = threadIdx.x; i < P; i += BT_) rows[i] = g.prow[(size_t)k * P + i];
-  return g.nprow[k];
+  for (int i = threadIdx.x; i < P; i += BT_) rows[i] = g.prow ? g.prow[(size_t)k * P + i] : i;
+  return g.prow ? g.nprow[k] : P;
 }
 
 // Threads per plane block: the 60 x 108 FP64 plane (105 KiB of LDS, one
@@ -281,9 +286,9 @@ __global__ __launch_bounds__(PT) void plane_hv_kernel(
   if constexpr (Rad<P>::S <= 2) {
     // inverse along q, then along p with the multiply by V and the forward
     // transform along p fused into the middle stage, then forward along q
-    lds_fft<R, Q, PT, P, true>(pl, rows ? nrows : P, LQ, 1, sQ, rows);
+    lds_fft_rows<R, Q, PT, P, true>(pl, nrows, LQ, 1, sQ, rows);
     lds_fft_pair<R, P, PT, Q>(pl, 1, LQ, sP, [&](int q, int p) { return vp[p * Q + q]; });
-    lds_fft<R, Q, PT, P, false>(pl, rows ? nrows : P, LQ, 1, sQ, rows);
+    lds_fft_rows<R, Q, PT, P, false>(pl, nrows, LQ, 1, sQ, rows);
   } else {
     plane_hv_mul<R, P, Q, PT>(pl, sP, sQ, rows, nrows, vp);
   }

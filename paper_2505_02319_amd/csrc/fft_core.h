@@ -190,9 +190,10 @@ template <typename R, bool INV> struct Dft<R, 16, INV> : DftComp<R, 4, 4, INV> {
 // ceil(MAXL * NB / NT) butterflies, neighbouring lanes take the same
 // butterfly of neighbouring lines (an LDS stride of lstride, which is 1 or
 // an odd pitch: no bank conflicts) and read the same twiddle (a broadcast).
-// With lmap, line l is the buffer line lmap[l] (a subset of the lines).
+// With lmap, line l is the buffer line lmap[l] (a subset of the lines); PK
+// deals the pairs over the nlines listed lines instead of MAXL.
 template <typename R, int N, int NT, int MAXL, bool INV, int STAGE, int NS,
-          typename ORD = Rad<N>>
+          typename ORD = Rad<N>, bool PK = false>
 struct Stages {
   // this stage alone
   __device__ __forceinline__ static void one(cplx<R>* buf, int nlines,
@@ -202,15 +203,35 @@ struct Stages {
     constexpr int RAD = ORD::r[STAGE];
     constexpr int NB = N / RAD;                   // butterflies per line
     constexpr int NV = (MAXL * NB + NT - 1) / NT; // butterflies per thread
-    constexpr int tot = MAXL * NB;
     const int tid = threadIdx.x;
+    // PK (packed; lmap required): the pairs are dealt over the nlines listed
+    // lines only (pair i -> line i % nlines, butterfly i / nlines), so no
+    // lane idles on an unlisted line and whole wavefronts drop out past
+    // nlines * NB.  i / n is (i * M) >> 31 with M = floor(2^31 / n) + 1:
+    // M n - 2^31 lies in (0, n], so the product overshoots i 2^31 / n by less
+    // than i n, under 2^31 for every i < MAXL * NB (MAXL <= 128, NB <= 64)
+    // and thus never reaches the next multiple of 2^31 / n.  Otherwise:
+    // line i % MAXL, lines past nlines idle.
+    const int tot = PK ? nlines * NB : MAXL * NB;
+    unsigned magic = 0;
+    if constexpr (PK) magic = 0x80000000u / (unsigned)(nlines > 0 ? nlines : 1) + 1u;
+    auto pair = [&](int i, int& l, int& b) {
+      if constexpr (PK) {
+        b = (int)(((unsigned long long)(unsigned)i * magic) >> 31);
+        l = i - b * nlines;
+      } else {
+        l = i % MAXL;
+        b = i / MAXL;
+      }
+    };
     cplx<R> v[NV][RAD];
 #pragma unroll
     for (int vi = 0; vi < NV; ++vi) {
       const int i = tid + NT * vi;
-      const int l = i % MAXL, b = i / MAXL;
+      int l, b;
+      pair(i, l, b);
       if (i < tot && l < nlines) {
-        cplx<R>* line = buf + (lmap ? lmap[l] : l) * lstride;
+        cplx<R>* line = buf + (PK ? lmap[l] : (lmap ? lmap[l] : l)) * lstride;
 #pragma unroll
         for (int r = 0; r < RAD; ++r) {
           cplx<R> x = line[(b + r * NB) * estride];
@@ -228,9 +249,10 @@ struct Stages {
 #pragma unroll
     for (int vi = 0; vi < NV; ++vi) {
       const int i = tid + NT * vi;
-      const int l = i % MAXL, b = i / MAXL;
+      int l, b;
+      pair(i, l, b);
       if (i < tot && l < nlines) {
-        cplx<R>* line = buf + (lmap ? lmap[l] : l) * lstride;
+        cplx<R>* line = buf + (PK ? lmap[l] : (lmap ? lmap[l] : l)) * lstride;
         const int d = (b / NS) * NS * RAD + (b % NS);
 #pragma unroll
         for (int r = 0; r < RAD; ++r) line[(d + r * NS) * estride] = v[vi][r];
@@ -245,7 +267,7 @@ struct Stages {
                                              const int* lmap = nullptr) {
     one(buf, nlines, lstride, estride, tw, lmap);
     if constexpr (STAGE + 1 < ORD::S)
-      Stages<R, N, NT, MAXL, INV, STAGE + 1, NS * ORD::r[STAGE], ORD>::run(
+      Stages<R, N, NT, MAXL, INV, STAGE + 1, NS * ORD::r[STAGE], ORD, PK>::run(
           buf, nlines, lstride, estride, tw, lmap);
   }
 };
@@ -258,6 +280,14 @@ __device__ __forceinline__ void lds_fft(cplx<R>* buf, int nlines, int lstride,
                                         int estride, const cplx<R>* tw,
                                         const int* lmap = nullptr) {
   Stages<R, N, NT, MAXL, INV, 0, 1>::run(buf, nlines, lstride, estride, tw, lmap);
+}
+
+// The nlines lines that lmap lists (non-null), their (line, butterfly)
+// pairs dealt over those lines only.
+template <typename R, int N, int NT, int MAXL, bool INV>
+__device__ __forceinline__ void lds_fft_rows(cplx<R>* buf, int nlines, int lstride,
+                                             int estride, const cplx<R>* tw, const int* lmap) {
+  Stages<R, N, NT, MAXL, INV, 0, 1, Rad<N>, true>::run(buf, nlines, lstride, estride, tw, lmap);
 }
 
 // An inverse transform of all MAXL lines, a pointwise multiply by
