@@ -283,7 +283,7 @@ __global__ __launch_bounds__(PT) void plane_hv_kernel(
   }
   __syncthreads();
   const R* vp = V + (v_per_slot ? (size_t)slot * g.C * P * Q : 0) + (size_t)c * P * Q;
-  if constexpr (Rad<P>::S <= 2) {
+  if constexpr (PairOrd<P>::S <= 2) {
     // inverse along q, then along p with the multiply by V and the forward
     // transform along p fused into the middle stage, then forward along q
     lds_fft_rows<R, Q, PT, P, true>(pl, nrows, LQ, 1, sQ, rows);

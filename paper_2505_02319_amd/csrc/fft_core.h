@@ -44,12 +44,23 @@ IKR_RAD(120, 8, 5, 3)
 IKR_RAD(128, 16, 8)
 #undef IKR_RAD
 
-// The same radices in reverse order, for lengths of one or two stages: a
-// transform in this order starts with the butterflies the forward order
-// ends with, on the same elements (see plane_mid).
-template <int N> struct RadRev {
-  static constexpr int S = Rad<N>::S;
-  static constexpr int r[2] = {Rad<N>::r[S - 1], Rad<N>::r[0]};
+// A radix order of one or two stages reversed: a transform in this order
+// starts with the butterflies the original order ends with, on the same
+// elements (lds_fft_pair).
+template <typename ORD> struct RevOrd {
+  static constexpr int S = ORD::S;
+  static constexpr int r[2] = {ORD::r[S - 1], ORD::r[0]};
+};
+
+// The radix order of the inverse transform of lds_fft_pair (the forward one
+// runs in reverse).  By default that of Rad<N>; 48 takes 12 * 4, whose stages
+// deal 4 and 12 butterflies per line, whole wavefronts over 48 lines, where
+// 16 * 3 deals 3 per line (144 per 48 lines: the third wavefront of 256
+// threads a quarter full) for about the same arithmetic.
+template <int N> struct PairOrd : Rad<N> {};
+template <> struct PairOrd<48> {
+  static constexpr int r[] = {12, 4};
+  static constexpr int S = 2;
 };
 
 // ------------------------------------------------------------ small DFTs
@@ -157,6 +168,12 @@ template <typename R, int A, int B, bool INV> struct DftComp {
         const int m = (j2 * k1) % N;
         if (m == 0) {
           y[j2][k1] = t[k1];
+        } else if (4 * m == N) {         // -i forward, +i inverse
+          y[j2][k1] = mul_mi<R, INV>(t[k1]);
+        } else if (2 * m == N) {         // -1
+          y[j2][k1] = mk<R>(-t[k1].x, -t[k1].y);
+        } else if (4 * m == 3 * N) {     // +i forward, -i inverse
+          y[j2][k1] = mul_mi<R, !INV>(t[k1]);
         } else {
           const R c = R(TwConst<N>::c[m]);
           const R sn = INV ? R(TwConst<N>::s[m]) : R(-TwConst<N>::s[m]);
@@ -301,9 +318,10 @@ __device__ __forceinline__ void lds_fft_rows(cplx<R>* buf, int nlines, int lstri
 template <typename R, int N, int NT, int MAXL, typename F>
 __device__ __forceinline__ void lds_fft_pair(cplx<R>* buf, int lstride, int estride,
                                              const cplx<R>* __restrict__ tw, F&& scale) {
-  static_assert(Rad<N>::S <= 2, "lds_fft_pair: one or two stages");
-  constexpr int S = Rad<N>::S;
-  constexpr int RAD = Rad<N>::r[S - 1];      // radix of the last inverse stage
+  using ORD = PairOrd<N>;
+  static_assert(ORD::S <= 2, "lds_fft_pair: one or two stages");
+  constexpr int S = ORD::S;
+  constexpr int RAD = ORD::r[S - 1];         // radix of the last inverse stage
   constexpr int NB = N / RAD;                // its butterflies per line = its stride
   constexpr int NV = (MAXL * NB + NT - 1) / NT;
   constexpr int tot = MAXL * NB;
@@ -318,7 +336,7 @@ __device__ __forceinline__ void lds_fft_pair(cplx<R>* buf, int lstride, int estr
     for (int r = 0; r < RAD; ++r) sv[vi][r] = i < tot ? scale(l, b + r * NB) : R(0);
   }
   if constexpr (S == 2)
-    Stages<R, N, NT, MAXL, true, 0, 1>::one(buf, MAXL, lstride, estride, tw);
+    Stages<R, N, NT, MAXL, true, 0, 1, ORD>::one(buf, MAXL, lstride, estride, tw);
   cplx<R> v[NV][RAD];
 #pragma unroll
   for (int vi = 0; vi < NV; ++vi) {
@@ -355,7 +373,7 @@ __device__ __forceinline__ void lds_fft_pair(cplx<R>* buf, int lstride, int estr
   }
   __syncthreads();
   if constexpr (S == 2)
-    Stages<R, N, NT, MAXL, false, 1, RAD, RadRev<N>>::run(buf, MAXL, lstride, estride, tw);
+    Stages<R, N, NT, MAXL, false, 1, RAD, RevOrd<ORD>>::run(buf, MAXL, lstride, estride, tw);
 }
 
 }  // namespace ikr
