@@ -3,7 +3,7 @@
 Follows the paper's Sec. 2.3.1 (plane-wave bases, eq. fourier_bases and
 eq. fft_ifft), eq. (Hamiltonian) and its Bloch form in Sec. 4.1.1.
 
-Readings where the paper is silent (all from the survey of the paper):
+Readings where the paper is silent or garbled, taken here:
   * orthorhombic cells only; reciprocal vectors b_i = 2 pi / a_i;
   * the k-grid is Gamma-centred and unshifted, k_j = (i_j / l_j) folded
     into [-1/2, 1/2), weights 1/N_k, no symmetry reduction (the printed
