@@ -136,7 +136,7 @@ def inexact_gmres(sys: System, gs: GroundState, kern: HxcKernel,
 
     restarts = 0
     while True:
-        # line 1: r0 = b - E~(0) x0 with ||(E - E~(0)) x0|| <= tau/3
+        # the initial residual r0 = b - E~(0) x0, with ||(E - E~(0)) x0|| <= tau/3
         if np.linalg.norm(x0v) == 0.0:
             r0 = rhs_vec.copy()
         else:

@@ -1314,7 +1314,7 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
   bool done = bnorm == 0.0;
   if (done) IKR_HIP(hipMemsetAsync(x_ext, 0, (size_t)n * sizeof(double), st));   // E^-1 0 = 0
   while (!done) {
-    // line 1: r0 = b - E~(0) x0 with tolerance tau/3
+    // the initial residual r0 = b - E~(0) x0, applied to tolerance tau/3
     double* v0 = V.get();
     if (x0_zero) {
       IKR_HIP(hipMemcpyAsync(v0, rhs, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1364,7 +1364,7 @@ void solve_response(System& s, const double* b_ext, double* x_ext, const ikr_sol
         x0_zero = false;
         if (stt) stt->sigma_min = sig;
         if (s_est <= sig) { done = true; conv = true; break; }
-        s_est = sig;            // line: restart with s = sigma_i(H_i)
+        s_est = sig;            // restart with s = sigma_i(H_i)
         conv = true;
         break;
       }
