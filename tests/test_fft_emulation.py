@@ -33,7 +33,7 @@ def emu(tmp_path_factory):
     if gxx is None:
         pytest.skip("no host C++ compiler")
     exe = str(tmp_path_factory.mktemp("fftemu") / "fft_emulate")
-    cmd = [gxx, "-std=c++20", "-O1", "-fno-omit-frame-pointer", "-pthread",
+    cmd = [gxx, "-std=c++20", "-O0", "-fno-omit-frame-pointer", "-pthread",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            "-I" + os.path.join(HERE, "host", "hipshim"),
            "-I" + os.path.join(ROOT, "paper_2505_02319_amd", "csrc"), DRIVER, "-o", exe]
