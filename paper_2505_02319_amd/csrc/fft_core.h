@@ -225,10 +225,10 @@ struct Stages {
     // lines only (pair i -> line i % nlines, butterfly i / nlines), so no
     // lane idles on an unlisted line and whole wavefronts drop out past
     // nlines * NB.  i / n is (i * M) >> 31 with M = floor(2^31 / n) + 1:
-    // M n - 2^31 lies in (0, n], so the product overshoots i 2^31 / n by less
-    // than i n, under 2^31 for every i < MAXL * NB (MAXL <= 128, NB <= 64)
-    // and thus never reaches the next multiple of 2^31 / n.  Otherwise:
-    // line i % MAXL, lines past nlines idle.
+    // with e = M n - 2^31 in (0, n], i M / 2^31 = i / n + i e / (n 2^31), and
+    // the added term stays below 1 / n (the least distance from i / n up to
+    // the next integer) while i e < 2^31, true for i < MAXL * NB <= 128 * 64.
+    // Otherwise: line i % MAXL, lines past nlines idle.
     const int tot = PK ? nlines * NB : MAXL * NB;
     unsigned magic = 0;
     if constexpr (PK) magic = 0x80000000u / (unsigned)(nlines > 0 ? nlines : 1) + 1u;
@@ -309,7 +309,7 @@ __device__ __forceinline__ void lds_fft_rows(cplx<R>* buf, int nlines, int lstri
 
 // An inverse transform of all MAXL lines, a pointwise multiply by
 // scale(line, element), and the forward transform, for lengths of one or two
-// stages.  The inverse runs in the order of Rad<N>, the forward one in the
+// stages.  The inverse runs in the order of PairOrd<N>, the forward one in the
 // reverse order: the last inverse stage (radix A, stride NS = N / A) reads
 // and writes elements b + r N/A of a line, and a forward transform that
 // starts with radix A (stride 1) reads exactly those, so the two stages and
